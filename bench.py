@@ -1,0 +1,205 @@
+"""Benchmark of the 3D 7-point Jacobi hot path on one MI355X.
+
+Default workload: 512^3 interior + halo, FP64, two ping-pong arrays plus f,
+u0 ~ U[0,1) (seed 2), f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z), h = 1/513;
+one step = 500 sweeps with the L2 residual fused into every 10th sweep
+(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  Throughput is
+grid-point updates per second (GLUP/s) over the timed steps.
+
+The JSON line also carries
+  roofline:     the dominant kernel (the plain FP64 sweep, 450 of the 500
+                launches of a step), its average duration from HIP events on
+                the stream it runs on, and its algorithmic bandwidth
+                (24 bytes per point update) against the MI355X HBM peak;
+  cpu_baseline: the CPU oracle timed on a bounded sample of the same
+                workload (a few of the 500 sweeps, on all host threads).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLUP/s + % HBM roofline; served solves/s and p50/p99 latency at 1e-8 resid"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP_F64 = 24.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2409_18824_amd", "csrc", "kernels.hip"), "rb") as fp:
+        h.update(fp.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "sweep_fp64_512_counters.json")
+    try:
+        with open(path) as fp:
+            d = json.load(fp)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernels_hip_sha256_16") != kernel_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(n: int, h: float, budget_s: float = 12.0):
+    """Time the oracle on a bounded sample: sweeps of the same 512^3 grid with
+    the same residual cadence (a residual pass before sweep 0 and every 10th)."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    u0, f = synth.uniform_field(n, n, n, 2, synth.STREAM_U0, 0.0, 1.0), synth.manufactured_f(n, n, n, h)
+    a, b = u0, u0.copy()
+    t0 = time.perf_counter()
+    sweeps = 0
+    while True:
+        if sweeps % 10 == 0:
+            oracle.residual_l2(a, f, h)
+        oracle.sweep(a, f, h, out=b)
+        a, b = b, a
+        sweeps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or sweeps >= 20:
+            break
+    glups = sweeps * n ** 3 / el / 1e9
+    del u0, f, a, b
+    return {"value": glups, "unit": "GLUP/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d of the 500 FP64 sweeps of the %d^3 grid (%d residual passes), %.1f s" % (
+                sweeps, n, (sweeps + 9) // 10, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--sweeps", type=int, default=500)
+    ap.add_argument("--resid-every", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    torch.cuda.set_device(0)
+    n, S, E = args.n, args.sweeps, args.resid_every
+    h = 1.0 / (n + 1)
+    print("[bench] allocating %d^3 FP64 (u_a, u_b, f)" % n, file=sys.stderr, flush=True)
+    ua = j3d.FArray.empty(n, n, n)
+    ub = j3d.FArray.empty(n, n, n)
+    j3d.j3d_fill_uniform(ua, 2, synth.STREAM_U0, 0.0, 1.0)
+    j3d.j3d_fill_const(ub, 0.0)
+    df = j3d.FArray.from_numpy(synth.manufactured_f(n, n, n, h))
+    torch.cuda.synchronize()
+    if args.no_tune:
+        tune = None
+    else:
+        tune = j3d.j3d_autotune_single(j3d.F64, n, n, n)
+    print("[bench] tile shape (rows, planes, variant, persistent) = %s" % (tune,), file=sys.stderr, flush=True)
+
+    nres = S // E + 1
+    resid = torch.zeros(nres, dtype=torch.float64, device="cuda")
+    n_plain = sum(1 for s in range(S) if s % E != 0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_plain)]
+
+    state = {"cur": ua, "nxt": ub}
+
+    def step(timed: bool):
+        cur, nxt = state["cur"], state["nxt"]
+        q = 0
+        for s in range(S):
+            if s % E == 0:
+                j3d.jacobi3d_sweep(cur, nxt, df, h, resid_out=resid[s // E:s // E + 1])
+            else:
+                if timed:
+                    ev[q][0].record()
+                j3d.jacobi3d_sweep(cur, nxt, df, h)
+                if timed:
+                    ev[q][1].record()
+                    q += 1
+            cur, nxt = nxt, cur
+        if S % E == 0:
+            j3d.residual_l2(cur, df, h, out=resid[S // E:S // E + 1])
+        state["cur"], state["nxt"] = cur, nxt
+
+    for w in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        print("[bench] warmup %d done" % w, file=sys.stderr, flush=True)
+
+    kernel_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(args.steps):
+        step(True)
+        # event pairs are reused by the next step: read them now (the region
+        # stays stream-ordered; this only waits for the host)
+        ev[-1][1].synchronize()
+        kernel_ms.extend(a.elapsed_time(b) for a, b in ev)
+        print("[bench] step %d done" % k, file=sys.stderr, flush=True)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    elapsed = max(wall, gpu_s)
+    lups = float(n) ** 3 * S * args.steps
+    glups = lups / elapsed / 1e9
+    r = resid.cpu().numpy()
+    assert np.all(np.isfinite(r)) and r[-1] < r[0], "residual did not decrease"
+
+    avg_ms = float(np.mean(kernel_ms))
+    achieved = BYTES_PER_LUP_F64 * n ** 3 / (avg_ms * 1e-3) / 1e9
+    khash = kernel_source_hash()
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash),
+            "kernel": "k_pass_one<double, F_WRITE> (FP64 sweep)", "avg_launch_us": round(avg_ms * 1e3, 2),
+            "launches": len(kernel_ms), "bytes_per_launch_algorithmic": int(BYTES_PER_LUP_F64 * n ** 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(n, h)
+
+    out = {
+        "metric": METRIC, "value": round(glups, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "jacobi3d-7pt-fp64-%dcubed-%dsweeps-resid%d" % (n, S, E),
+                   "grid": [n, n, n], "halo": 1, "layout": "fortran-column-major",
+                   "sweeps_per_step": S, "resid_every": E, "tile": tune,
+                   "hbm_frac_of_step": round(glups * BYTES_PER_LUP_F64 / HBM_PEAK_GBS, 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,344 @@
+/*
+ * j3d.h -- C ABI of libj3d: 3D 7-point Jacobi / Poisson kernels for AMD
+ * Instinct MI355X (gfx950), with Fortran array semantics.
+ *
+ * The computation is the Fortran loop nest that the paper's jacobi
+ * benchmark runs (Sec. "Flang performance comparison"), taken to three
+ * dimensions as a Poisson problem -Lap(u) = f on a grid with spacing h:
+ *
+ *   sweep:     u'(i,j,k) = (u(i-1,j,k) + u(i+1,j,k) + u(i,j-1,k) + u(i,j+1,k)
+ *                           + u(i,j,k-1) + u(i,j,k+1) + h^2 f(i,j,k)) / 6
+ *   residual:  r(i,j,k)  = f(i,j,k) - (6 u(i,j,k) - [same six-neighbour sum]) / h^2
+ *   norm:      ||r||_2   = sqrt(sum of r^2 over the interior)
+ *
+ * The norm is a sum reduction initialised at zero, the pattern the paper
+ * lowers Fortran's sum/dot_product intrinsics to (Sec. "Handling of other
+ * constructs", Listing 8).  Sums of neighbours are formed in the order
+ * x-, x+, y-, y+, z-, z+ and no multiply-add is contracted, so results are
+ * reproducible bit for bit.
+ *
+ * ARRAYS.  Every field is a Fortran array with explicit bounds, described by
+ * a j3d_array in the manner of an MLIR memref (base, sizes, strides; Sec.
+ * "Handling of memory"): element (i,j,k) lives at
+ *     base + (i-lbound[0])*stride[0] + (j-lbound[1])*stride[1] + (k-lbound[2])*stride[2]
+ * elements, which is Fortran's lower-bound subtraction.  The outermost
+ * layer on every side is a one-cell halo holding Dirichlet boundary values;
+ * the interior is lbound+1 .. ubound-1 on each axis and must be at least one
+ * cell wide.  x is the unit-stride (column-major) axis.  Strided subviews
+ * are accepted as they are, without a copy.  Kernels read the halo of their
+ * input and never write any halo.
+ *
+ * INTENT.  Arguments marked const are intent(in); outputs are intent(out).
+ * Scalars are passed by value.  Inputs and outputs of one call must not
+ * overlap in memory (Fortran's rule for modified dummy arguments; an
+ * in-place Jacobi sweep would turn into an order-dependent Gauss-Seidel
+ * sweep): overlap is rejected with J3D_EALIAS.
+ *
+ * OWNERSHIP.  Array memory belongs to the caller: the library never
+ * allocates, reallocates or frees it.  It must stay valid until the stream
+ * has passed the call.  Scratch memory (per-tile partial sums, flags,
+ * solver work arrays, captured graphs) belongs to the library, is cached per
+ * device and stream, and is released by j3d_release_cache().
+ *
+ * STREAMS.  `stream` is a hipStream_t passed as void* (NULL: the null
+ * stream).  Calls are asynchronous and stream-ordered unless stated.
+ *
+ * ERRORS.  Every call returns J3D_OK (0) or a negative J3D_E* code; no
+ * exception crosses the ABI.  j3d_last_error() returns a message for the
+ * last failure on the calling thread.  Argument checks happen before any
+ * device work is queued: a call that fails validation has no effect.
+ * Device faults of asynchronous work surface as J3D_EHIP at a later
+ * synchronising call.
+ */
+#ifndef J3D_H
+#define J3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define J3D_ABI_VERSION 1
+
+/* dtype codes */
+#define J3D_F64 0
+#define J3D_F32 1
+
+/* status codes */
+#define J3D_OK 0
+#define J3D_EINVAL (-1)     /* null pointer, bad bounds/strides, n < 1, h <= 0 or not finite */
+#define J3D_EDTYPE (-2)     /* wrong element type for the argument */
+#define J3D_EALIAS (-3)     /* inputs and outputs overlap */
+#define J3D_ENOMEM (-4)     /* library scratch allocation failed */
+#define J3D_EBUDGET (-5)    /* a served request can never fit the memory budget */
+#define J3D_EHIP (-6)       /* HIP runtime error (message in j3d_last_error) */
+#define J3D_ENONFINITE (-7) /* residual is NaN or Inf */
+#define J3D_EAGAIN (-8)     /* serve queue full; try again later */
+#define J3D_ESTATE (-9)     /* call not valid in the object's current state */
+
+/* flags for jacobi3d_sweep */
+#define J3D_HOST_RESULT 1u  /* resid_out is a host pointer; the call waits for the stream */
+
+/*
+ * A Fortran array u(lbound[0]:ubound[0], lbound[1]:ubound[1], lbound[2]:ubound[2]).
+ * base points at element (lbound[0], lbound[1], lbound[2]) in device memory.
+ * Bounds are inclusive and include the one-cell halo.  Strides are in
+ * elements: stride[0] must be 1, stride[1] >= extent[0], stride[2] >=
+ * stride[1]*extent[1], where extent[d] = ubound[d]-lbound[d]+1 >= 3.  The
+ * largest element offset must be below 2^31.
+ */
+typedef struct j3d_array {
+  void* base;
+  int32_t dtype;      /* J3D_F64 or J3D_F32 */
+  int32_t reserved;   /* must be 0 */
+  int64_t lbound[3];
+  int64_t ubound[3];
+  int64_t stride[3];
+} j3d_array;
+
+/* Library version (J3D_ABI_VERSION) and the last error text of this thread. */
+int j3d_abi_version(void);
+const char* j3d_last_error(void);
+
+/*
+ * Host-only: the element offset of Fortran index (i,j,k) in `a`, computed by
+ * lower-bound subtraction (Sec. "Handling of memory", Listings 6-7).  Returns
+ * J3D_EINVAL if `a` is not a valid descriptor or (i,j,k) lies outside its
+ * bounds.  Touches no device.
+ */
+int j3d_element_offset(const j3d_array* a, int64_t i, int64_t j, int64_t k, int64_t* offset);
+
+/*
+ * Host-only: validate a descriptor for use as a field of the given dtype.
+ * Returns J3D_OK, J3D_EINVAL or J3D_EDTYPE.  Touches no device.
+ */
+int j3d_check_array(const j3d_array* a, int32_t dtype);
+
+/*
+ * One Jacobi sweep u_out = J(u_in; f, h) over the interior (the update
+ * formula above).  All three arrays have the same dtype (FP64 or FP32) and
+ * the same interior extents; each may have its own bounds and strides.
+ * u_out's halo is not written (give both ping-pong arrays the same halo).
+ * If resid_out is not NULL, the L2 norm of the residual of u_in,
+ * ||f - A u_in||_2, is computed in FP64 in the same pass (from the values
+ * the sweep loads, so it costs no extra memory traffic) and stored to
+ * *resid_out: a device address, or a host address with J3D_HOST_RESULT
+ * (then the call synchronises the stream).  The fused residual needs FP64
+ * arrays (J3D_EDTYPE otherwise).  FP32 sweeps use h^2 = (float)(h*h).
+ */
+int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
+                   double h, uint32_t flags, double* resid_out, void* stream);
+
+/*
+ * ||f - A u||_2 over the interior, in FP64 (u and f FP64).  `out` is a
+ * device address (or host, with J3D_HOST_RESULT in flags).
+ */
+int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags,
+                double* out, void* stream);
+
+/* Solver modes */
+#define J3D_MODE_FP64 0  /* FP64 Jacobi sweeps */
+#define J3D_MODE_MIXED 1 /* FP32 correction sweeps with FP64 defect correction */
+
+typedef struct j3d_solve_opts {
+  int32_t mode;          /* J3D_MODE_FP64 or J3D_MODE_MIXED */
+  int32_t check_every;   /* FP64 mode: sweeps between residual checks (>= 1) */
+  int32_t inner_sweeps;  /* MIXED mode: FP32 sweeps per defect step (>= 1) */
+  int32_t reserved;      /* must be 0 */
+  int64_t max_sweeps;    /* sweep cap (>= 0); MIXED counts FP32 sweeps */
+  double rtol;           /* stop at the first check with ||r||_2 <= rtol * ||f||_2 */
+  double* history;       /* host array for ||r||_2 at every check, in order (nullable) */
+  int64_t history_cap;   /* capacity of history */
+} j3d_solve_opts;
+
+typedef struct j3d_solve_result {
+  int64_t sweeps;        /* sweeps performed up to the returned iterate */
+  double resid;          /* ||f - A u||_2 of the returned u (FP64) */
+  double resid0;         /* ||f - A u0||_2 of the initial guess */
+  double norm_f;         /* ||f||_2 */
+  int32_t converged;     /* 1 if resid <= rtol * norm_f */
+  int32_t status;        /* J3D_OK or J3D_ENONFINITE */
+  int64_t history_len;   /* entries written to opts->history */
+} j3d_solve_result;
+
+/*
+ * Solve A u = f by Jacobi iteration from the initial guess in u; the result
+ * overwrites u's interior (u, f FP64; halo of u = Dirichlet data).
+ *
+ * FP64 mode: the residual of the iterate after sweep s is checked at
+ * s = 0, c, 2c, ... (c = check_every), fused into sweep s+1; the solve stops
+ * at the first check with ||r|| <= rtol*||f|| or after max_sweeps sweeps.
+ * This is an early-exit loop (cf. the paper's lowering of iterate_while,
+ * Sec. "Handling of control structures"); the test runs on the device.
+ *
+ * MIXED mode (defect correction): each cycle does an FP64 defect step
+ * (u += e from the previous cycle, r = f - A u, ||r||, convergence test)
+ * then min(inner_sweeps, sweeps left) FP32 Jacobi sweeps on A e = (float) r
+ * from e = 0 with h^2 = (float)(h*h).  The last cycle ends with a defect
+ * step, so u includes every correction and `resid` is its residual.
+ *
+ * Not converging is not an error (converged = 0).  A NaN/Inf residual stops
+ * the solve with status and return value J3D_ENONFINITE.  The call blocks
+ * until the solve has finished.  Work arrays (one FP64 array in FP64 mode,
+ * three FP32 arrays in MIXED mode) are allocated by the library and cached.
+ */
+int poisson_solve(const j3d_array* u, const j3d_array* f, double h,
+                  const j3d_solve_opts* opts, j3d_solve_result* result, void* stream);
+
+/* One grid of a batch: two ping-pong arrays with equal halos, and f (all FP64). */
+typedef struct j3d_grid {
+  j3d_array u_a;   /* initial iterate; holds the result if nsweeps is even */
+  j3d_array u_b;   /* second buffer; holds the result if nsweeps is odd */
+  j3d_array f;
+  double h;
+} j3d_grid;
+
+/*
+ * Tile shape of the sweep kernels.  A workgroup sweeps 64 x-points (one
+ * 64-lane wavefront per row) x `rows` y-rows x `planes` z-planes, marching
+ * through z with the previous, current and next plane in registers.
+ * variant 0 reads x/y neighbours through the cache, variant 1 stages each
+ * plane in LDS.  persistent = 1 launches a fixed grid of workgroups that
+ * stride over the tile list; 0 launches one workgroup per tile.
+ * The supported combinations are listed by j3d_tune_list().
+ */
+typedef struct j3d_tune {
+  int32_t rows;
+  int32_t planes;
+  int32_t variant;
+  int32_t persistent;
+} j3d_tune;
+
+/* Number of supported tile shapes, and the i-th one (host-only). */
+int j3d_tune_count(void);
+int j3d_tune_get(int32_t index, j3d_tune* out);
+
+/*
+ * Sweep `ngrids` independent grids of uneven sizes `nsweeps` times each,
+ * all grids in one kernel per sweep over a packed tile list, the sweeps
+ * captured in one HIP graph (cached per argument set and stream, replayed on
+ * later identical calls).  The result of grid g lands in u_a if nsweeps is
+ * even, else in u_b.  If resid_out is not NULL it is a device array of
+ * ngrids * (nsweeps/resid_every + 1) doubles: row g holds ||f - A u||_2 of
+ * grid g after sweeps 0, e, 2e, ... (e = resid_every), fused into the
+ * following sweep where there is one.  Each grid's numbers equal those of
+ * the same grid swept alone with the same tile shape, bit for bit.
+ * tune = NULL selects the tile shape with the autotuner (timed once per
+ * batch shape class and cached; J3D_TUNE_CACHE names an optional file).
+ */
+int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
+                         int32_t resid_every, double* resid_out, const j3d_tune* tune,
+                         void* stream);
+
+/* Autotune: time each supported tile shape on these grids (one sweep each,
+ * after a warm-up) and write the fastest to *best.  Writes to u_b only.
+ * Blocks until done. */
+int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* stream);
+
+/* Autotune the single-grid sweep of this element type and interior shape on
+ * library-allocated scratch arrays; the choice is used by jacobi3d_sweep,
+ * residual_l2 and poisson_solve for this shape from then on.  Blocks. */
+int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
+                        void* stream);
+
+/* Pin the tile shape used for single-grid calls on this dtype and shape. */
+int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of Poisson solves under a memory budget */
+/* ------------------------------------------------------------------ */
+
+typedef struct j3d_server j3d_server;
+
+typedef struct j3d_serve_opts {
+  uint64_t hbm_budget_bytes;  /* device memory the server may hold for request state */
+  int32_t max_slots;          /* maximum concurrently active requests */
+  int32_t cycle_sweeps;       /* FP32 sweeps per defect-correction cycle (e.g. 50) */
+  int32_t device;             /* HIP device ordinal */
+  int32_t queue_cap;          /* maximum queued (not yet admitted) requests */
+} j3d_serve_opts;
+
+typedef struct j3d_request {
+  int32_t nx, ny, nz;         /* interior extents (>= 1) */
+  int32_t reserved;           /* must be 0 */
+  double h;                   /* grid spacing (> 0) */
+  const double* f_host;       /* padded right-hand side, (nz+2)(ny+2)(nx+2) doubles
+                                 with x fastest; NULL: draw f ~ U[-1,1) from `seed` */
+  uint64_t seed;              /* used when f_host is NULL */
+  double rtol;                /* target ||r||_2 / ||f||_2 */
+  int64_t max_sweeps;         /* FP32 sweep cap */
+  double* u_host;             /* nullable: receives the padded solution when done */
+} j3d_request;
+
+typedef struct j3d_result {
+  uint64_t ticket;
+  int32_t status;             /* J3D_OK or J3D_ENONFINITE */
+  int32_t converged;
+  int64_t sweeps;
+  double resid;               /* FP64 ||r||_2 of the returned solution */
+  double norm_f;
+  double t_submit, t_admit, t_done;  /* seconds on the server's monotonic clock */
+} j3d_result;
+
+/* Bytes of device state one request of this size holds while active. */
+uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz);
+
+/*
+ * Create a server with its own worker thread and HIP stream on opts->device.
+ * Requests are admitted in arrival order while their state fits the budget
+ * and a slot is free; every active request is a slot in one batched
+ * mixed-precision cycle (FP64 defect step + cycle_sweeps FP32 sweeps over
+ * all slots' tiles).  At every cycle boundary converged or capped requests
+ * retire and waiting ones are admitted (continuous batching).  A request's
+ * result does not depend on which others share its cycles.
+ */
+int poisson_serve_create(const j3d_serve_opts* opts, j3d_server** out);
+/* Queue a request.  J3D_EBUDGET if it can never fit; J3D_EAGAIN if the queue
+ * is full.  f_host is copied before the call returns; u_host must stay valid
+ * until the ticket's result has been polled. */
+int poisson_serve_submit(j3d_server* s, const j3d_request* req, uint64_t* ticket);
+/* Move up to cap finished results into out[0..*n). Non-blocking. */
+int poisson_serve_poll(j3d_server* s, j3d_result* out, int32_t cap, int32_t* n);
+/* Block until every submitted request has finished (or timeout_s elapses;
+ * returns J3D_EAGAIN on timeout).  timeout_s <= 0 waits forever. */
+int poisson_serve_drain(j3d_server* s, double timeout_s);
+/* Current server clock (seconds) and counters: active, queued, finished. */
+int poisson_serve_stats(j3d_server* s, double* now, int32_t* active, int32_t* queued,
+                        int64_t* finished);
+/* Stop the worker (after finishing the cycle in flight) and free all state. */
+int poisson_serve_destroy(j3d_server* s);
+
+/* ------------------------------------------------------------------ */
+/* Utilities                                                           */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Fill the interior of an FP64 array with U[lo,hi) draws, counter-based:
+ * point (i,j,k) takes counter (i-1) + nx*((j-1) + ny*(k-1)) of SplitMix64
+ * (Steele, Lea, Flood 2014) seeded with seed XOR (stream_id << 40); value
+ * lo + (hi-lo) * ((bits >> 11) * 2^-53).  The halo is set to `halo`.
+ */
+int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, double lo,
+                     double hi, double halo, void* stream);
+
+/* Set every element (halo included) of an FP64 or FP32 array to `value`. */
+int j3d_fill_const(const j3d_array* a, double value, void* stream);
+
+/*
+ * Streaming probe for the achievable memory bandwidth: copies n doubles from
+ * src to dst (device) `reps` times and returns the best rate in GB/s
+ * (bytes read + written per second).  Blocks.
+ */
+int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps,
+                        double* gbps, void* stream);
+
+/* Free every cached scratch buffer and graph of the calling process. */
+int j3d_release_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* J3D_H */

@@ -48,6 +48,8 @@ def lib():
         I = ctypes.c_int64
         D = ctypes.c_double
         F = ctypes.c_float
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = ctypes.c_int
         L.oracle_sweep_f64.argtypes = [P, P, P, I, I, I, I, I, D]
         L.oracle_sweep_f64.restype = None
         L.oracle_residual_field_f64.argtypes = [P, P, P, I, I, I, I, I, D]
@@ -66,6 +68,10 @@ def lib():
         L.oracle_solve_mixed.restype = None
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    return int(lib().oracle_threads())
 
 
 def _geom(a: np.ndarray, dtype):

@@ -37,6 +37,9 @@
  * a[i + sy*j + sz*k] with unit stride in x.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -44,6 +47,15 @@
 typedef int64_t idx_t;
 
 #define AT(i, j, k) ((i) + sy * (j) + sz * (k))
+
+/* Number of threads the loops below run on. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Compensated summation                                               */

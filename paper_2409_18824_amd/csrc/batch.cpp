@@ -1,0 +1,519 @@
+// Batched sweeps over uneven grids, captured in one HIP graph, and the tile
+// shape autotuner.
+//
+// A batch is flattened into one tile list: grid g owns tiles
+// [tile0[g], tile0[g] + tiles(g)) and its launch descriptor sits in a table in
+// device memory (one structure of arrays per grid, as the paper keeps one
+// memref per member of a derived type, Sec. "Handling of other
+// constructs").  One kernel per sweep walks the whole list; the sweeps of a
+// call are captured once into a graph and replayed.  Tile shapes are
+// compile-time template parameters picked by the autotuner, the analogue of
+// the paper's static-shape specialisation (Sec. "Performance").
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+namespace j3d {
+TileCfg default_cfg(int dtype, int nx, int ny, int nz);
+
+namespace {
+
+// ---------------------------------------------------------------------
+// Tune cache
+// ---------------------------------------------------------------------
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+std::map<std::string, TileCfg> g_tune;
+
+std::string single_key(int dtype, int nx, int ny, int nz) {
+  char b[96];
+  snprintf(b, sizeof b, "single:%d:%d:%d:%d", dtype, nx, ny, nz);
+  return b;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string batch_key(int ngrids, const Field* ua) {
+  uint64_t h = 1469598103934665603ull;
+  for (int g = 0; g < ngrids; ++g) {
+    int e[3] = {ua[g].nx(), ua[g].ny(), ua[g].nz()};
+    h = fnv1a(e, sizeof e, h);
+  }
+  char b[64];
+  snprintf(b, sizeof b, "batch:%d:%016llx", ngrids, (unsigned long long)h);
+  return b;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("J3D_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = fopen(path, "r");
+  if (!fp) return;
+  char key[128];
+  TileCfg c;
+  while (fscanf(fp, "%127s %d %d %d %d", key, &c.rows, &c.planes, &c.variant, &c.persistent) == 5)
+    if (tile_cfg_supported(c)) g_tune[key] = c;
+  fclose(fp);
+}
+
+void tune_store(const std::string& key, const TileCfg& c) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = c;
+  const char* path = getenv("J3D_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = fopen(path, "w");
+  if (!fp) return;
+  for (auto& kv : g_tune)
+    fprintf(fp, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.rows, kv.second.planes,
+            kv.second.variant, kv.second.persistent);
+  fclose(fp);
+}
+
+bool tune_lookup(const std::string& key, TileCfg* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// ---------------------------------------------------------------------
+// Batch validation and tables
+// ---------------------------------------------------------------------
+struct BatchFields {
+  std::vector<Field> a, b, f;
+  std::vector<double> h;
+};
+
+int check_batch(int ngrids, const j3d_grid* grids, BatchFields* bf) {
+  if (ngrids < 1) return fail(J3D_EINVAL, "ngrids must be >= 1");
+  if (grids == nullptr) return fail(J3D_EINVAL, "grids: null pointer");
+  bf->a.resize(ngrids);
+  bf->b.resize(ngrids);
+  bf->f.resize(ngrids);
+  bf->h.resize(ngrids);
+  struct Iv {
+    const char* lo;
+    const char* hi;
+    int grid;
+    bool written;
+  };
+  std::vector<Iv> iv;
+  iv.reserve(3 * (size_t)ngrids);
+  for (int g = 0; g < ngrids; ++g) {
+    char nm[3][32];
+    snprintf(nm[0], 32, "grids[%d].u_a", g);
+    snprintf(nm[1], 32, "grids[%d].u_b", g);
+    snprintf(nm[2], 32, "grids[%d].f", g);
+    J3D_TRY(check_field(&grids[g].u_a, J3D_F64, &bf->a[g], nm[0]));
+    J3D_TRY(check_field(&grids[g].u_b, J3D_F64, &bf->b[g], nm[1]));
+    J3D_TRY(check_field(&grids[g].f, J3D_F64, &bf->f[g], nm[2]));
+    J3D_TRY(check_same_interior(bf->a[g], bf->b[g], nm[0], nm[1]));
+    J3D_TRY(check_same_interior(bf->a[g], bf->f[g], nm[0], nm[2]));
+    J3D_TRY(check_h(grids[g].h));
+    bf->h[g] = grids[g].h;
+    const Field* fs[3] = {&bf->a[g], &bf->b[g], &bf->f[g]};
+    for (int r = 0; r < 3; ++r)
+      iv.push_back({fs[r]->base, fs[r]->base + fs[r]->span_bytes(), g, r < 2});
+  }
+  // Sweep in address order: a written array may overlap nothing, a read-only
+  // array (f) may overlap only other read-only arrays.
+  std::sort(iv.begin(), iv.end(), [](const Iv& x, const Iv& y) { return x.lo < y.lo; });
+  const char* hi_all = nullptr;
+  const char* hi_written = nullptr;
+  for (const Iv& v : iv) {
+    if ((v.written && hi_all && v.lo < hi_all) || (hi_written && v.lo < hi_written))
+      return fail(J3D_EALIAS, "an array of grid %d overlaps another array of the batch", v.grid);
+    if (!hi_all || v.hi > hi_all) hi_all = v.hi;
+    if (v.written && (!hi_written || v.hi > hi_written)) hi_written = v.hi;
+  }
+  return J3D_OK;
+}
+
+// tab[0]: u_a -> u_b (+residual of u_a); tab[1]: u_b -> u_a; tab[2]/[3]:
+// residual-only of u_a / u_b.
+void build_tables(const BatchFields& bf, const TileCfg& c, std::vector<GridArgs> tab[4], int* ntiles) {
+  const int n = (int)bf.a.size();
+  for (int t = 0; t < 4; ++t) tab[t].resize(n);
+  int tile0 = 0;
+  for (int g = 0; g < n; ++g) {
+    tab[0][g] = make_args(&bf.a[g], &bf.b[g], &bf.f[g], nullptr, nullptr, bf.h[g], c, tile0);
+    tab[1][g] = make_args(&bf.b[g], &bf.a[g], &bf.f[g], nullptr, nullptr, bf.h[g], c, tile0);
+    tab[2][g] = make_args(&bf.a[g], nullptr, &bf.f[g], nullptr, nullptr, bf.h[g], c, tile0);
+    tab[3][g] = make_args(&bf.b[g], nullptr, &bf.f[g], nullptr, nullptr, bf.h[g], c, tile0);
+    for (int t = 0; t < 4; ++t) tab[t][g].id = g;
+    tile0 += tab[0][g].tiles_x * tab[0][g].tiles_y * tab[0][g].tiles_z;
+  }
+  *ntiles = tile0;
+}
+
+// ---------------------------------------------------------------------
+// Plans (device tables + captured graph), cached per call signature
+// ---------------------------------------------------------------------
+struct Plan {
+  std::string key;
+  int device = 0;
+  int ngrids = 0, ntiles = 0;
+  GridArgs* tab = nullptr;  // device, 4 * ngrids
+  double* partials = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t stamp = 0;
+};
+
+std::mutex g_plan_mu;
+std::vector<Plan*> g_plans;
+uint64_t g_stamp = 0;
+constexpr size_t kMaxPlans = 16;
+hipStream_t g_cap_stream[64] = {};
+
+void free_plan(Plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->tab) (void)hipFree(p->tab);
+  if (p->partials) (void)hipFree(p->partials);
+  delete p;
+}
+
+int capture_stream(int dev, hipStream_t* out) {
+  if (dev < 0 || dev >= 64) return fail(J3D_EINVAL, "device ordinal out of range");
+  if (!g_cap_stream[dev]) J3D_HIP(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking));
+  *out = g_cap_stream[dev];
+  return J3D_OK;
+}
+
+// Enqueue the whole batch on `st` (used for capture).
+int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, double* resid_out,
+                  hipStream_t st) {
+  const GridArgs* tab = p.tab;
+  const int n = p.ngrids;
+  const int nres = resid_out ? nsweeps / every + 1 : 0;
+  for (int s = 0; s < nsweeps; ++s) {
+    const bool check = resid_out && (s % every) == 0;
+    const GridArgs* t = tab + (size_t)(s & 1) * n;
+    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), c, t, n, p.ntiles, p.partials,
+                              nullptr, st));
+    if (check)
+      J3D_HIP(launch_reduce_batch(p.partials, t, n, resid_out, nres, s / every, nullptr, nullptr, 0,
+                                  nullptr, nullptr, nullptr, st));
+  }
+  if (resid_out && nsweeps % every == 0) {
+    const GridArgs* t = tab + (size_t)(2 + (nsweeps & 1)) * n;
+    J3D_HIP(launch_pass_batch(J3D_F64, F_RES, c, t, n, p.ntiles, p.partials, nullptr, st));
+    J3D_HIP(launch_reduce_batch(p.partials, t, n, resid_out, nres, nsweeps / every, nullptr, nullptr,
+                                0, nullptr, nullptr, nullptr, st));
+  }
+  return J3D_OK;
+}
+
+int make_plan(const std::string& key, const BatchFields& bf, const TileCfg& c, int nsweeps, int every,
+              double* resid_out, Plan** out) {
+  int dev = 0;
+  J3D_HIP(hipGetDevice(&dev));
+  Plan* p = new Plan();
+  p->key = key;
+  p->device = dev;
+  p->ngrids = (int)bf.a.size();
+  std::vector<GridArgs> tab[4];
+  build_tables(bf, c, tab, &p->ntiles);
+  std::vector<GridArgs> flat;
+  for (int t = 0; t < 4; ++t) flat.insert(flat.end(), tab[t].begin(), tab[t].end());
+  void* mem = nullptr;
+  int rc = dev_alloc(&mem, flat.size() * sizeof(GridArgs), "batch table");
+  if (rc == J3D_OK) {
+    p->tab = static_cast<GridArgs*>(mem);
+    rc = dev_alloc(&mem, (size_t)p->ntiles * sizeof(double), "batch partials");
+  }
+  if (rc == J3D_OK) p->partials = static_cast<double*>(mem);
+  if (rc != J3D_OK) {
+    free_plan(p);
+    return rc;
+  }
+  hipError_t e = hipMemcpy(p->tab, flat.data(), flat.size() * sizeof(GridArgs), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "upload batch table");
+  }
+  hipStream_t cs;
+  rc = capture_stream(dev, &cs);
+  if (rc != J3D_OK) {
+    free_plan(p);
+    return rc;
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  rc = enqueue_batch(*p, c, nsweeps, every, resid_out, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (rc != J3D_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    free_plan(p);
+    return rc != J3D_OK ? rc : hip_fail(e, "hipStreamEndCapture");
+  }
+  p->graph = graph;
+  e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  *out = p;
+  return J3D_OK;
+}
+
+// ---------------------------------------------------------------------
+// Autotuning
+// ---------------------------------------------------------------------
+std::vector<TileCfg> candidates() {
+  std::vector<TileCfg> v;
+  const int n = j3d_tune_count();
+  for (int i = 0; i < n; ++i) {
+    j3d_tune t;
+    j3d_tune_get(i, &t);
+    v.push_back(TileCfg{t.rows, t.planes, t.variant, t.persistent});
+  }
+  return v;
+}
+
+// Time F_WRITE passes for every candidate on the given single-grid or batch
+// arguments and return the fastest.  `fill` builds the launch for a cfg.
+template <typename BuildAndLaunch>
+int time_candidates(hipStream_t st, TileCfg* best, BuildAndLaunch&& launch) {
+  hipEvent_t e0, e1;
+  J3D_HIP(hipEventCreate(&e0));
+  J3D_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int rc = J3D_OK;
+  for (const TileCfg& c : candidates()) {
+    rc = launch(c);  // warm-up (also builds tables)
+    if (rc != J3D_OK) break;
+    float ms_min = 1e30f;
+    for (int r = 0; r < 3 && rc == J3D_OK; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(J3D_EHIP, "event record"); break; }
+      rc = launch(c);
+      if (rc != J3D_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(J3D_EHIP, "event sync");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (rc != J3D_OK) break;
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      *best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // namespace
+
+bool tune_cache_lookup_single(int dtype, int nx, int ny, int nz, TileCfg* out) {
+  return tune_lookup(single_key(dtype, nx, ny, nz), out);
+}
+
+void release_batch_cache() {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (Plan* p : g_plans) {
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    free_plan(p);
+  }
+  g_plans.clear();
+}
+
+// Tunes the batched sweep for the batch's shape class (used by serve.cpp too).
+int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st);
+
+int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st) {
+  const int n = (int)bf.a.size();
+  GridArgs* dtab = nullptr;
+  double* parts = nullptr;
+  size_t tab_cap = 0, part_cap = 0;
+  auto launch = [&](const TileCfg& c) -> int {
+    std::vector<GridArgs> tab[4];
+    int nt = 0;
+    build_tables(bf, c, tab, &nt);
+    if ((size_t)n > tab_cap) {
+      if (dtab) (void)hipFree(dtab);
+      void* m = nullptr;
+      J3D_TRY(dev_alloc(&m, (size_t)n * sizeof(GridArgs), "tune table"));
+      dtab = static_cast<GridArgs*>(m);
+      tab_cap = n;
+    }
+    if ((size_t)nt > part_cap) {
+      if (parts) (void)hipFree(parts);
+      void* m = nullptr;
+      J3D_TRY(dev_alloc(&m, (size_t)nt * sizeof(double), "tune partials"));
+      parts = static_cast<double*>(m);
+      part_cap = nt;
+    }
+    J3D_HIP(hipMemcpyAsync(dtab, tab[0].data(), (size_t)n * sizeof(GridArgs), hipMemcpyHostToDevice, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, c, dtab, n, nt, parts, nullptr, st));
+    return J3D_OK;
+  };
+  int rc = time_candidates(st, best, launch);
+  (void)hipStreamSynchronize(st);
+  if (dtab) (void)hipFree(dtab);
+  if (parts) (void)hipFree(parts);
+  return rc;
+}
+
+}  // namespace j3d
+
+using namespace j3d;
+
+extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
+                                    int32_t resid_every, double* resid_out, const j3d_tune* tune,
+                                    void* stream) {
+  BatchFields bf;
+  J3D_TRY(check_batch(ngrids, grids, &bf));
+  if (nsweeps < 0) return fail(J3D_EINVAL, "nsweeps must be >= 0");
+  if (resid_out != nullptr && resid_every < 1) return fail(J3D_EINVAL, "resid_every must be >= 1");
+  if (nsweeps > (1 << 20)) return fail(J3D_EINVAL, "nsweeps too large for one graph");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TileCfg c;
+  if (tune != nullptr) {
+    c = TileCfg{tune->rows, tune->planes, tune->variant, tune->persistent};
+    if (!tile_cfg_supported(c)) return fail(J3D_EINVAL, "unsupported tile shape");
+  } else {
+    const std::string bk = batch_key(ngrids, bf.a.data());
+    if (!tune_lookup(bk, &c)) {
+      J3D_TRY(autotune_batch_fields(bf, &c, st));
+      tune_store(bk, c);
+    }
+  }
+  if (nsweeps == 0 && resid_out == nullptr) return J3D_OK;
+  // Plan key: every descriptor, h, counts, output and tile shape.
+  std::string key;
+  key.append(reinterpret_cast<const char*>(grids), sizeof(j3d_grid) * (size_t)ngrids);
+  int dev = 0;
+  J3D_HIP(hipGetDevice(&dev));
+  const long long meta[8] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
+                             c.rows * 1000000LL + c.planes * 100 + c.variant * 10 + c.persistent,
+                             dev, 0, 0};
+  key.append(reinterpret_cast<const char*>(meta), sizeof meta);
+  Plan* plan = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (Plan* p : g_plans)
+      if (p->key == key) {
+        plan = p;
+        break;
+      }
+    if (plan == nullptr) {
+      J3D_TRY(make_plan(key, bf, c, nsweeps, resid_every, resid_out, &plan));
+      if (g_plans.size() >= kMaxPlans) {
+        auto it = std::min_element(g_plans.begin(), g_plans.end(),
+                                   [](Plan* x, Plan* y) { return x->stamp < y->stamp; });
+        (void)hipDeviceSynchronize();
+        free_plan(*it);
+        g_plans.erase(it);
+      }
+      g_plans.push_back(plan);
+    }
+    plan->stamp = ++g_stamp;
+  }
+  J3D_HIP(hipGraphLaunch(plan->exec, st));
+  return J3D_OK;
+}
+
+extern "C" int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* stream) {
+  BatchFields bf;
+  J3D_TRY(check_batch(ngrids, grids, &bf));
+  if (best == nullptr) return fail(J3D_EINVAL, "best: null pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TileCfg c{};
+  J3D_TRY(autotune_batch_fields(bf, &c, st));
+  tune_store(batch_key(ngrids, bf.a.data()), c);
+  if (ngrids == 1) tune_store(single_key(J3D_F64, bf.a[0].nx(), bf.a[0].ny(), bf.a[0].nz()), c);
+  best->rows = c.rows;
+  best->planes = c.planes;
+  best->variant = c.variant;
+  best->persistent = c.persistent;
+  return J3D_OK;
+}
+
+extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
+                                   void* stream) {
+  if (dtype != J3D_F64 && dtype != J3D_F32) return fail(J3D_EDTYPE, "dtype must be F64 or F32");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(J3D_EINVAL, "extents must be >= 1");
+  if (best == nullptr) return fail(J3D_EINVAL, "best: null pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int es = dtype == J3D_F64 ? 8 : 4;
+  const int align = 128 / es;
+  Field a;
+  a.dtype = dtype;
+  a.esize = es;
+  a.ex = nx + 2;
+  a.ey = ny + 2;
+  a.ez = nz + 2;
+  a.sy = ((long long)a.ex + align - 1) / align * align;
+  a.sz = a.sy * a.ey;
+  if (a.sz * a.ez >= (1LL << 31) - align) return fail(J3D_EINVAL, "grid too large");
+  const size_t bytes = ((size_t)(a.sz * a.ez + align) * es + 255) / 256 * 256;
+  void* mem = nullptr;
+  J3D_TRY(dev_alloc(&mem, 3 * bytes, "autotune arrays"));
+  char* m = static_cast<char*>(mem);
+  hipError_t e = hipMemsetAsync(m, 0, 3 * bytes, st);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return hip_fail(e, "autotune memset");
+  }
+  Field u = a, o = a, f = a;
+  u.base = m + (align - 1) * es;
+  o.base = m + bytes + (align - 1) * es;
+  f.base = m + 2 * bytes + (align - 1) * es;
+  auto launch = [&](const TileCfg& c) -> int {
+    GridArgs g = make_args(&u, &o, &f, nullptr, nullptr, 0.01, c, 0);
+    J3D_HIP(launch_pass_one(dtype, F_WRITE, c, g, nullptr, nullptr, st));
+    return J3D_OK;
+  };
+  TileCfg c{};
+  int rc = time_candidates(st, &c, launch);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(mem);
+  if (rc != J3D_OK) return rc;
+  tune_store(single_key(dtype, nx, ny, nz), c);
+  best->rows = c.rows;
+  best->planes = c.planes;
+  best->variant = c.variant;
+  best->persistent = c.persistent;
+  return J3D_OK;
+}
+
+extern "C" int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t) {
+  if (t == nullptr) return fail(J3D_EINVAL, "tune: null pointer");
+  TileCfg c{t->rows, t->planes, t->variant, t->persistent};
+  if (!tile_cfg_supported(c)) return fail(J3D_EINVAL, "unsupported tile shape");
+  if (dtype != J3D_F64 && dtype != J3D_F32) return fail(J3D_EDTYPE, "dtype must be F64 or F32");
+  tune_store(single_key(dtype, nx, ny, nz), c);
+  return J3D_OK;
+}

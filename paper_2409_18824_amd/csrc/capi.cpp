@@ -1,0 +1,211 @@
+// C-ABI entry points of libj3d: single sweeps, residual norms, fills,
+// bandwidth probe and housekeeping.  Solves, batches and serving live in
+// solve.cpp, batch.cpp and serve.cpp.
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace j3d {
+const char* last_error_text();
+int release_all_scratch();
+bool tune_cache_lookup_single(int dtype, int nx, int ny, int nz, TileCfg* out);
+
+namespace {
+const int kRows[] = {1, 2, 4, 8};
+const int kPlanes[] = {8, 16, 32, 64, 128};
+constexpr int kNumTunes = 4 * 5 * 2 * 2;
+
+TileCfg tune_at(int idx) {
+  TileCfg c;
+  c.persistent = idx % 2;
+  idx /= 2;
+  c.variant = idx % 2;
+  idx /= 2;
+  c.planes = kPlanes[idx % 5];
+  idx /= 5;
+  c.rows = kRows[idx % 4];
+  return c;
+}
+}  // namespace
+
+TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
+  TileCfg c;
+  if (tune_cache_lookup_single(dtype, nx, ny, nz, &c)) return c;
+  c.rows = 4;
+  c.planes = 32;
+  c.variant = 0;
+  c.persistent = 0;
+  return c;
+}
+
+// Sum-of-squares pass over (u, f) followed by the deterministic reduce into
+// `out` (device).  flags is F_RES (residual of u) or F_NORM (norm of f).
+static int norm_pass(unsigned flags, const Field& u, const Field& f, const Field* o, double h,
+                     const TileCfg& c, double* out, hipStream_t st, Scratch* s) {
+  const Field* up = (flags & F_NORM) ? nullptr : &u;
+  GridArgs g = make_args(up, o, &f, nullptr, nullptr, h, c, 0);
+  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  J3D_HIP(launch_pass_one(J3D_F64, flags, c, g, s->partials, nullptr, st));
+  J3D_HIP(launch_reduce_one(s->partials, 0, nt, out, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));
+  return J3D_OK;
+}
+
+}  // namespace j3d
+
+using namespace j3d;
+
+extern "C" {
+
+int j3d_abi_version(void) { return J3D_ABI_VERSION; }
+
+const char* j3d_last_error(void) { return last_error_text(); }
+
+int j3d_element_offset(const j3d_array* a, int64_t i, int64_t j, int64_t k, int64_t* offset) {
+  J3D_TRY(check_field(a, -1, nullptr, "array"));
+  if (offset == nullptr) return fail(J3D_EINVAL, "offset: null pointer");
+  const int64_t idx[3] = {i, j, k};
+  int64_t off = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (idx[d] < a->lbound[d] || idx[d] > a->ubound[d])
+      return fail(J3D_EINVAL, "index %lld outside bounds %lld:%lld on axis %d", (long long)idx[d],
+                  (long long)a->lbound[d], (long long)a->ubound[d], d);
+    off += (idx[d] - a->lbound[d]) * a->stride[d];
+  }
+  *offset = off;
+  return J3D_OK;
+}
+
+int j3d_check_array(const j3d_array* a, int32_t dtype) { return check_field(a, dtype, nullptr, "array"); }
+
+int j3d_tune_count(void) { return kNumTunes; }
+
+int j3d_tune_get(int32_t index, j3d_tune* out) {
+  if (out == nullptr || index < 0 || index >= kNumTunes) return fail(J3D_EINVAL, "tune index out of range");
+  TileCfg c = tune_at(index);
+  out->rows = c.rows;
+  out->planes = c.planes;
+  out->variant = c.variant;
+  out->persistent = c.persistent;
+  return J3D_OK;
+}
+
+int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+                   uint32_t flags, double* resid_out, void* stream) {
+  Field a, b, c;
+  J3D_TRY(check_field(u_in, -1, &a, "u_in"));
+  J3D_TRY(check_field(u_out, a.dtype, &b, "u_out"));
+  J3D_TRY(check_field(f, a.dtype, &c, "f"));
+  J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
+  J3D_TRY(check_same_interior(a, c, "u_in", "f"));
+  J3D_TRY(check_h(h));
+  if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
+  if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
+  if (resid_out != nullptr && a.dtype != J3D_F64)
+    return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const TileCfg cfg = default_cfg(a.dtype, a.nx(), a.ny(), a.nz());
+  GridArgs g = make_args(&a, &b, &c, nullptr, nullptr, h, cfg, 0);
+  if (resid_out == nullptr) {
+    J3D_HIP(launch_pass_one(a.dtype, F_WRITE, cfg, g, nullptr, nullptr, st));
+    return J3D_OK;
+  }
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  J3D_HIP(launch_pass_one(J3D_F64, F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
+  const bool host = (flags & J3D_HOST_RESULT) != 0;
+  double* dst = host ? &s->ctl->value : resid_out;
+  J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));
+  if (host) {
+    J3D_HIP(hipMemcpyAsync(&s->ctl_host->value, &s->ctl->value, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    *resid_out = s->ctl_host->value;
+  }
+  return J3D_OK;
+}
+
+int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags, double* out,
+                void* stream) {
+  Field a, c;
+  J3D_TRY(check_field(u, J3D_F64, &a, "u"));
+  J3D_TRY(check_field(f, J3D_F64, &c, "f"));
+  J3D_TRY(check_same_interior(a, c, "u", "f"));
+  J3D_TRY(check_h(h));
+  if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  if (out == nullptr) return fail(J3D_EINVAL, "out: null pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const TileCfg cfg = default_cfg(J3D_F64, a.nx(), a.ny(), a.nz());
+  const bool host = (flags & J3D_HOST_RESULT) != 0;
+  J3D_TRY(norm_pass(F_RES, a, c, nullptr, h, cfg, host ? &s->ctl->value : out, st, s));
+  if (host) {
+    J3D_HIP(hipMemcpyAsync(&s->ctl_host->value, &s->ctl->value, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    *out = s->ctl_host->value;
+  }
+  return J3D_OK;
+}
+
+int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, double lo, double hi,
+                     double halo, void* stream) {
+  Field x;
+  J3D_TRY(check_field(a, J3D_F64, &x, "a"));
+  if (x.ey > 65535 || x.ez > 65535) return fail(J3D_EINVAL, "fill: y/z extents above 65535");
+  const unsigned long long key = seed ^ (static_cast<unsigned long long>(stream_id) << 40);
+  J3D_HIP(launch_fill_uniform(reinterpret_cast<double*>(x.base), x.ex, x.ey, x.ez, x.sy, x.sz, key,
+                              lo, hi, halo, static_cast<hipStream_t>(stream)));
+  return J3D_OK;
+}
+
+int j3d_fill_const(const j3d_array* a, double value, void* stream) {
+  Field x;
+  J3D_TRY(check_field(a, -1, &x, "a"));
+  if (x.ey > 65535 || x.ez > 65535) return fail(J3D_EINVAL, "fill: y/z extents above 65535");
+  J3D_HIP(launch_fill_const(x.base, x.dtype, x.ex, x.ey, x.ez, x.sy, x.sz, value,
+                            static_cast<hipStream_t>(stream)));
+  return J3D_OK;
+}
+
+int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps, double* gbps,
+                        void* stream) {
+  if (src == nullptr || dst == nullptr || gbps == nullptr || n < 2 || reps < 1)
+    return fail(J3D_EINVAL, "bandwidth probe: bad arguments");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(J3D_EINVAL, "bandwidth probe: buffers must be 16-byte aligned");
+  if ((src < dst && src + n > dst) || (dst < src && dst + n > src) || src == dst)
+    return fail(J3D_EALIAS, "bandwidth probe: buffers overlap");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  J3D_HIP(hipEventCreate(&e0));
+  J3D_HIP(hipEventCreate(&e1));
+  J3D_HIP(launch_copy(src, dst, n, st));  // warm-up
+  double best = 0.0;
+  for (int r = 0; r < reps; ++r) {
+    J3D_HIP(hipEventRecord(e0, st));
+    J3D_HIP(launch_copy(src, dst, n, st));
+    J3D_HIP(hipEventRecord(e1, st));
+    J3D_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    J3D_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double rate = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
+    if (rate > best) best = rate;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *gbps = best;
+  return J3D_OK;
+}
+
+int j3d_release_cache(void) {
+  release_batch_cache();
+  return release_all_scratch();
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal interface between the host runtime and the gfx950 kernels of libj3d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "j3d.h"
+
+namespace j3d {
+
+// Per-grid launch descriptor.  Every pointer addresses the array element at
+// Fortran index (lbound0, lbound1, lbound2), i.e. the corner of the halo, so
+// that interior point (i,j,k), 1 <= i <= nx etc., is at i + sy*j + sz*k.
+struct GridArgs {
+  const void* u;    // input iterate (T)
+  void* o;          // output iterate (T), written with F_WRITE
+  const void* f;    // right-hand side (T); for FP32 correction sweeps: r32
+  double* u64;      // FP64 field the update is added to, with F_LAST
+  float* r32;       // FP32 copy of the residual, written with F_R32
+  int nx, ny, nz;
+  int su_y, su_z;   // strides of u
+  int so_y, so_z;   // strides of o
+  int sf_y, sf_z;   // strides of f
+  int s64_y, s64_z; // strides of u64
+  int sr_y, sr_z;   // strides of r32
+  int tiles_x, tiles_y, tiles_z;
+  int tile0;        // first tile of this grid in the batch's tile numbering
+  int planes;       // z-planes per tile
+  int id;           // index of this grid's flags and norms in per-grid arrays
+  double h2;        // h*h in FP64
+  float h2f;        // (float)(h*h)
+  float pad2_;
+};
+
+// Kernel pass flags (compile-time).
+enum : unsigned {
+  F_WRITE = 1u,   // write the Jacobi update to o
+  F_RES = 2u,     // accumulate sum of r^2 of the input iterate (FP64)
+  F_R32 = 4u,     // store (float) r to r32
+  F_FIRST = 8u,   // the input iterate is identically zero (not read)
+  F_LAST = 16u,   // add (double) update to u64 instead of writing o
+  F_NORM = 32u,   // accumulate sum of f^2 only
+};
+
+struct TileCfg {
+  int rows;       // y-rows per workgroup = wavefronts per workgroup
+  int planes;     // z-planes per tile
+  int variant;    // 0: neighbours through the cache, 1: plane staged in LDS
+  int persistent; // 1: fixed grid striding over tiles
+};
+
+// Supported rows values and variants (kernels are instantiated for these).
+bool tile_cfg_supported(const TileCfg& c);
+
+// Number of tiles of one grid under a tile shape.
+void tile_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
+
+// Number of resident workgroups used for persistent launches.
+int persistent_grid(const TileCfg& c);
+
+// Launch one pass over one grid (args by value).  partials receives one
+// double per tile (slot = tile index) when flags include F_RES or F_NORM.
+// done, if not null, is a flag: when *done != 0 the launch does nothing.
+hipError_t launch_pass_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                           double* partials, const int* done, hipStream_t st);
+
+// Launch one pass over a table of grids in device memory (tile0 ascending,
+// tiles of grid g are [tile0[g], tile0[g] + tx*ty*tz)).  done, if not
+// null, is a flag array indexed by GridArgs::id; tiles of done grids are
+// skipped.
+hipError_t launch_pass_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table,
+                             int ngrids, int ntiles, double* partials, const int* done,
+                             hipStream_t st);
+
+// Deterministic sum of partials[part0 .. part0+n) -> sqrt -> *out.
+// If test_normf is not null: when sqrt(sum) <= rtol * (*test_normf) or is not
+// finite, set *done = 1 and *conv_at = s; a non-finite value also sets
+// *nonfinite = 1.  When done is not null and *done != 0 on entry, nothing is
+// written.
+hipError_t launch_reduce_one(const double* partials, int part0, int n, double* out,
+                             const double* test_normf, double rtol, long long s, int* done,
+                             long long* conv_at, int* nonfinite, hipStream_t st);
+
+// Batched reduce: one workgroup per table entry; entry g (id = table[g].id)
+// sums its own tile slots and writes sqrt to out[id*ostride + q].  Grids
+// flagged done[id] are skipped.  With normf (indexed by id) the convergence
+// test of launch_reduce_one is applied per grid (done, conv_at, nonfinite,
+// rtol all indexed by id).
+hipError_t launch_reduce_batch(const double* partials, const GridArgs* table, int ngrids,
+                               double* out, int ostride, int q, const double* normf,
+                               const double* rtol, long long s, int* done, long long* conv_at,
+                               int* nonfinite, hipStream_t st);
+
+hipError_t launch_fill_uniform(double* a, int ex, int ey, int ez, long long sy, long long sz,
+                               unsigned long long key, double lo, double hi, double halo,
+                               hipStream_t st);
+hipError_t launch_fill_const(void* a, int dtype, int ex, int ey, int ez, long long sy,
+                             long long sz, double v, hipStream_t st);
+hipError_t launch_copy(const double* src, double* dst, long long n, hipStream_t st);
+hipError_t launch_copy_interior(const double* src, double* dst, int nx, int ny, int nz,
+                                long long ssy, long long ssz, long long dsy, long long dsz,
+                                hipStream_t st);
+hipError_t launch_set_int(int* p, int n, int v, hipStream_t st);
+
+}  // namespace j3d

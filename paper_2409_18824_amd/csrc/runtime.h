@@ -1,0 +1,97 @@
+// Host runtime shared by the C-ABI entry points of libj3d.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "j3d_internal.h"
+
+namespace j3d {
+
+// Records a message for j3d_last_error() on this thread and returns code.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char* what);
+
+#define J3D_HIP(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return ::j3d::hip_fail(e_, #expr); \
+  } while (0)
+
+#define J3D_TRY(expr)            \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != J3D_OK) return rc_; \
+  } while (0)
+
+// A validated Fortran array.
+struct Field {
+  char* base = nullptr;  // element (lbound0, lbound1, lbound2)
+  int dtype = 0;
+  int esize = 8;
+  int ex = 0, ey = 0, ez = 0;  // extents including the halo
+  long long sy = 0, sz = 0;    // strides (elements)
+  int nx() const { return ex - 2; }
+  int ny() const { return ey - 2; }
+  int nz() const { return ez - 2; }
+  long long span_elems() const { return (long long)(ez - 1) * sz + (long long)(ey - 1) * sy + ex; }
+  size_t span_bytes() const { return (size_t)span_elems() * esize; }
+};
+
+// Validate a descriptor; dtype < 0 accepts either element type.
+int check_field(const j3d_array* a, int dtype, Field* out, const char* name);
+bool fields_overlap(const Field& a, const Field& b);
+int check_same_interior(const Field& a, const Field& b, const char* an, const char* bn);
+int check_h(double h);
+
+// Launch arguments for one pass.  `o`, `f`, `u64`, `r32` may be null when the
+// pass does not touch them.
+GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* u64,
+                   const Field* r32, double h, const TileCfg& c, int tile0);
+
+// Default tile shape for a grid of this size and element type (the
+// autotuner's cached choice when there is one).
+TileCfg default_cfg(int dtype, int nx, int ny, int nz);
+
+// Per-(device, stream) scratch: tile partials, control words, pinned host
+// words.  Grows on demand; lives until j3d_release_cache().
+struct Control {
+  double normf;
+  double value;
+  double value2;
+  double pad;
+  long long conv_at;
+  int done;
+  int nonfinite;
+};
+
+struct Scratch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double* partials = nullptr;
+  size_t partials_cap = 0;
+  Control* ctl = nullptr;      // device
+  Control* ctl_host = nullptr; // pinned host mirror
+  double* hist = nullptr;      // device history
+  size_t hist_cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // work arrays for poisson_solve
+  void* work = nullptr;
+  size_t work_bytes = 0;
+};
+
+int get_scratch(hipStream_t st, Scratch** out);
+int ensure_partials(Scratch* s, size_t n);
+int ensure_hist(Scratch* s, size_t n);
+int ensure_work(Scratch* s, size_t bytes);
+
+// Device memory helpers that report through fail().
+int dev_alloc(void** p, size_t bytes, const char* what);
+
+// Cached graphs / batch plans are released by this hook (batch.cpp).
+void release_batch_cache();
+
+double now_seconds();
+
+}  // namespace j3d

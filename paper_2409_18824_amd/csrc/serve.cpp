@@ -1,0 +1,543 @@
+// Continuous-batching Poisson server.
+//
+// Each admitted request is a slot holding its device state (u, f in FP64;
+// r32, e0, e1 in FP32).  One worker thread runs cycles over all active slots:
+//   1. FP64 defect step of every slot in one batched kernel (r = f - A u,
+//      r32 = (float) r, per-tile sums of r^2), one batched reduce that writes
+//      each slot's ||r|| and raises its done flag when ||r|| <= rtol ||f||;
+//   2. cycle_sweeps batched FP32 correction sweeps over the slots that still
+//      have sweeps left (done slots are skipped by flag); the last one adds
+//      the correction to u.
+// While a cycle runs on the GPU the worker admits queued requests (in
+// arrival order, while their state fits the memory budget and a slot is
+// free): it allocates their state and queues their set-up behind the cycle.
+// At the cycle boundary it retires converged and capped slots, copies their
+// results out, and the admitted requests join the next cycle.
+//
+// Every slot sees the same sequence of operations as a solo mixed solve
+// with inner_sweeps = cycle_sweeps, so its result does not depend on which
+// other requests share its cycles.  A request's max_sweeps is rounded up to a
+// whole number of cycles.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "runtime.h"
+
+namespace j3d {
+TileCfg default_cfg(int dtype, int nx, int ny, int nz);
+const char* last_error_text();
+}
+
+using namespace j3d;
+
+namespace {
+
+struct Layout {
+  Field u, f, r32, e0, e1;
+  size_t bytes = 0;
+};
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Carve the five arrays of a request out of one allocation.  Rows are padded
+// to 128 bytes and element (1, j, k) of every row is 128-byte aligned.
+Layout make_layout(int nx, int ny, int nz, char* mem) {
+  Layout L;
+  size_t off = 0;
+  auto place = [&](Field& a, int dtype) {
+    const int es = dtype == J3D_F64 ? 8 : 4;
+    const int al = 128 / es;
+    a.dtype = dtype;
+    a.esize = es;
+    a.ex = nx + 2;
+    a.ey = ny + 2;
+    a.ez = nz + 2;
+    a.sy = ((long long)a.ex + al - 1) / al * al;
+    a.sz = a.sy * a.ey;
+    a.base = mem ? mem + off + (size_t)(al - 1) * es : nullptr;
+    off += round256((size_t)(a.sz * a.ez + al) * es);
+  };
+  place(L.u, J3D_F64);
+  place(L.f, J3D_F64);
+  place(L.r32, J3D_F32);
+  place(L.e0, J3D_F32);
+  place(L.e1, J3D_F32);
+  L.bytes = off;
+  return L;
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  j3d_request r{};
+  std::vector<double> f;  // copy of f_host (empty: draw from seed)
+  double t_submit = 0, t_admit = 0;
+  int64_t max_sweeps = 0;
+  size_t bytes = 0;
+};
+
+struct Slot {
+  Request* req = nullptr;
+  int id = -1;
+  char* mem = nullptr;
+  Layout L;
+  int64_t sweeps = 0;
+  bool ready = false;  // set-up queued before the current cycle
+};
+
+}  // namespace
+
+struct j3d_server {
+  j3d_serve_opts o{};
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work;
+  std::condition_variable cv_done;
+  std::deque<Request*> queue;
+  std::vector<j3d_result> finished;
+  std::vector<Slot*> active;
+  std::vector<int> free_ids;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  int64_t n_submitted = 0;
+  int64_t n_finished = 0;
+  size_t used_bytes = 0;
+  double t0 = 0;
+  int error = J3D_OK;
+  std::string error_text;
+
+  // device state (owned by the worker)
+  hipStream_t st = nullptr;
+  double* d_normf = nullptr;  // [max_slots]
+  double* d_rtol = nullptr;
+  double* d_resid = nullptr;
+  int* d_done = nullptr;
+  int* d_nonfinite = nullptr;
+  long long* d_conv = nullptr;
+  GridArgs* d_tab = nullptr;  // 6 kinds * max_slots
+  double* d_part = nullptr;
+  size_t part_cap = 0;
+  GridArgs* h_tab = nullptr;  // pinned staging
+  double* h_rtol = nullptr;
+  double* h_out = nullptr;    // pinned: resid[max_slots]
+  int* h_flags = nullptr;     // pinned: done[max_slots], nonfinite[max_slots]
+  hipEvent_t ev = nullptr;
+  TileCfg cd{}, cs{};
+
+  double now() const { return now_seconds() - t0; }
+};
+
+namespace {
+
+enum Kind { K_DEF = 0, K_FIRST, K_MID01, K_MID10, K_LAST0, K_LAST1, K_NKINDS };
+
+int serve_fail(j3d_server* s, int code, const char* what) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->error == J3D_OK) {
+    s->error = code;
+    s->error_text = what;
+  }
+  s->stop = true;
+  s->cv_done.notify_all();
+  return code;
+}
+
+int setup_device(j3d_server* s) {
+  const int n = s->o.max_slots;
+  J3D_HIP(hipSetDevice(s->o.device));
+  J3D_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+  J3D_HIP(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
+  void* p = nullptr;
+  J3D_TRY(dev_alloc(&p, n * sizeof(double), "serve normf")); s->d_normf = (double*)p;
+  J3D_TRY(dev_alloc(&p, n * sizeof(double), "serve rtol")); s->d_rtol = (double*)p;
+  J3D_TRY(dev_alloc(&p, n * sizeof(double), "serve resid")); s->d_resid = (double*)p;
+  J3D_TRY(dev_alloc(&p, 2 * n * sizeof(int), "serve flags")); s->d_done = (int*)p;
+  s->d_nonfinite = s->d_done + n;
+  J3D_TRY(dev_alloc(&p, n * sizeof(long long), "serve conv")); s->d_conv = (long long*)p;
+  J3D_TRY(dev_alloc(&p, (size_t)K_NKINDS * n * sizeof(GridArgs), "serve tables")); s->d_tab = (GridArgs*)p;
+  J3D_HIP(hipHostMalloc((void**)&s->h_tab, (size_t)K_NKINDS * n * sizeof(GridArgs), hipHostMallocDefault));
+  J3D_HIP(hipHostMalloc((void**)&s->h_rtol, n * sizeof(double), hipHostMallocDefault));
+  J3D_HIP(hipHostMalloc((void**)&s->h_out, n * sizeof(double), hipHostMallocDefault));
+  J3D_HIP(hipHostMalloc((void**)&s->h_flags, 2 * n * sizeof(int), hipHostMallocDefault));
+  J3D_HIP(hipMemsetAsync(s->d_done, 0, 2 * n * sizeof(int), s->st));
+  s->cd = default_cfg(J3D_F64, 128, 128, 128);
+  s->cs = default_cfg(J3D_F32, 128, 128, 128);
+  s->cd.persistent = 0;
+  s->cs.persistent = 0;
+  return J3D_OK;
+}
+
+void teardown_device(j3d_server* s) {
+  if (s->st) (void)hipStreamSynchronize(s->st);
+  for (Slot* sl : s->active) {
+    if (sl->mem) (void)hipFree(sl->mem);
+    delete sl->req;
+    delete sl;
+  }
+  s->active.clear();
+  (void)hipFree(s->d_normf);
+  (void)hipFree(s->d_rtol);
+  (void)hipFree(s->d_resid);
+  (void)hipFree(s->d_done);
+  (void)hipFree(s->d_conv);
+  (void)hipFree(s->d_tab);
+  if (s->d_part) (void)hipFree(s->d_part);
+  if (s->h_tab) (void)hipHostFree(s->h_tab);
+  if (s->h_rtol) (void)hipHostFree(s->h_rtol);
+  if (s->h_out) (void)hipHostFree(s->h_out);
+  if (s->h_flags) (void)hipHostFree(s->h_flags);
+  if (s->ev) (void)hipEventDestroy(s->ev);
+  if (s->st) (void)hipStreamDestroy(s->st);
+}
+
+// Queue the set-up of an admitted slot on the server stream: zero state
+// (zero initial guess and zero Dirichlet halo), f from the host copy or the
+// seed, ||f|| into d_normf[id], flags cleared.
+int queue_setup(j3d_server* s, Slot* sl) {
+  const Request& q = *sl->req;
+  J3D_HIP(hipMemsetAsync(sl->mem, 0, sl->L.bytes, s->st));
+  const Field& f = sl->L.f;
+  if (!q.f.empty()) {
+    J3D_HIP(hipMemcpy2DAsync(f.base, (size_t)f.sy * 8, q.f.data(), (size_t)f.ex * 8, (size_t)f.ex * 8,
+                             (size_t)f.ey * f.ez, hipMemcpyHostToDevice, s->st));
+  } else {
+    const unsigned long long key = q.r.seed ^ (2ull << 40);  // stream 2: right-hand sides
+    J3D_HIP(launch_fill_uniform(reinterpret_cast<double*>(f.base), f.ex, f.ey, f.ez, f.sy, f.sz, key,
+                                -1.0, 1.0, 0.0, s->st));
+  }
+  GridArgs g = make_args(nullptr, nullptr, &f, nullptr, nullptr, q.r.h, s->cd, 0);
+  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  if ((size_t)nt > s->part_cap) {
+    // Growing the partials buffer: wait for users of the old one.
+    J3D_HIP(hipStreamSynchronize(s->st));
+    if (s->d_part) J3D_HIP(hipFree(s->d_part));
+    s->d_part = nullptr;
+    void* p = nullptr;
+    J3D_TRY(dev_alloc(&p, (size_t)nt * 2 * sizeof(double), "serve partials"));
+    s->d_part = (double*)p;
+    s->part_cap = (size_t)nt * 2;
+  }
+  J3D_HIP(launch_pass_one(J3D_F64, F_NORM, s->cd, g, s->d_part, nullptr, s->st));
+  J3D_HIP(launch_reduce_one(s->d_part, 0, nt, s->d_normf + sl->id, nullptr, 0.0, 0, nullptr, nullptr,
+                            nullptr, s->st));
+  J3D_HIP(launch_set_int(s->d_done + sl->id, 1, 0, s->st));
+  J3D_HIP(launch_set_int(s->d_nonfinite + sl->id, 1, 0, s->st));
+  sl->ready = true;
+  return J3D_OK;
+}
+
+// Admit queued requests while budget and slots allow.
+int admit(j3d_server* s) {
+  for (;;) {
+    Request* q = nullptr;
+    int id = -1;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->queue.empty() || s->free_ids.empty()) return J3D_OK;
+      Request* head = s->queue.front();
+      if (s->used_bytes + head->bytes > s->o.hbm_budget_bytes) return J3D_OK;
+      s->queue.pop_front();
+      id = s->free_ids.back();
+      s->free_ids.pop_back();
+      s->used_bytes += head->bytes;
+      q = head;
+    }
+    Slot* sl = new Slot();
+    sl->req = q;
+    sl->id = id;
+    void* mem = nullptr;
+    int rc = dev_alloc(&mem, q->bytes, "request state");
+    if (rc != J3D_OK) {
+      // Could not allocate now: put it back and retry after a retirement.
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->queue.push_front(q);
+      s->free_ids.push_back(id);
+      s->used_bytes -= q->bytes;
+      delete sl;
+      return s->active.empty() ? rc : J3D_OK;
+    }
+    sl->mem = static_cast<char*>(mem);
+    sl->L = make_layout(q->r.nx, q->r.ny, q->r.nz, sl->mem);
+    q->t_admit = s->now();
+    J3D_TRY(queue_setup(s, sl));
+    s->active.push_back(sl);
+  }
+}
+
+// Build the per-kind tables of the active slots and queue one cycle.
+int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
+  const int n = (int)slots.size();
+  const int cyc = s->o.cycle_sweeps;
+  GridArgs* T[K_NKINDS];
+  for (int k = 0; k < K_NKINDS; ++k) T[k] = s->h_tab + (size_t)k * s->o.max_slots;
+  int nt_def = 0, nt_swp = 0, n_in = 0;
+  for (int g = 0; g < n; ++g) {
+    Slot* sl = slots[g];
+    const Layout& L = sl->L;
+    const double h = sl->req->r.h;
+    GridArgs d = make_args(&L.u, nullptr, &L.f, nullptr, &L.r32, h, s->cd, nt_def);
+    d.id = sl->id;
+    T[K_DEF][g] = d;
+    nt_def += d.tiles_x * d.tiles_y * d.tiles_z;
+    s->h_rtol[sl->id] = sl->req->r.rtol;
+    if (sl->sweeps >= sl->req->max_sweeps) continue;  // final defect only
+    GridArgs a[K_NKINDS];
+    a[K_FIRST] = make_args(nullptr, &L.e0, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
+    a[K_MID01] = make_args(&L.e0, &L.e1, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
+    a[K_MID10] = make_args(&L.e1, &L.e0, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
+    a[K_LAST0] = make_args(&L.e0, nullptr, &L.r32, &L.u, nullptr, h, s->cs, nt_swp);
+    a[K_LAST1] = make_args(&L.e1, nullptr, &L.r32, &L.u, nullptr, h, s->cs, nt_swp);
+    for (int k = K_FIRST; k < K_NKINDS; ++k) {
+      a[k].id = sl->id;
+      T[k][n_in] = a[k];
+    }
+    nt_swp += a[K_FIRST].tiles_x * a[K_FIRST].tiles_y * a[K_FIRST].tiles_z;
+    ++n_in;
+  }
+  if ((size_t)nt_def > s->part_cap) {
+    J3D_HIP(hipStreamSynchronize(s->st));
+    if (s->d_part) J3D_HIP(hipFree(s->d_part));
+    s->d_part = nullptr;
+    void* p = nullptr;
+    J3D_TRY(dev_alloc(&p, (size_t)nt_def * 2 * sizeof(double), "serve partials"));
+    s->d_part = (double*)p;
+    s->part_cap = (size_t)nt_def * 2;
+  }
+  const size_t row = (size_t)s->o.max_slots;
+  J3D_HIP(hipMemcpyAsync(s->d_tab, s->h_tab, (size_t)K_NKINDS * row * sizeof(GridArgs),
+                         hipMemcpyHostToDevice, s->st));
+  J3D_HIP(hipMemcpyAsync(s->d_rtol, s->h_rtol, row * sizeof(double), hipMemcpyHostToDevice, s->st));
+  GridArgs* D[K_NKINDS];
+  for (int k = 0; k < K_NKINDS; ++k) D[k] = s->d_tab + (size_t)k * row;
+  int* done = s->d_done;
+  J3D_HIP(launch_pass_batch(J3D_F64, F_RES | F_R32, s->cd, D[K_DEF], n, nt_def, s->d_part, done, s->st));
+  J3D_HIP(launch_reduce_batch(s->d_part, D[K_DEF], n, s->d_resid, 1, 0, s->d_normf, s->d_rtol, 0, done,
+                              s->d_conv, s->d_nonfinite, s->st));
+  if (n_in > 0) {
+    if (cyc == 1) {
+      // A one-sweep cycle: first and last sweep at once.
+      J3D_HIP(launch_pass_batch(J3D_F32, F_LAST | F_FIRST, s->cs, D[K_LAST0], n_in, nt_swp, nullptr,
+                                done, s->st));
+    } else {
+      J3D_HIP(launch_pass_batch(J3D_F32, F_WRITE | F_FIRST, s->cs, D[K_FIRST], n_in, nt_swp, nullptr,
+                                done, s->st));
+      for (int p = 1; p <= cyc - 2; ++p)
+        J3D_HIP(launch_pass_batch(J3D_F32, F_WRITE, s->cs, (p & 1) ? D[K_MID01] : D[K_MID10], n_in,
+                                  nt_swp, nullptr, done, s->st));
+      J3D_HIP(launch_pass_batch(J3D_F32, F_LAST, s->cs, ((cyc - 2) & 1) ? D[K_LAST1] : D[K_LAST0], n_in,
+                                nt_swp, nullptr, done, s->st));
+    }
+  }
+  // Residuals and flags of this cycle's defect step, for the host.
+  J3D_HIP(hipMemcpyAsync(s->h_out, s->d_resid, row * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  J3D_HIP(hipMemcpyAsync(s->h_flags, s->d_done, 2 * row * sizeof(int), hipMemcpyDeviceToHost, s->st));
+  J3D_HIP(hipEventRecord(s->ev, s->st));
+  return J3D_OK;
+}
+
+int retire(j3d_server* s, Slot* sl, bool converged, bool nonfinite, double resid, double normf) {
+  Request* q = sl->req;
+  if (q->r.u_host != nullptr) {
+    const Field& u = sl->L.u;
+    J3D_HIP(hipMemcpy2DAsync(q->r.u_host, (size_t)u.ex * 8, u.base, (size_t)u.sy * 8, (size_t)u.ex * 8,
+                             (size_t)u.ey * u.ez, hipMemcpyDeviceToHost, s->st));
+    J3D_HIP(hipStreamSynchronize(s->st));
+  }
+  J3D_HIP(hipFree(sl->mem));
+  j3d_result r{};
+  r.ticket = q->ticket;
+  r.status = nonfinite ? J3D_ENONFINITE : J3D_OK;
+  r.converged = (converged && !nonfinite) ? 1 : 0;
+  r.sweeps = sl->sweeps;
+  r.resid = resid;
+  r.norm_f = normf;
+  r.t_submit = q->t_submit;
+  r.t_admit = q->t_admit;
+  r.t_done = s->now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->finished.push_back(r);
+    s->n_finished++;
+    s->used_bytes -= q->bytes;
+    s->free_ids.push_back(sl->id);
+  }
+  s->cv_done.notify_all();
+  delete q;
+  delete sl;
+  return J3D_OK;
+}
+
+int worker_loop(j3d_server* s) {
+  J3D_TRY(setup_device(s));
+  std::vector<double> normf_h((size_t)s->o.max_slots, 0.0);
+  for (;;) {
+    J3D_TRY(admit(s));
+    if (s->active.empty()) {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      if (s->stop) return J3D_OK;
+      continue;
+    }
+    std::vector<Slot*> cyc = s->active;  // slots in this cycle
+    J3D_TRY(queue_cycle(s, cyc));
+    // Overlap: admit arrivals while the cycle runs; their set-up is queued
+    // behind it and they join the next cycle.
+    J3D_TRY(admit(s));
+    J3D_HIP(hipEventSynchronize(s->ev));
+    J3D_HIP(hipMemcpy(normf_h.data(), s->d_normf, normf_h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<Slot*> keep;
+    const int ms = s->o.max_slots;
+    for (Slot* sl : s->active) {
+      const bool in_cycle = std::find(cyc.begin(), cyc.end(), sl) != cyc.end();
+      if (!in_cycle) {
+        keep.push_back(sl);
+        continue;
+      }
+      const bool done = s->h_flags[sl->id] != 0;
+      const bool bad = s->h_flags[ms + sl->id] != 0;
+      const double resid = s->h_out[sl->id];
+      if (done || bad) {
+        J3D_TRY(retire(s, sl, done, bad, resid, normf_h[sl->id]));
+      } else if (sl->sweeps >= sl->req->max_sweeps) {
+        J3D_TRY(retire(s, sl, false, false, resid, normf_h[sl->id]));
+      } else {
+        sl->sweeps += s->o.cycle_sweeps;
+        keep.push_back(sl);
+      }
+    }
+    s->active.swap(keep);
+    bool stop;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      stop = s->stop;
+    }
+    if (stop) return J3D_OK;
+  }
+}
+
+void worker_main(j3d_server* s) {
+  int rc = worker_loop(s);
+  if (rc != J3D_OK) serve_fail(s, rc, j3d::last_error_text());
+  teardown_device(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return 0;
+  return make_layout(nx, ny, nz, nullptr).bytes;
+}
+
+int poisson_serve_create(const j3d_serve_opts* opts, j3d_server** out) {
+  if (opts == nullptr || out == nullptr) return fail(J3D_EINVAL, "opts/out: null pointer");
+  if (opts->max_slots < 1 || opts->max_slots > 65536) return fail(J3D_EINVAL, "max_slots out of range");
+  if (opts->cycle_sweeps < 1) return fail(J3D_EINVAL, "cycle_sweeps must be >= 1");
+  if (opts->queue_cap < 1) return fail(J3D_EINVAL, "queue_cap must be >= 1");
+  if (opts->hbm_budget_bytes == 0) return fail(J3D_EINVAL, "hbm_budget_bytes must be > 0");
+  int ndev = 0;
+  J3D_HIP(hipGetDeviceCount(&ndev));
+  if (opts->device < 0 || opts->device >= ndev) return fail(J3D_EINVAL, "no such device");
+  j3d_server* s = new j3d_server();
+  s->o = *opts;
+  s->t0 = now_seconds();
+  for (int i = opts->max_slots - 1; i >= 0; --i) s->free_ids.push_back(i);
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return J3D_OK;
+}
+
+int poisson_serve_submit(j3d_server* s, const j3d_request* req, uint64_t* ticket) {
+  if (s == nullptr || req == nullptr || ticket == nullptr) return fail(J3D_EINVAL, "null pointer");
+  if (req->nx < 1 || req->ny < 1 || req->nz < 1) return fail(J3D_EINVAL, "extents must be >= 1");
+  if (req->reserved != 0) return fail(J3D_EINVAL, "reserved field must be 0");
+  J3D_TRY(check_h(req->h));
+  if (!(req->rtol >= 0.0) || !std::isfinite(req->rtol)) return fail(J3D_EINVAL, "rtol must be finite and >= 0");
+  if (req->max_sweeps < 0) return fail(J3D_EINVAL, "max_sweeps must be >= 0");
+  const long long ex = req->nx + 2LL, ey = req->ny + 2LL, ez = req->nz + 2LL;
+  if (ey > 65535 || ez > 65535 || ((ex + 31) / 32 * 32) * ey * ez >= (1LL << 31) - 64)
+    return fail(J3D_EINVAL, "grid too large");
+  const size_t bytes = make_layout(req->nx, req->ny, req->nz, nullptr).bytes;
+  if (bytes > s->o.hbm_budget_bytes)
+    return fail(J3D_EBUDGET, "request needs %zu bytes, budget is %llu", bytes,
+                (unsigned long long)s->o.hbm_budget_bytes);
+  Request* q = new Request();
+  q->r = *req;
+  q->bytes = bytes;
+  const int64_t c = s->o.cycle_sweeps;
+  q->max_sweeps = (req->max_sweeps + c - 1) / c * c;
+  if (req->f_host != nullptr) q->f.assign(req->f_host, req->f_host + ex * ey * ez);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->error != J3D_OK) {
+    delete q;
+    return fail(s->error, "server stopped: %s", s->error_text.c_str());
+  }
+  if ((int)s->queue.size() >= s->o.queue_cap) {
+    delete q;
+    return fail(J3D_EAGAIN, "queue full");
+  }
+  q->ticket = s->next_ticket++;
+  q->t_submit = s->now();
+  s->queue.push_back(q);
+  s->n_submitted++;
+  *ticket = q->ticket;
+  s->cv_work.notify_one();
+  return J3D_OK;
+}
+
+int poisson_serve_poll(j3d_server* s, j3d_result* out, int32_t cap, int32_t* n) {
+  if (s == nullptr || n == nullptr || (cap > 0 && out == nullptr)) return fail(J3D_EINVAL, "null pointer");
+  std::lock_guard<std::mutex> lk(s->mu);
+  const int m = std::min<int>(cap, (int)s->finished.size());
+  for (int i = 0; i < m; ++i) out[i] = s->finished[i];
+  s->finished.erase(s->finished.begin(), s->finished.begin() + m);
+  *n = m;
+  if (s->error != J3D_OK) return fail(s->error, "server stopped: %s", s->error_text.c_str());
+  return J3D_OK;
+}
+
+int poisson_serve_drain(j3d_server* s, double timeout_s) {
+  if (s == nullptr) return fail(J3D_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto pred = [&] { return s->n_finished >= s->n_submitted || s->error != J3D_OK; };
+  if (timeout_s <= 0) {
+    s->cv_done.wait(lk, pred);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) {
+    return fail(J3D_EAGAIN, "drain timed out");
+  }
+  if (s->error != J3D_OK) return fail(s->error, "server stopped: %s", s->error_text.c_str());
+  return J3D_OK;
+}
+
+int poisson_serve_stats(j3d_server* s, double* now, int32_t* active, int32_t* queued, int64_t* finished) {
+  if (s == nullptr) return fail(J3D_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (now) *now = s->now();
+  if (active) *active = (int32_t)(s->o.max_slots - (int)s->free_ids.size());
+  if (queued) *queued = (int32_t)s->queue.size();
+  if (finished) *finished = s->n_finished;
+  return J3D_OK;
+}
+
+int poisson_serve_destroy(j3d_server* s) {
+  if (s == nullptr) return fail(J3D_EINVAL, "null server");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (Request* q : s->queue) delete q;
+  s->queue.clear();
+  delete s;
+  return J3D_OK;
+}
+
+}  // extern "C"

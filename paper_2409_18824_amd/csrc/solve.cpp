@@ -1,0 +1,299 @@
+// poisson_solve: plain FP64 Jacobi and FP32-sweep / FP64-defect-correction
+// mixed-precision solves, with the convergence test on the device.
+//
+// The host enqueues kernels in chunks of a few milliseconds and, between
+// chunks, reads a pinned copy of the device's `done` flag.  Every kernel
+// queued after the flag is raised returns at once, so overshooting the
+// convergence point costs only empty launches.  This is the early-exit loop
+// of the paper's iterate_while lowering (Sec. "Handling of control
+// structures") with the exit test evaluated where the data lives.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "runtime.h"
+
+namespace j3d {
+namespace {
+
+// Chunk length (in sweeps) that keeps the device busy for about 2 ms.
+long long chunk_sweeps(long long points, double bytes_per_point, long long multiple) {
+  const double t = std::max(3e-6, bytes_per_point * (double)points / 5e12);
+  long long n = (long long)std::ceil(2e-3 / t);
+  n = std::max<long long>(n, 1);
+  n = std::min<long long>(n, 1 << 16);
+  n = ((n + multiple - 1) / multiple) * multiple;
+  return n;
+}
+
+int publish_done(Scratch* s, int slot, hipStream_t st) {
+  J3D_HIP(hipMemcpyAsync(&s->ctl_host->done, &s->ctl->done, sizeof(int), hipMemcpyDeviceToHost, st));
+  J3D_HIP(hipEventRecord(s->ev[slot & 1], st));
+  return J3D_OK;
+}
+
+// Waits for the event of an earlier chunk and returns the flag it published.
+int poll_done(Scratch* s, int slot, bool* done) {
+  J3D_HIP(hipEventSynchronize(s->ev[slot & 1]));
+  *done = __atomic_load_n(&s->ctl_host->done, __ATOMIC_ACQUIRE) != 0;
+  return J3D_OK;
+}
+
+int read_control(Scratch* s, Control* out, hipStream_t st) {
+  J3D_HIP(hipMemcpyAsync(s->ctl_host, s->ctl, sizeof(Control), hipMemcpyDeviceToHost, st));
+  J3D_HIP(hipStreamSynchronize(st));
+  std::memcpy(out, s->ctl_host, sizeof(Control));
+  return J3D_OK;
+}
+
+int read_history(Scratch* s, long long nh, std::vector<double>* h, hipStream_t st) {
+  h->assign((size_t)nh, 0.0);
+  if (nh > 0)
+    J3D_HIP(hipMemcpyAsync(h->data(), s->hist, (size_t)nh * sizeof(double), hipMemcpyDeviceToHost, st));
+  J3D_HIP(hipStreamSynchronize(st));
+  return J3D_OK;
+}
+
+int norm_f(const Field& f, const TileCfg& c, Scratch* s, hipStream_t st) {
+  GridArgs g = make_args(nullptr, nullptr, &f, nullptr, nullptr, 1.0, c, 0);
+  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  J3D_HIP(launch_pass_one(J3D_F64, F_NORM, c, g, s->partials, nullptr, st));
+  J3D_HIP(launch_reduce_one(s->partials, 0, nt, &s->ctl->normf, nullptr, 0.0, 0, nullptr, nullptr,
+                            nullptr, st));
+  return J3D_OK;
+}
+
+void fill_result(j3d_solve_result* r, long long sweeps, double resid, const std::vector<double>& hist,
+                 double normf, bool converged, bool nonfinite, const j3d_solve_opts& o) {
+  r->sweeps = sweeps;
+  r->resid = resid;
+  r->resid0 = hist.empty() ? resid : hist[0];
+  r->norm_f = normf;
+  r->converged = (converged && !nonfinite) ? 1 : 0;
+  r->status = nonfinite ? J3D_ENONFINITE : J3D_OK;
+  long long n = 0;
+  if (o.history != nullptr && o.history_cap > 0) {
+    n = std::min<long long>((long long)hist.size(), o.history_cap);
+    std::memcpy(o.history, hist.data(), (size_t)n * sizeof(double));
+  }
+  r->history_len = n;
+}
+
+// ---------------------------------------------------------------------
+// FP64 mode
+// ---------------------------------------------------------------------
+int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o,
+               j3d_solve_result* res, hipStream_t st) {
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const TileCfg cfg = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());
+  const long long S = o.max_sweeps;
+  const long long c = o.check_every;
+
+  // The second ping-pong array has u's layout and starts as a copy of u
+  // (which gives it the same halo).
+  Field w = u;
+  J3D_TRY(ensure_work(s, u.span_bytes()));
+  w.base = static_cast<char*>(s->work);
+  J3D_HIP(hipMemcpyAsync(w.base, u.base, u.span_bytes(), hipMemcpyDeviceToDevice, st));
+
+  const GridArgs fwd = make_args(&u, &w, &f, nullptr, nullptr, h, cfg, 0);  // u -> w
+  const GridArgs bwd = make_args(&w, &u, &f, nullptr, nullptr, h, cfg, 0);  // w -> u
+  const int nt = fwd.tiles_x * fwd.tiles_y * fwd.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  const long long nchecks = S / c + 1;
+  J3D_TRY(ensure_hist(s, (size_t)nchecks));
+
+  J3D_HIP(hipMemsetAsync(s->ctl, 0, sizeof(Control), st));
+  J3D_TRY(norm_f(f, cfg, s, st));
+  int* done = &s->ctl->done;
+
+  const long long points = (long long)u.nx() * u.ny() * u.nz();
+  const long long chunk = chunk_sweeps(points, 24.0, c);
+  long long sw = 0;
+  int slot = 0;
+  bool seen = false;
+  while (sw < S && !seen) {
+    const long long end = std::min(S, sw + chunk);
+    for (; sw < end; ++sw) {
+      const bool check = (sw % c) == 0;
+      const GridArgs& g = (sw & 1) ? bwd : fwd;
+      J3D_HIP(launch_pass_one(J3D_F64, F_WRITE | (check ? F_RES : 0u), cfg, g, s->partials, done, st));
+      if (check)
+        J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + sw / c, &s->ctl->normf, o.rtol,
+                                  sw / c, done, &s->ctl->conv_at, &s->ctl->nonfinite, st));
+    }
+    J3D_TRY(publish_done(s, slot, st));
+    if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
+    ++slot;
+  }
+  // Residual of the iterate after the last sweep (a check when S % c == 0).
+  {
+    const Field& cur = (S & 1) ? w : u;
+    GridArgs g = make_args(&cur, nullptr, &f, nullptr, nullptr, h, cfg, 0);
+    J3D_HIP(launch_pass_one(J3D_F64, F_RES, cfg, g, s->partials, done, st));
+    if (S % c == 0)
+      J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + S / c, &s->ctl->normf, o.rtol, S / c,
+                                done, &s->ctl->conv_at, &s->ctl->nonfinite, st));
+    else
+      J3D_HIP(launch_reduce_one(s->partials, 0, nt, &s->ctl->value, nullptr, 0.0, 0, done, nullptr,
+                                nullptr, st));
+  }
+  Control ctl;
+  J3D_TRY(read_control(s, &ctl, st));
+  long long sweeps, nh;
+  if (ctl.done) {
+    sweeps = ctl.conv_at * c;
+    nh = ctl.conv_at + 1;
+  } else {
+    sweeps = S;
+    nh = S / c + 1;
+  }
+  std::vector<double> hist;
+  J3D_TRY(read_history(s, nh, &hist, st));
+  const double resid = (ctl.done || S % c == 0) ? hist[(size_t)nh - 1] : ctl.value;
+  if (sweeps & 1) {
+    J3D_HIP(launch_copy_interior(reinterpret_cast<const double*>(w.base), reinterpret_cast<double*>(u.base),
+                                 u.nx(), u.ny(), u.nz(), w.sy, w.sz, u.sy, u.sz, st));
+    J3D_HIP(hipStreamSynchronize(st));
+  }
+  fill_result(res, sweeps, resid, hist, ctl.normf, ctl.done != 0, ctl.nonfinite != 0, o);
+  return ctl.nonfinite ? fail(J3D_ENONFINITE, "residual became non-finite") : J3D_OK;
+}
+
+// ---------------------------------------------------------------------
+// Mixed mode
+// ---------------------------------------------------------------------
+
+// A compact FP32 array with the interior extents of `like`, rows padded to
+// 128 bytes and element (1, j, k) 128-byte aligned, carved from `mem`.
+Field f32_field(const Field& like, char* mem, size_t* bytes) {
+  Field a;
+  a.dtype = J3D_F32;
+  a.esize = 4;
+  a.ex = like.ex;
+  a.ey = like.ey;
+  a.ez = like.ez;
+  const long long ld = ((long long)like.ex + 31) / 32 * 32;
+  a.sy = ld;
+  a.sz = ld * like.ey;
+  a.base = mem + 31 * 4;
+  *bytes = (size_t)(a.sz * a.ez + 32) * 4;
+  *bytes = (*bytes + 255) / 256 * 256;
+  return a;
+}
+
+int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& o,
+                j3d_solve_result* res, hipStream_t st) {
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const TileCfg cd = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());
+  const TileCfg cs = default_cfg(J3D_F32, u.nx(), u.ny(), u.nz());
+  const long long S = o.max_sweeps;
+  const long long m_in = o.inner_sweeps;
+
+  size_t b1 = 0;
+  (void)f32_field(u, nullptr, &b1);
+  J3D_TRY(ensure_work(s, 3 * b1));
+  char* mem = static_cast<char*>(s->work);
+  size_t tmp;
+  const Field r32 = f32_field(u, mem, &tmp);
+  const Field e0 = f32_field(u, mem + b1, &tmp);
+  const Field e1 = f32_field(u, mem + 2 * b1, &tmp);
+  J3D_HIP(hipMemsetAsync(mem, 0, 3 * b1, st));  // zero halos of the correction
+
+  const GridArgs defect = make_args(&u, nullptr, &f, nullptr, &r32, h, cd, 0);
+  const GridArgs first = make_args(nullptr, &e0, &r32, nullptr, nullptr, h, cs, 0);
+  const GridArgs first_last = make_args(nullptr, nullptr, &r32, &u, nullptr, h, cs, 0);
+  const GridArgs mid01 = make_args(&e0, &e1, &r32, nullptr, nullptr, h, cs, 0);
+  const GridArgs mid10 = make_args(&e1, &e0, &r32, nullptr, nullptr, h, cs, 0);
+  const GridArgs last0 = make_args(&e0, nullptr, &r32, &u, nullptr, h, cs, 0);
+  const GridArgs last1 = make_args(&e1, nullptr, &r32, &u, nullptr, h, cs, 0);
+  const int nt = defect.tiles_x * defect.tiles_y * defect.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  const long long ncyc = (S + m_in - 1) / m_in + 1;  // defect steps at most
+  J3D_TRY(ensure_hist(s, (size_t)ncyc));
+
+  J3D_HIP(hipMemsetAsync(s->ctl, 0, sizeof(Control), st));
+  J3D_TRY(norm_f(f, cd, s, st));
+  int* done = &s->ctl->done;
+
+  const long long points = (long long)u.nx() * u.ny() * u.nz();
+  const long long chunk = chunk_sweeps(points, 12.6, m_in);
+  long long sw = 0, q = 0, since = 0;
+  int slot = 0;
+  bool seen = false;
+  for (;;) {
+    J3D_HIP(launch_pass_one(J3D_F64, F_RES | F_R32, cd, defect, s->partials, done, st));
+    J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + q, &s->ctl->normf, o.rtol, q, done,
+                              &s->ctl->conv_at, &s->ctl->nonfinite, st));
+    if (sw >= S) break;
+    const long long m = std::min(m_in, S - sw);
+    if (m == 1) {
+      J3D_HIP(launch_pass_one(J3D_F32, F_LAST | F_FIRST, cs, first_last, nullptr, done, st));
+    } else {
+      J3D_HIP(launch_pass_one(J3D_F32, F_WRITE | F_FIRST, cs, first, nullptr, done, st));
+      for (long long p = 1; p <= m - 2; ++p)
+        J3D_HIP(launch_pass_one(J3D_F32, F_WRITE, cs, (p & 1) ? mid01 : mid10, nullptr, done, st));
+      J3D_HIP(launch_pass_one(J3D_F32, F_LAST, cs, ((m - 2) & 1) ? last1 : last0, nullptr, done, st));
+    }
+    sw += m;
+    ++q;
+    since += m;
+    if (since >= chunk) {
+      since = 0;
+      J3D_TRY(publish_done(s, slot, st));
+      if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
+      ++slot;
+      if (seen) break;
+    }
+  }
+  Control ctl;
+  J3D_TRY(read_control(s, &ctl, st));
+  long long nh, sweeps;
+  if (ctl.done) {
+    nh = ctl.conv_at + 1;
+    sweeps = std::min(ctl.conv_at * m_in, S);
+  } else {
+    nh = q + 1;
+    sweeps = S;
+  }
+  std::vector<double> hist;
+  J3D_TRY(read_history(s, nh, &hist, st));
+  fill_result(res, sweeps, hist[(size_t)nh - 1], hist, ctl.normf, ctl.done != 0, ctl.nonfinite != 0, o);
+  return ctl.nonfinite ? fail(J3D_ENONFINITE, "residual became non-finite") : J3D_OK;
+}
+
+}  // namespace
+}  // namespace j3d
+
+using namespace j3d;
+
+extern "C" int poisson_solve(const j3d_array* u, const j3d_array* f, double h,
+                             const j3d_solve_opts* opts, j3d_solve_result* result, void* stream) {
+  Field a, b;
+  J3D_TRY(check_field(u, J3D_F64, &a, "u"));
+  J3D_TRY(check_field(f, J3D_F64, &b, "f"));
+  J3D_TRY(check_same_interior(a, b, "u", "f"));
+  J3D_TRY(check_h(h));
+  if (opts == nullptr || result == nullptr) return fail(J3D_EINVAL, "opts/result: null pointer");
+  if (opts->reserved != 0) return fail(J3D_EINVAL, "opts: reserved field must be 0");
+  if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u and f overlap");
+  if (opts->max_sweeps < 0) return fail(J3D_EINVAL, "max_sweeps must be >= 0");
+  if (!(opts->rtol >= 0.0) || !std::isfinite(opts->rtol)) return fail(J3D_EINVAL, "rtol must be finite and >= 0");
+  if (opts->history_cap < 0 || (opts->history_cap > 0 && opts->history == nullptr))
+    return fail(J3D_EINVAL, "history buffer missing");
+  std::memset(result, 0, sizeof(*result));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (opts->mode == J3D_MODE_FP64) {
+    if (opts->check_every < 1) return fail(J3D_EINVAL, "check_every must be >= 1");
+    return solve_fp64(a, b, h, *opts, result, st);
+  }
+  if (opts->mode == J3D_MODE_MIXED) {
+    if (opts->inner_sweeps < 1) return fail(J3D_EINVAL, "inner_sweeps must be >= 1");
+    return solve_mixed(a, b, h, *opts, result, st);
+  }
+  return fail(J3D_EINVAL, "unknown solve mode %d", opts->mode);
+}

@@ -1,0 +1,187 @@
+"""C-ABI checks that need no GPU: symbols, descriptors, validation codes.
+
+Every call here fails validation (or is host-only) before the library
+touches a device, so it runs on a machine without a GPU.
+"""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_2409_18824_amd import j3d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "j3d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for must in ("jacobi3d_sweep", "residual_l2", "poisson_solve", "jacobi3d_sweep_batch",
+                 "poisson_serve_create", "poisson_serve_submit", "poisson_serve_poll",
+                 "poisson_serve_drain", "poisson_serve_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(j3d.LIB_PATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding wraps every one of them under the same name
+    assert set(header_functions()) == set(j3d.EXPORTED)
+
+
+def test_abi_version():
+    assert j3d.abi_version() == 1
+
+
+def fake_desc(nx, ny, nz, dtype=j3d.F64, base=0x10000, lb=(0, 0, 0), ld=None, plane=None):
+    d = j3d.J3DArray()
+    d.base = base
+    d.dtype = dtype
+    d.reserved = 0
+    ex, ey, ez = nx + 2, ny + 2, nz + 2
+    ld = ex if ld is None else ld
+    plane = ld * ey if plane is None else plane
+    for k, (l, e) in enumerate(zip(lb, (ex, ey, ez))):
+        d.lbound[k] = l
+        d.ubound[k] = l + e - 1
+    d.stride[0], d.stride[1], d.stride[2] = 1, ld, plane
+    return d
+
+
+def test_element_offset_matches_paper_example(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "fortran_index.json")))
+    lib = ctypes.CDLL(j3d.LIB_PATH)
+    lib.j3d_element_offset.argtypes = [ctypes.POINTER(j3d.J3DArray), ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    # The paper's 1-D example as a 10 x 1 x 1 array with lbound 1 (extents
+    # padded to 3 on the unused axes, which lbound subtraction ignores).
+    ex = g["paper_example"]
+    d = j3d.J3DArray()
+    d.base, d.dtype, d.reserved = 0x10000, j3d.F64, 0
+    for k, (l, e) in enumerate(((ex["lbound"], ex["extent"]), (1, 3), (1, 3))):
+        d.lbound[k], d.ubound[k] = l, l + e - 1
+    d.stride[0], d.stride[1], d.stride[2] = 1, ex["extent"], 3 * ex["extent"]
+    out = ctypes.c_int64()
+    assert lib.j3d_element_offset(ctypes.byref(d), ex["index"], 1, 1, ctypes.byref(out)) == 0
+    assert out.value == ex["offset"]
+    for c in g["cases_3d"]:
+        d = j3d.J3DArray()
+        d.base, d.dtype, d.reserved = 0x10000, j3d.F64, 0
+        for k in range(3):
+            d.lbound[k] = c["lbound"][k]
+            d.ubound[k] = c["lbound"][k] + 5
+            d.stride[k] = c["stride"][k]
+        d.stride[1] = max(d.stride[1], 6)
+        d.stride[2] = max(d.stride[2], 6 * d.stride[1])
+        want = sum((c["index"][k] - c["lbound"][k]) * d.stride[k] for k in range(3))
+        if d.stride[1] == c["stride"][1] and d.stride[2] == c["stride"][2]:
+            assert want == c["offset"]
+        assert lib.j3d_element_offset(ctypes.byref(d), *c["index"], ctypes.byref(out)) == 0
+        assert out.value == want
+    # outside the bounds
+    assert lib.j3d_element_offset(ctypes.byref(d), 1000, 0, 0, ctypes.byref(out)) == j3d.EINVAL
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda d: setattr(d, "base", None), j3d.EINVAL),
+    (lambda d: setattr(d, "reserved", 1), j3d.EINVAL),
+    (lambda d: setattr(d, "dtype", 7), j3d.EDTYPE),
+    (lambda d: d.stride.__setitem__(0, 2), j3d.EINVAL),
+    (lambda d: d.stride.__setitem__(1, 3), j3d.EINVAL),
+    (lambda d: d.stride.__setitem__(2, 5), j3d.EINVAL),
+    (lambda d: d.ubound.__setitem__(2, d.lbound[2] + 1), j3d.EINVAL),  # no interior on z
+    (lambda d: setattr(d, "base", 0x10003), j3d.EINVAL),              # misaligned
+])
+def test_check_array_rejects(mutate, code):
+    d = fake_desc(4, 5, 6)
+    assert j3d.j3d_check_array(d, j3d.F64) == 0
+    mutate(d)
+    assert j3d.j3d_check_array(d, -1) == code
+
+
+def test_check_array_dtype_and_views():
+    d = fake_desc(4, 5, 6, dtype=j3d.F32)
+    assert j3d.j3d_check_array(d, j3d.F64) == j3d.EDTYPE
+    assert j3d.j3d_check_array(d, j3d.F32) == 0
+    # strided subview: padded leading dimension and plane stride are fine
+    d = fake_desc(4, 5, 6, ld=64, plane=64 * 7 + 3, lb=(-3, 5, 2))
+    assert j3d.j3d_check_array(d, j3d.F64) == 0
+    # offsets beyond 2^31 are rejected
+    d = fake_desc(2000, 2000, 2000)
+    assert j3d.j3d_check_array(d, j3d.F64) == j3d.EINVAL
+
+
+def _call_sweep(a, b, c, h=0.1, flags=0):
+    lib = j3d._lib
+    return lib.jacobi3d_sweep(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), h, flags, None, None)
+
+
+def test_sweep_validation_codes():
+    n = 4
+    span = (n + 2) ** 3 * 8
+    a = fake_desc(n, n, n, base=0x100000)
+    b = fake_desc(n, n, n, base=0x100000 + span)
+    c = fake_desc(n, n, n, base=0x100000 + 2 * span)
+    # overlapping input and output
+    b_alias = fake_desc(n, n, n, base=0x100000 + 8)
+    assert _call_sweep(a, b_alias, c) == j3d.EALIAS
+    assert "overlap" in j3d.last_error()
+    # output overlapping f
+    assert _call_sweep(a, b, fake_desc(n, n, n, base=0x100000 + span + 64)) == j3d.EALIAS
+    # mismatched interiors
+    assert _call_sweep(a, b, fake_desc(n, n, n + 1, base=0x100000 + 2 * span)) == j3d.EINVAL
+    # mixed dtypes
+    assert _call_sweep(a, fake_desc(n, n, n, dtype=j3d.F32, base=0x100000 + span), c) == j3d.EDTYPE
+    # bad h
+    assert _call_sweep(a, b, c, h=0.0) == j3d.EINVAL
+    assert _call_sweep(a, b, c, h=float("nan")) == j3d.EINVAL
+    # unknown flag bits
+    assert _call_sweep(a, b, c, flags=0x80) == j3d.EINVAL
+
+
+def test_solve_and_batch_validation_codes():
+    lib = j3d._lib
+    n = 4
+    span = (n + 2) ** 3 * 8
+    u = fake_desc(n, n, n, base=0x200000)
+    f = fake_desc(n, n, n, base=0x200000 + span)
+    o = j3d.SolveOpts(5, 10, 50, 0, 100, 1e-8, None, 0)
+    r = j3d.SolveResult()
+    assert lib.poisson_solve(ctypes.byref(u), ctypes.byref(f), 0.1, ctypes.byref(o), ctypes.byref(r), None) == j3d.EINVAL
+    o = j3d.SolveOpts(0, 0, 50, 0, 100, 1e-8, None, 0)
+    assert lib.poisson_solve(ctypes.byref(u), ctypes.byref(f), 0.1, ctypes.byref(o), ctypes.byref(r), None) == j3d.EINVAL
+    o = j3d.SolveOpts(0, 10, 50, 0, -1, 1e-8, None, 0)
+    assert lib.poisson_solve(ctypes.byref(u), ctypes.byref(f), 0.1, ctypes.byref(o), ctypes.byref(r), None) == j3d.EINVAL
+    # batch: grid 1's u_b overlaps grid 0's f
+    g = (j3d.Grid * 2)()
+    g[0].u_a, g[0].u_b, g[0].f, g[0].h = fake_desc(n, n, n, base=0x300000), fake_desc(n, n, n, base=0x300000 + span), \
+        fake_desc(n, n, n, base=0x300000 + 2 * span), 0.1
+    g[1].u_a, g[1].u_b, g[1].f, g[1].h = fake_desc(n, n, n, base=0x300000 + 3 * span), \
+        fake_desc(n, n, n, base=0x300000 + 2 * span + 16), fake_desc(n, n, n, base=0x300000 + 5 * span), 0.1
+    assert lib.jacobi3d_sweep_batch(2, g, 10, 1, None, None, None) == j3d.EALIAS
+    # two grids may share one read-only f
+    g[1].u_b = fake_desc(n, n, n, base=0x300000 + 4 * span)
+    g[1].f = g[0].f
+    t = j3d.Tune(3, 32, 0, 0)  # unsupported rows -> rejected before any device work
+    assert lib.jacobi3d_sweep_batch(2, g, 10, 1, None, ctypes.byref(t), None) == j3d.EINVAL
+    assert lib.jacobi3d_sweep_batch(0, g, 10, 1, None, None, None) == j3d.EINVAL
+
+
+def test_tune_list_and_request_bytes():
+    tl = j3d.tune_list()
+    assert len(tl) == 80 and len(set(tl)) == 80
+    assert all(r in (1, 2, 4, 8) and v in (0, 1) and p in (0, 1) for r, _, v, p in tl)
+    # 28 bytes per padded point (u, f FP64; r32, e0, e1 FP32) plus row padding
+    b = j3d.j3d_request_bytes(384, 384, 384)
+    assert 28 * 386 ** 3 <= b <= 1.1 * 28 * 386 ** 3
+    assert j3d.j3d_request_bytes(0, 4, 4) == 0

@@ -1,0 +1,124 @@
+"""GPU parity of poisson_solve (plain FP64 and mixed precision) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import RESID_RTOL, needs_gpu, rel, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+from paper_2409_18824_amd import j3d  # noqa: E402
+
+
+def test_small_plain_100_sweeps_residual_every_sweep():
+    """64^3 FP64, u0 ~ U[0,1), f ~ U[-1,1), h = 1/65: 100 sweeps, residual after each."""
+    say("64^3 x 100 sweeps")
+    u0, f, h = synth.small_plain(64, seed=1)
+    du = j3d.FArray.from_numpy(u0)
+    df = j3d.FArray.from_numpy(f)
+    res = j3d.poisson_solve(du, df, h, mode=j3d.MODE_FP64, rtol=0.0, max_sweeps=100, check_every=1)
+    uo, ro = oracle.solve_plain(u0, f, h, rtol=0.0, check_every=1, max_sweeps=100)
+    assert res.sweeps == ro.sweeps == 100 and not res.converged
+    assert len(res.history) == len(ro.history) == 101
+    worst = max(rel(a, b) for a, b in zip(res.history, ro.history))
+    say("worst residual rel err", worst)
+    assert worst <= RESID_RTOL
+    assert rel(res.norm_f, ro.norm_f) <= RESID_RTOL
+    assert np.array_equal(du.to_numpy(), uo)
+
+
+@pytest.mark.parametrize("max_sweeps,check_every", [(0, 1), (7, 3), (10, 5), (1, 1)])
+def test_plain_cadence_edges(max_sweeps, check_every):
+    n = (9, 11, 6)
+    say("cadence", max_sweeps, check_every)
+    u0 = synth.uniform_field(*n, 4, 1, 0, 1)
+    f = synth.uniform_field(*n, 4, 2, -1, 1)
+    h = 0.1
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    res = j3d.poisson_solve(du, df, h, rtol=0.0, max_sweeps=max_sweeps, check_every=check_every)
+    uo, ro = oracle.solve_plain(u0, f, h, rtol=0.0, check_every=check_every, max_sweeps=max_sweeps)
+    assert res.sweeps == ro.sweeps
+    assert len(res.history) == len(ro.history)
+    assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
+    assert rel(res.resid, ro.resid) <= RESID_RTOL
+    assert np.array_equal(du.to_numpy(), uo)
+
+
+def test_plain_early_exit_matches_oracle():
+    n = 20
+    say("plain early exit")
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 2, 1, 0, 1)
+    f = synth.manufactured_f(n, n, n, h)
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    res = j3d.poisson_solve(du, df, h, rtol=1e-6, max_sweeps=100000, check_every=10)
+    uo, ro = oracle.solve_plain(u0, f, h, rtol=1e-6, check_every=10, max_sweeps=100000)
+    assert ro.converged and res.converged
+    assert res.sweeps == ro.sweeps
+    assert rel(res.resid, ro.resid) <= RESID_RTOL and res.resid <= 1e-6 * res.norm_f
+    assert np.array_equal(du.to_numpy(), uo)
+
+
+@pytest.mark.parametrize("n,inner,rtol,cap", [(24, 50, 1e-8, 100000), (13, 7, 1e-10, 100000),
+                                              (16, 50, 1e-14, 120), (10, 1, 1e-3, 1000)])
+def test_mixed_matches_oracle(n, inner, rtol, cap):
+    say("mixed", n, inner, rtol, cap)
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 2, 1, 0, 1)
+    f = synth.manufactured_f(n, n, n, h)
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    res = j3d.poisson_solve(du, df, h, mode=j3d.MODE_MIXED, rtol=rtol, max_sweeps=cap, inner_sweeps=inner)
+    uo, ro = oracle.solve_mixed(u0, f, h, rtol=rtol, inner=inner, max_sweeps=cap)
+    assert res.converged == ro.converged
+    assert res.sweeps == ro.sweeps
+    assert len(res.history) == len(ro.history)
+    assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
+    # FP32 sweeps, FP64 defects, same order on both sides: the fields agree bitwise
+    assert np.array_equal(du.to_numpy(), uo)
+
+
+def test_mixed_and_plain_reach_tolerance_at_same_sweep_count():
+    n = 24
+    say("mixed vs plain sweep count")
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 2, 1, 0, 1)
+    f = synth.manufactured_f(n, n, n, h)
+    a, b = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(u0)
+    df = j3d.FArray.from_numpy(f)
+    rp = j3d.poisson_solve(a, df, h, mode=j3d.MODE_FP64, rtol=1e-8, max_sweeps=10 ** 6, check_every=50)
+    rm = j3d.poisson_solve(b, df, h, mode=j3d.MODE_MIXED, rtol=1e-8, max_sweeps=10 ** 6, inner_sweeps=50)
+    assert rp.converged and rm.converged and rp.sweeps == rm.sweeps
+    # the converged fields agree to the tolerance's order
+    ua, ub = a.to_numpy(), b.to_numpy()
+    assert np.max(np.abs(ua - ub)) <= 1e-7 * np.max(np.abs(ua))
+    # both residuals verified on the CPU
+    assert oracle.residual_l2(ub, f, h) <= 1e-8 * rm.norm_f * (1 + 1e-9)
+
+
+def test_nonfinite_reported():
+    n = 8
+    u0 = np.zeros((n + 2,) * 3)
+    f = synth.uniform_field(n, n, n, 3, 2, -1, 1)
+    f[4, 4, 4] = np.nan
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    with pytest.raises(j3d.J3DError) as ei:
+        j3d.poisson_solve(du, df, 0.1, rtol=1e-8, max_sweeps=50, check_every=5)
+    assert ei.value.code == j3d.ENONFINITE
+    r = j3d.poisson_solve(du, df, 0.1, mode=j3d.MODE_MIXED, rtol=1e-8, max_sweeps=50, raise_nonfinite=False)
+    assert r.status == j3d.ENONFINITE and not r.converged
+
+
+def test_warm_start_resume():
+    """Solving in two halves from the returned iterate equals one solve."""
+    n = 12
+    h = 1.0 / 13
+    u0 = synth.uniform_field(n, n, n, 6, 1, 0, 1)
+    f = synth.uniform_field(n, n, n, 6, 2, -1, 1)
+    a, b = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(u0)
+    df = j3d.FArray.from_numpy(f)
+    j3d.poisson_solve(a, df, h, rtol=0.0, max_sweeps=60, check_every=10)
+    j3d.poisson_solve(b, df, h, rtol=0.0, max_sweeps=30, check_every=10)
+    j3d.poisson_solve(b, df, h, rtol=0.0, max_sweeps=30, check_every=10)
+    assert np.array_equal(a.to_numpy(), b.to_numpy())

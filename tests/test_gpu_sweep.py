@@ -1,0 +1,147 @@
+"""GPU parity of the sweep, the fused and standalone residual, and fills.
+
+Every case runs the HIP path through the C ABI and compares it with the CPU
+oracle on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import RESID_RTOL, assert_sweep_close, needs_gpu, rel, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+from paper_2409_18824_amd import j3d  # noqa: E402
+
+SHAPES = [(1, 1, 1), (4, 4, 4), (3, 4, 5), (17, 9, 33), (64, 64, 64), (130, 67, 45), (65, 3, 70)]
+TUNES = [(1, 8, 0, 0), (2, 16, 1, 0), (4, 32, 0, 0), (4, 32, 1, 1), (8, 64, 0, 1), (8, 128, 1, 0)]
+
+
+def make_inputs(nx, ny, nz, seed=1):
+    h = 1.0 / (max(nx, ny, nz) + 1)
+    u = synth.uniform_field(nx, ny, nz, seed, synth.STREAM_U0, 0.0, 1.0)
+    f = synth.uniform_field(nx, ny, nz, seed, synth.STREAM_F, -1.0, 1.0)
+    # non-zero Dirichlet data in the halo exercises boundary reads
+    halo = synth.uniform(seed, 9, np.arange(u.size, dtype=np.uint64), -0.5, 0.5).reshape(u.shape)
+    mask = np.ones(u.shape, dtype=bool)
+    mask[1:-1, 1:-1, 1:-1] = False
+    u[mask] = halo[mask]
+    return u, f, h
+
+
+def test_fill_uniform_matches_generator():
+    for (nx, ny, nz) in [(17, 9, 33), (64, 64, 64), (1, 1, 1)]:
+        say("fill", nx, ny, nz)
+        a = j3d.FArray.empty(nx, ny, nz, lbound=(1, -2, 3))
+        j3d.j3d_fill_uniform(a, 1234, synth.STREAM_F, -1.0, 1.0, halo=0.25)
+        torch.cuda.synchronize()
+        want = synth.uniform_field(nx, ny, nz, 1234, synth.STREAM_F, -1.0, 1.0, halo=0.25)
+        assert np.array_equal(a.to_numpy(), want)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("tune", TUNES)
+def test_sweep_fp64_parity(shape, tune):
+    nx, ny, nz = shape
+    say("sweep fp64", shape, tune)
+    u, f, h = make_inputs(nx, ny, nz)
+    j3d.j3d_tune_set_single(j3d.F64, nx, ny, nz, tune)
+    du = j3d.FArray.from_numpy(u)
+    dv = j3d.FArray.from_numpy(np.zeros_like(u))
+    dv.copy_from(u)  # same halo in both ping-pong arrays
+    dv.view()[1:-1, 1:-1, 1:-1] = -7.0  # interior must be overwritten
+    df = j3d.FArray.from_numpy(f)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    got = dv.to_numpy()
+    want = oracle.sweep(u, f, h)
+    ndiff = assert_sweep_close(got, want, u, f, h)
+    assert ndiff == 0, "expected bitwise equality (same order, no contraction)"
+    # halo untouched
+    assert np.array_equal(got[0], u[0]) and np.array_equal(got[:, :, -1], u[:, :, -1])
+    # fused residual of the input iterate
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+    # standalone residual with the same tile shape: identical reduction order
+    assert j3d.residual_l2(du, df, h) == float(r.item())
+
+
+@pytest.mark.parametrize("tune", [(1, 8, 0, 0), (4, 32, 1, 0), (8, 16, 0, 1)])
+def test_sweep_fp32_parity(tune):
+    nx, ny, nz = 70, 13, 21
+    say("sweep fp32", tune)
+    e = synth.uniform_field(nx, ny, nz, 5, 1, -1, 1).astype(np.float32)
+    r32 = synth.uniform_field(nx, ny, nz, 5, 2, -1, 1).astype(np.float32)
+    h2 = np.float32((1.0 / 71) ** 2)
+    j3d.j3d_tune_set_single(j3d.F32, nx, ny, nz, tune)
+    de = j3d.FArray.from_numpy(e, dtype=j3d.F32)
+    do = j3d.FArray.from_numpy(e, dtype=j3d.F32)
+    dr = j3d.FArray.from_numpy(r32, dtype=j3d.F32)
+    j3d.jacobi3d_sweep(de, do, dr, 1.0 / 71)
+    torch.cuda.synchronize()
+    got = do.to_numpy()
+    want = oracle.sweep_f32(e, r32, h2)
+    assert got.dtype == np.float32
+    # same order, correctly rounded FP32 division, no contraction: bitwise
+    assert np.array_equal(got, want)
+
+
+def test_fp32_fused_residual_rejected():
+    a = j3d.FArray.empty(4, 4, 4, dtype=j3d.F32)
+    b = j3d.FArray.empty(4, 4, 4, dtype=j3d.F32)
+    c = j3d.FArray.empty(4, 4, 4, dtype=j3d.F32)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(j3d.J3DError) as ei:
+        j3d.jacobi3d_sweep(a, b, c, 0.1, resid_out=r)
+    assert ei.value.code == j3d.EDTYPE
+
+
+def test_strided_views_and_lbounds():
+    nx, ny, nz = 33, 18, 12
+    say("strided views")
+    u, f, h = make_inputs(nx, ny, nz, seed=3)
+    want = oracle.sweep(u, f, h)
+    j3d.j3d_tune_set_single(j3d.F64, nx, ny, nz, (4, 8, 1, 0))
+    du = j3d.FArray.from_numpy(u, lbound=(-3, 5, 2), ld_extra=7, plane_extra=5)
+    dv = j3d.FArray.from_numpy(u, lbound=(1, 1, 1), align_bytes=8)
+    df = j3d.FArray.from_numpy(f, lbound=(0, 0, 0), ld_extra=1, plane_extra=123)
+    assert du.stride[1] != dv.stride[1] != df.stride[1]
+    j3d.jacobi3d_sweep(du, dv, df, h)
+    torch.cuda.synchronize()
+    assert np.array_equal(dv.to_numpy(), want)
+    # element addressing through the descriptor (lbound subtraction)
+    assert j3d.j3d_element_offset(du, -3, 5, 2) == 0
+    assert j3d.j3d_element_offset(du, -2, 6, 3) == 1 + du.stride[1] + du.stride[2]
+
+
+def test_full_size_sweep_512():
+    """The bench's grid (512^3, FP64) in the bench's launch configuration."""
+    n = 512
+    say("512^3 sweep + fused residual")
+    h = 1.0 / (n + 1)
+    f = synth.manufactured_f(n, n, n, h)
+    du = j3d.FArray.empty(n, n, n)
+    j3d.j3d_fill_uniform(du, 2, synth.STREAM_U0, 0.0, 1.0)
+    dv = j3d.FArray.empty(n, n, n)
+    df = j3d.FArray.from_numpy(f)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    u = du.to_numpy()
+    assert np.array_equal(u, synth.uniform_field(n, n, n, 2, synth.STREAM_U0, 0.0, 1.0)[:, :, :])
+    want = oracle.sweep(u, f, h)
+    got = dv.to_numpy()
+    assert np.array_equal(got[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1])
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+
+
+def test_bandwidth_probe_sane():
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = j3d.j3d_bandwidth_probe(a, b, reps=5)
+    say("copy GB/s", g)
+    assert torch.equal(a, b)
+    assert 500.0 < g < 8000.0 * 1.05
