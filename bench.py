@@ -55,7 +55,7 @@ def measured_traffic(kernel_hash: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(n: int, h: float, budget_s: float = 12.0):
+def cpu_baseline(n: int, h: float, budget_s: float = 10.0):
     """Time the oracle on a bounded sample: sweeps of the same 512^3 grid with
     the same residual cadence (a residual pass before sweep 0 and every 10th)."""
     import numpy as np
@@ -74,7 +74,7 @@ def cpu_baseline(n: int, h: float, budget_s: float = 12.0):
         a, b = b, a
         sweeps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or sweeps >= 20:
+        if el >= budget_s or sweeps >= 500:
             break
     glups = sweeps * n ** 3 / el / 1e9
     del u0, f, a, b
@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--resid-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="also time the copy kernel on 2 x 1 GiB (achievable-bandwidth ceiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -124,12 +126,14 @@ def main():
     nres = S // E + 1
     resid = torch.zeros(nres, dtype=torch.float64, device="cuda")
     n_plain = sum(1 for s in range(S) if s % E != 0)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_plain)]
+    events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(n_plain)] for _ in range(args.steps)]
 
     state = {"cur": ua, "nxt": ub}
 
-    def step(timed: bool):
+    def step(ev):
         cur, nxt = state["cur"], state["nxt"]
+        timed = ev is not None
         q = 0
         for s in range(S):
             if s % E == 0:
@@ -147,7 +151,7 @@ def main():
         state["cur"], state["nxt"] = cur, nxt
 
     for w in range(args.warmup):
-        step(False)
+        step(None)
         torch.cuda.synchronize()
         print("[bench] warmup %d done" % w, file=sys.stderr, flush=True)
 
@@ -158,15 +162,13 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for k in range(args.steps):
-        step(True)
-        # event pairs are reused by the next step: read them now (the region
-        # stays stream-ordered; this only waits for the host)
-        ev[-1][1].synchronize()
-        kernel_ms.extend(a.elapsed_time(b) for a, b in ev)
-        print("[bench] step %d done" % k, file=sys.stderr, flush=True)
+        step(events[k])
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    for ev in events:
+        kernel_ms.extend(a.elapsed_time(b) for a, b in ev)
+    print("[bench] %d timed steps done" % args.steps, file=sys.stderr, flush=True)
     gpu_s = e0.elapsed_time(e1) / 1e3
     elapsed = max(wall, gpu_s)
     lups = float(n) ** 3 * S * args.steps
@@ -181,6 +183,16 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash),
             "kernel": "k_pass_one<double, F_WRITE> (FP64 sweep)", "avg_launch_us": round(avg_ms * 1e3, 2),
             "launches": len(kernel_ms), "bytes_per_launch_algorithmic": int(BYTES_PER_LUP_F64 * n ** 3)}
+
+    probe = None
+    if args.probe:
+        nprobe = 1 << 27  # 1 GiB of doubles per buffer
+        src = torch.ones(nprobe, dtype=torch.float64, device="cuda")
+        dst = torch.zeros(nprobe, dtype=torch.float64, device="cuda")
+        probe = {"copy_gbps": round(j3d.j3d_bandwidth_probe(src, dst, reps=5), 1), "bytes_per_launch": 2 * 8 * nprobe}
+        roof["copy_ceiling_gbps"] = probe["copy_gbps"]
+        roof["frac_of_copy_ceiling"] = round(achieved / probe["copy_gbps"], 4)
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

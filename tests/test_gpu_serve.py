@@ -79,10 +79,10 @@ def test_budget_admission_and_rejection():
 
 def test_continuous_batching_late_arrivals_join():
     """Requests arriving while others run are admitted at cycle boundaries."""
-    reqs = [(48, 1e-12, 2000, 40, False)] + [(12, 1e-8, 5000, 41 + k, False) for k in range(4)]
+    reqs = [(160, 1e-14, 20000, 40, False)] + [(12, 1e-8, 5000, 41 + k, False) for k in range(4)]
     say("late arrivals")
     with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=8, cycle_sweeps=50) as s:
-        res, _ = run(s, reqs, gaps=0.02)
+        res, _ = run(s, reqs, gaps=0.005)
     long = res[0]
     for k in range(1, 5):
         # each short request was admitted and finished while the long one was still running
