@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--resid-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tile", default=None,
+                    help="pin the tile shape as rows,planes,variant,persistent instead of autotuning")
     ap.add_argument("--probe", action="store_true",
                     help="also time the copy kernel on 2 x 1 GiB (achievable-bandwidth ceiling)")
     args = ap.parse_args()
@@ -117,7 +119,10 @@ def main():
     j3d.j3d_fill_const(ub, 0.0)
     df = j3d.FArray.from_numpy(synth.manufactured_f(n, n, n, h))
     torch.cuda.synchronize()
-    if args.no_tune:
+    if args.tile:
+        tune = tuple(int(x) for x in args.tile.split(","))
+        j3d.j3d_tune_set_single(j3d.F64, n, n, n, tune)
+    elif args.no_tune:
         tune = None
     else:
         tune = j3d.j3d_autotune_single(j3d.F64, n, n, n)

@@ -199,9 +199,14 @@ typedef struct j3d_grid {
  * Tile shape of the sweep kernels.  A workgroup sweeps 64 x-points (one
  * 64-lane wavefront per row) x `rows` y-rows x `planes` z-planes, marching
  * through z with the previous, current and next plane in registers.
- * variant 0 reads x/y neighbours through the cache, variant 1 stages each
- * plane in LDS.  persistent = 1 launches a fixed grid of workgroups that
- * stride over the tile list; 0 launches one workgroup per tile.
+ * variant is a bit set: 1 stages each plane in LDS (else x/y neighbours are
+ * read through the cache); 2 and 16 give each thread 2^(bit 2 + 2 x bit 16)
+ * consecutive rows (register blocking in y: the tile then has rows x that
+ * many y-rows); 4 writes outputs with nontemporal stores; 8 keeps the
+ * launch's workgroup order (else each of the 8 XCDs receives one contiguous
+ * block of tiles).  persistent = 1 launches a fixed
+ * grid of workgroups that stride over the tile list; 0 launches one
+ * workgroup per tile.
  * The supported combinations are listed by j3d_tune_list().
  */
 typedef struct j3d_tune {

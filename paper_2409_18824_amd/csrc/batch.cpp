@@ -17,6 +17,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "runtime.h"
@@ -296,39 +297,74 @@ std::vector<TileCfg> candidates() {
   return v;
 }
 
-// Time F_WRITE passes for every candidate on the given single-grid or batch
-// arguments and return the fastest.  `fill` builds the launch for a cfg.
-template <typename BuildAndLaunch>
-int time_candidates(hipStream_t st, TileCfg* best, BuildAndLaunch&& launch) {
+// Time F_WRITE passes of tile shapes and return the fastest.  The search is
+// staged rather than exhaustive: rows x planes with the plain variant, then
+// every variant and persistence setting at the best rows x planes, then rows x
+// planes again at the best variant.  `launch` enqueues one pass for a shape.
+template <typename Launcher>
+int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
   hipEvent_t e0, e1;
   J3D_HIP(hipEventCreate(&e0));
   J3D_HIP(hipEventCreate(&e1));
-  float best_ms = 1e30f;
+  std::map<std::tuple<int, int, int, int>, float> seen;
   int rc = J3D_OK;
-  for (const TileCfg& c : candidates()) {
-    rc = launch(c);  // warm-up (also builds tables)
-    if (rc != J3D_OK) break;
+  auto time_of = [&](const TileCfg& c, float* out) -> int {
+    auto key = std::make_tuple(c.rows, c.planes, c.variant, c.persistent);
+    auto it = seen.find(key);
+    if (it != seen.end()) {
+      *out = it->second;
+      return J3D_OK;
+    }
+    J3D_TRY(launch(c));  // warm-up (also builds tables)
     float ms_min = 1e30f;
-    for (int r = 0; r < 3 && rc == J3D_OK; ++r) {
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(J3D_EHIP, "event record"); break; }
-      rc = launch(c);
-      if (rc != J3D_OK) break;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        rc = fail(J3D_EHIP, "event sync");
-        break;
-      }
+    for (int r = 0; r < 3; ++r) {
+      J3D_HIP(hipEventRecord(e0, st));
+      J3D_TRY(launch(c));
+      J3D_HIP(hipEventRecord(e1, st));
+      J3D_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
+      J3D_HIP(hipEventElapsedTime(&ms, e0, e1));
       ms_min = std::min(ms_min, ms);
     }
-    if (rc != J3D_OK) break;
-    if (ms_min < best_ms) {
-      best_ms = ms_min;
-      *best = c;
+    seen[key] = ms_min;
+    *out = ms_min;
+    return J3D_OK;
+  };
+  const std::vector<TileCfg> all = candidates();
+  std::vector<int> rows_set, planes_set, var_set;
+  for (const TileCfg& c : all) {
+    if (std::find(rows_set.begin(), rows_set.end(), c.rows) == rows_set.end()) rows_set.push_back(c.rows);
+    if (std::find(planes_set.begin(), planes_set.end(), c.planes) == planes_set.end())
+      planes_set.push_back(c.planes);
+    if (std::find(var_set.begin(), var_set.end(), c.variant) == var_set.end()) var_set.push_back(c.variant);
+  }
+  TileCfg b{4, 32, 0, 0};
+  float bt = 1e30f;
+  auto consider = [&](const TileCfg& c) -> int {
+    float t = 0.f;
+    J3D_TRY(time_of(c, &t));
+    if (t < bt) {
+      bt = t;
+      b = c;
+    }
+    return J3D_OK;
+  };
+  for (int stage = 0; stage < 3 && rc == J3D_OK; ++stage) {
+    const TileCfg base = b;
+    if (stage == 1) {
+      for (int v : var_set)
+        for (int p = 0; p < 2 && rc == J3D_OK; ++p) rc = consider(TileCfg{base.rows, base.planes, v, p});
+    } else {
+      for (int r : rows_set)
+        for (int pl : planes_set) {
+          if (rc != J3D_OK) break;
+          rc = consider(TileCfg{r, pl, stage == 0 ? 0 : base.variant, stage == 0 ? 0 : base.persistent});
+        }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc == J3D_OK) *best = b;
   return rc;
 }
 

@@ -13,17 +13,19 @@ bool tune_cache_lookup_single(int dtype, int nx, int ny, int nz, TileCfg* out);
 
 namespace {
 const int kRows[] = {1, 2, 4, 8};
-const int kPlanes[] = {8, 16, 32, 64, 128};
-constexpr int kNumTunes = 4 * 5 * 2 * 2;
+const int kPlanes[] = {1, 2, 4, 8, 16, 32, 64, 128};
+constexpr int kNumPlanes = 8;
+constexpr int kNumVariants = 32;
+constexpr int kNumTunes = 4 * kNumPlanes * kNumVariants * 2;
 
 TileCfg tune_at(int idx) {
   TileCfg c;
   c.persistent = idx % 2;
   idx /= 2;
-  c.variant = idx % 2;
-  idx /= 2;
-  c.planes = kPlanes[idx % 5];
-  idx /= 5;
+  c.variant = idx % kNumVariants;
+  idx /= kNumVariants;
+  c.planes = kPlanes[idx % kNumPlanes];
+  idx /= kNumPlanes;
   c.rows = kRows[idx % 4];
   return c;
 }

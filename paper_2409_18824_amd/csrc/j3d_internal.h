@@ -29,7 +29,7 @@ struct GridArgs {
   int id;           // index of this grid's flags and norms in per-grid arrays
   double h2;        // h*h in FP64
   float h2f;        // (float)(h*h)
-  float pad2_;
+  int order;        // 0: XCD-blocked dispatch order, 1: dispatch order as launched
 };
 
 // Kernel pass flags (compile-time).
@@ -45,7 +45,8 @@ enum : unsigned {
 struct TileCfg {
   int rows;       // y-rows per workgroup = wavefronts per workgroup
   int planes;     // z-planes per tile
-  int variant;    // 0: neighbours through the cache, 1: plane staged in LDS
+  int variant;    // bit set: 1 LDS plane, 2 prefetch, 4 nontemporal stores,
+                  // 8 keep the launch's dispatch order (no XCD blocking)
   int persistent; // 1: fixed grid striding over tiles
 };
 

@@ -127,6 +127,7 @@ GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* 
   g.planes = c.planes;
   g.h2 = h * h;
   g.h2f = static_cast<float>(h * h);
+  g.order = (c.variant & 8) ? 1 : 0;
   return g;
 }
 

@@ -1,0 +1,363 @@
+// The z-marching tile kernel shared by every sweep-shaped pass of libj3d
+// (FP64 sweep, fused residual, defect residual, FP32 correction sweeps,
+// norms), its single-grid and batched entry points, and the launch
+// templates.  Included by kernels_f64.hip and kernels_f32.hip, which
+// instantiate it for their element type.
+//
+// Memory layout: Fortran column-major arrays with a one-cell halo; x is the
+// unit-stride axis.  A workgroup owns a tile of 64 x-points (one 64-lane
+// wavefront per row) by BY y-rows by `planes` z-planes and marches through
+// z, keeping the previous, current and next value of its column in
+// registers, so every plane of u and f is fetched from HBM once per tile.
+// The sweep streams about 24 bytes per FP64 point update and does 8 flops,
+// far below the ridge of the FP64 VALU: it is HBM-bound and there is no dense
+// contraction, hence no MFMA.
+//
+// VAR selects how the tile is fed (bits may be combined):
+//   1  the current plane is staged in LDS with its x/y halo ring
+//      (double-buffered, one barrier per plane); otherwise x and y
+//      neighbours are read through the vector L1/L2 caches;
+//   2, 16  each thread owns 2^(bit2 + 2*bit16) consecutive rows (1, 2, 4 or
+//      8): register blocking in y, which multiplies the independent HBM
+//      loads each wavefront has in flight per plane;
+//   4  outputs are written with nontemporal stores (streamed past L2).
+// Variant bit 8 (a run-time choice, not a template parameter) keeps the
+// launch's workgroup order instead of giving each XCD a contiguous block.
+//
+// Arithmetic order is fixed and the library is built with contraction off:
+//   S  = ((((u[i-1] + u[i+1]) + u[j-1]) + u[j+1]) + u[k-1]) + u[k+1]
+//   u' = (S + h2 * f) / 6                  (true IEEE division)
+//   r  = f - (6 * u - S) / h2              (FP64)
+// A tile's sum of r^2 is reduced by a fixed butterfly within the wavefront
+// and in wave order across wavefronts into one fixed slot per tile.
+#pragma once
+
+#include "j3d_internal.h"
+
+namespace j3d {
+namespace sweep_detail {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Map dispatch order to logical tile order so that each XCD receives
+// one contiguous block of tiles: neighbouring tiles then share halo rows in
+// the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, idx = b >> 3;
+  return x * q + min(x, r) + idx;
+}
+
+template <typename T>
+__device__ __forceinline__ T h2_of(const GridArgs& g);
+template <>
+__device__ __forceinline__ double h2_of<double>(const GridArgs& g) { return g.h2; }
+template <>
+__device__ __forceinline__ float h2_of<float>(const GridArgs& g) { return g.h2f; }
+
+template <typename T, bool NT>
+__device__ __forceinline__ void put(T* p, T v) {
+  if (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Rows per thread encoded in the variant bits 2 and 16.
+constexpr int rows_per_thread(int var) { return 1 << (((var >> 1) & 1) + 2 * ((var >> 4) & 1)); }
+
+// Shared memory of a workgroup: the double-buffered plane with its x/y halo
+// ring (LDS variants only; one element otherwise) and one partial sum per
+// wavefront.
+template <typename T, int BY, int VAR>
+struct Smem {
+  static constexpr bool LDS = (VAR & 1) != 0;
+  static constexpr int TR = BY * rows_per_thread(VAR);
+  T pl[LDS ? 2 : 1][LDS ? TR + 2 : 1][LDS ? WAVE + 2 : 1];
+  double red[BY];
+};
+
+// One tile: local tile index t of grid g.  Writes the tile's partial sum
+// (F_RES / F_NORM) to partials[g.tile0 + t].
+//
+// Each thread owns RY consecutive rows of its column (register blocking in
+// y as well as z): per plane it issues the 2*RY HBM loads of its rows at
+// once, and the y-neighbours inside its block come from registers.  Every
+// lane loads from in-bounds addresses (lanes and rows past the interior are
+// clamped onto the last interior column/row), so loads need no per-lane
+// branches; only stores and sums are masked.
+template <typename T, int BY, int VAR, unsigned FL>
+__device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __restrict__ partials,
+                                           Smem<T, BY, VAR>& sm) {
+  constexpr bool STENCIL = !(FL & (F_FIRST | F_NORM));
+  constexpr bool USE_LDS = (VAR & 1) && STENCIL;
+  constexpr int RY = rows_per_thread(VAR);
+  constexpr int TR = BY * RY;  // rows per tile
+  constexpr bool NT = (VAR & 4) != 0;
+  const int lane = threadIdx.x;
+  const int wy = threadIdx.y;
+  const int tx = t % g.tiles_x;
+  const int t2 = t / g.tiles_x;
+  const int ty = t2 % g.tiles_y;
+  const int tz = t2 / g.tiles_y;
+  const int i = 1 + tx * WAVE + lane;
+  const int jb = 1 + ty * TR + wy * RY;  // first row of this thread
+  const int k0 = 1 + tz * g.planes;
+  const int k1 = min(k0 + g.planes, g.nz + 1);
+  const bool ix = i <= g.nx;
+  const int ic = min(i, g.nx);
+  const int jc = min(jb, g.ny);
+
+  // Row r of the block is row jb + r, clamped; dj[r] is its offset in rows
+  // from row jc (uniform across the wavefront).
+  int dj[RY];
+  bool act[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    dj[r] = min(jb + r, g.ny) - jc;
+    act[r] = ix && (jb + r <= g.ny);
+  }
+
+  const T* __restrict__ pu = static_cast<const T*>(g.u) + (ic + g.su_y * jc + g.su_z * k0);
+  const T* __restrict__ pf = static_cast<const T*>(g.f) + (ic + g.sf_y * jc + g.sf_z * k0);
+  T* __restrict__ po = static_cast<T*>(g.o) + (ic + g.so_y * jc + g.so_z * k0);
+  float* __restrict__ pr = g.r32 + (ic + g.sr_y * jc + g.sr_z * k0);
+  double* __restrict__ p64 = g.u64 + (ic + g.s64_y * jc + g.s64_z * k0);
+  const T h2 = h2_of<T>(g);
+
+  double acc = 0.0;
+  T um[RY], uc[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    um[r] = T(0);
+    uc[r] = T(0);
+    if (STENCIL) {
+      um[r] = pu[dj[r] * g.su_y - g.su_z];
+      uc[r] = pu[dj[r] * g.su_y];
+    }
+  }
+
+  for (int k = k0; k < k1; ++k) {
+    T fc[RY], up[RY], xm[RY], xp[RY], ym[RY], yp[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const T* u_r = pu + dj[r] * g.su_y;
+      fc[r] = pf[dj[r] * g.sf_y];
+      up[r] = STENCIL ? u_r[g.su_z] : T(0);
+      xm[r] = xp[r] = ym[r] = yp[r] = T(0);
+      if (STENCIL && !USE_LDS) {
+        xm[r] = u_r[-1];
+        xp[r] = u_r[1];
+        // y-neighbours: registers inside the block, loads at its edges and
+        // where the next row is the halo.
+        ym[r] = (r == 0) ? u_r[-g.su_y] : uc[r - 1];
+        yp[r] = (r + 1 < RY && jb + r < g.ny) ? uc[r + 1] : u_r[g.su_y];
+      }
+    }
+    if (USE_LDS) {
+      auto& pl = sm.pl[(k - k0) & 1];
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        if (act[r]) {
+          const T* u_r = pu + dj[r] * g.su_y;
+          const int row = wy * RY + r + 1;
+          pl[row][lane + 1] = uc[r];
+          if (lane == 0) pl[row][0] = u_r[-1];
+          if (lane == WAVE - 1 || i == g.nx) pl[row][lane + 2] = u_r[1];
+          if (row == 1) pl[0][lane + 1] = u_r[-g.su_y];
+          if (row == TR || jb + r == g.ny) pl[row + 1][lane + 1] = u_r[g.su_y];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const int row = wy * RY + r + 1;
+        xm[r] = pl[row][lane];
+        xp[r] = pl[row][lane + 2];
+        ym[r] = pl[row - 1][lane + 1];
+        yp[r] = pl[row + 1][lane + 1];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      T s = T(0);
+      if (STENCIL) {
+        s = xm[r] + xp[r];
+        s = s + ym[r];
+        s = s + yp[r];
+        s = s + um[r];
+        s = s + up[r];
+      }
+      if (FL & F_NORM) {
+        const double v = static_cast<double>(fc[r]) * static_cast<double>(fc[r]);
+        acc += act[r] ? v : 0.0;
+      } else {
+        if (STENCIL && (FL & (F_RES | F_R32))) {
+          const double res = static_cast<double>(fc[r]) -
+                             (6.0 * static_cast<double>(uc[r]) - static_cast<double>(s)) / g.h2;
+          if (FL & F_RES) acc += act[r] ? res * res : 0.0;
+          if ((FL & F_R32) && act[r]) put<float, NT>(pr + dj[r] * g.sr_y, static_cast<float>(res));
+        }
+        if (FL & (F_WRITE | F_LAST)) {
+          const T v = (s + h2 * fc[r]) / T(6);
+          if ((FL & F_WRITE) && act[r]) put<T, NT>(po + dj[r] * g.so_y, v);
+          if ((FL & F_LAST) && act[r]) {
+            double* q = p64 + dj[r] * g.s64_y;
+            q[0] = q[0] + static_cast<double>(v);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      um[r] = uc[r];
+      uc[r] = up[r];
+    }
+    pu += g.su_z;
+    pf += g.sf_z;
+    po += g.so_z;
+    pr += g.sr_z;
+    p64 += g.s64_z;
+  }
+
+  if (FL & (F_RES | F_NORM)) {
+    const double v = wave_sum(acc);
+    if (lane == 0) sm.red[wy] = v;
+    __syncthreads();
+    if (wy == 0 && lane == 0) {
+      double tot = 0.0;
+#pragma unroll
+      for (int q = 0; q < BY; ++q) tot += sm.red[q];
+      partials[g.tile0 + t] = tot;
+    }
+  }
+  // The next tile of a persistent workgroup reuses the shared buffers.
+  __syncthreads();
+}
+
+template <typename T, int BY, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * BY)
+    k_pass_one(GridArgs g, double* __restrict__ partials, const int* __restrict__ done) {
+  if (done != nullptr && *done != 0) return;
+  __shared__ Smem<T, BY, VAR> sm;
+  const int ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
+  const int first = g.order ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+  for (int t = first; t < ntiles; t += gridDim.x) sweep_tile<T, BY, VAR, FL>(g, t, partials, sm);
+}
+
+template <typename T, int BY, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * BY)
+    k_pass_batch(const GridArgs* __restrict__ table, int ngrids, int ntiles,
+                 double* __restrict__ partials, const int* __restrict__ done, int order) {
+  __shared__ Smem<T, BY, VAR> sm;
+  const int first = order ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+  for (int t = first; t < ntiles; t += gridDim.x) {
+    int lo = 0, hi = ngrids - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (table[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    if (done != nullptr && done[table[lo].id] != 0) continue;
+    const GridArgs g = table[lo];
+    sweep_tile<T, BY, VAR, FL>(g, t - g.tile0, partials, sm);
+  }
+}
+
+// ---------------------------------------------------------------------
+// Host-side launch templates
+// ---------------------------------------------------------------------
+
+int device_cus();
+
+template <typename K>
+int resident_blocks(K kernel, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb <= 0)
+    nb = 1;
+  return nb * device_cus();
+}
+
+struct Launch {
+  bool batch;
+  const TileCfg* c;
+  const GridArgs* one;
+  const GridArgs* table;
+  int ngrids, ntiles;
+  double* partials;
+  const int* done;
+  hipStream_t st;
+};
+
+template <typename T, int BY, int VAR, unsigned FL>
+hipError_t go(const Launch& L) {
+  int grid;
+  if (L.batch) {
+    grid = L.ntiles;
+    if (L.c->persistent) {
+      static int cap = 0;
+      if (cap == 0) cap = resident_blocks(k_pass_batch<T, BY, VAR, FL>, WAVE * BY);
+      grid = min(grid, cap);
+    }
+    if (grid <= 0 || L.ngrids <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pass_batch<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, L.st, L.table,
+                       L.ngrids, L.ntiles, L.partials, L.done, (L.c->variant & 8) ? 1 : 0);
+  } else {
+    const GridArgs& g = *L.one;
+    grid = g.tiles_x * g.tiles_y * g.tiles_z;
+    if (L.c->persistent) {
+      static int cap = 0;
+      if (cap == 0) cap = resident_blocks(k_pass_one<T, BY, VAR, FL>, WAVE * BY);
+      grid = min(grid, cap);
+    }
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_pass_one<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, L.st, g,
+                       L.partials, L.done);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int BY, unsigned FL>
+hipError_t by_variant(const Launch& L) {
+  switch (L.c->variant & 0x17) {
+    case 0: return go<T, BY, 0, FL>(L);
+    case 1: return go<T, BY, 1, FL>(L);
+    case 2: return go<T, BY, 2, FL>(L);
+    case 3: return go<T, BY, 3, FL>(L);
+    case 4: return go<T, BY, 4, FL>(L);
+    case 5: return go<T, BY, 5, FL>(L);
+    case 6: return go<T, BY, 6, FL>(L);
+    case 7: return go<T, BY, 7, FL>(L);
+    case 16: return go<T, BY, 16, FL>(L);
+    case 17: return go<T, BY, 17, FL>(L);
+    case 18: return go<T, BY, 18, FL>(L);
+    case 19: return go<T, BY, 19, FL>(L);
+    case 20: return go<T, BY, 20, FL>(L);
+    case 21: return go<T, BY, 21, FL>(L);
+    case 22: return go<T, BY, 22, FL>(L);
+    case 23: return go<T, BY, 23, FL>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, unsigned FL>
+hipError_t by_shape(const Launch& L) {
+  switch (L.c->rows) {
+    case 1: return by_variant<T, 1, FL>(L);
+    case 2: return by_variant<T, 2, FL>(L);
+    case 4: return by_variant<T, 4, FL>(L);
+    case 8: return by_variant<T, 8, FL>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t dispatch_f64(unsigned flags, const Launch& L);
+hipError_t dispatch_f32(unsigned flags, const Launch& L);
+
+}  // namespace sweep_detail
+}  // namespace j3d

@@ -179,8 +179,8 @@ def test_solve_and_batch_validation_codes():
 
 def test_tune_list_and_request_bytes():
     tl = j3d.tune_list()
-    assert len(tl) == 80 and len(set(tl)) == 80
-    assert all(r in (1, 2, 4, 8) and v in (0, 1) and p in (0, 1) for r, _, v, p in tl)
+    assert len(tl) == 2048 and len(set(tl)) == 2048
+    assert all(r in (1, 2, 4, 8) and 0 <= v <= 31 and p in (0, 1) for r, _, v, p in tl)
     # 28 bytes per padded point (u, f FP64; r32, e0, e1 FP32) plus row padding
     b = j3d.j3d_request_bytes(384, 384, 384)
     assert 28 * 386 ** 3 <= b <= 1.1 * 28 * 386 ** 3

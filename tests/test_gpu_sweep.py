@@ -16,7 +16,10 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 from paper_2409_18824_amd import j3d  # noqa: E402
 
 SHAPES = [(1, 1, 1), (4, 4, 4), (3, 4, 5), (17, 9, 33), (64, 64, 64), (130, 67, 45), (65, 3, 70)]
-TUNES = [(1, 8, 0, 0), (2, 16, 1, 0), (4, 32, 0, 0), (4, 32, 1, 1), (8, 64, 0, 1), (8, 128, 1, 0)]
+# (rows, planes, variant bits: 1 LDS, 2 prefetch, 4 nontemporal; persistent)
+TUNES = [(1, 8, 0, 0), (2, 16, 1, 0), (4, 32, 2, 0), (4, 32, 3, 1), (8, 64, 4, 1), (8, 128, 7, 0),
+         (1, 16, 6, 0), (2, 8, 5, 1), (1, 1, 12, 0), (2, 4, 9, 1), (8, 2, 15, 0),
+         (1, 8, 30, 0), (4, 32, 22, 0), (2, 2, 31, 1), (8, 16, 19, 0), (1, 3 + 1, 28, 0)]
 
 
 def make_inputs(nx, ny, nz, seed=1):
@@ -68,7 +71,8 @@ def test_sweep_fp64_parity(shape, tune):
     assert j3d.residual_l2(du, df, h) == float(r.item())
 
 
-@pytest.mark.parametrize("tune", [(1, 8, 0, 0), (4, 32, 1, 0), (8, 16, 0, 1)])
+@pytest.mark.parametrize("tune", [(1, 8, 0, 0), (4, 32, 1, 0), (8, 16, 0, 1), (2, 16, 6, 0), (4, 64, 7, 1),
+                                  (1, 8, 30, 0), (2, 4, 23, 1)])
 def test_sweep_fp32_parity(tune):
     nx, ny, nz = 70, 13, 21
     say("sweep fp32", tune)
