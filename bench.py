@@ -14,7 +14,18 @@ The JSON line also carries
   cpu_baseline: the CPU oracle timed on a bounded sample of the same
                 workload (a few of the 500 sweeps, on all host threads).
 
+Other workloads (their own JSON line; not the default):
+  --workload mixed   FP32-sweep / FP64-defect-correction solve against the
+                     plain FP64 solve of the same manufactured problem, both
+                     to a relative residual of 1e-8 (time to solution);
+  --workload batch   256 independent grids, each axis uniform in {32..256},
+                     200 sweeps with residuals every 10, one graph launch;
+  --workload serve   a Poisson request stream (200/s, n log-uniform in
+                     [32, 384], tolerance 1e-6 or 1e-8, 5000-sweep cap) through
+                     the continuous-batching server: solves/s, p50/p99 latency.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--workload plain|mixed|batch|serve]
 """
 from __future__ import annotations
 
@@ -34,10 +45,15 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP_F64 = 24.0
 
 
+KERNEL_SOURCES = ("sweep.h", "kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "j3d_internal.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the device sources; counter summaries name the hash they were taken on."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2409_18824_amd", "csrc", "kernels.hip"), "rb") as fp:
-        h.update(fp.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_18824_amd", "csrc", name), "rb") as fp:
+            h.update(fp.read())
     return h.hexdigest()[:16]
 
 
@@ -50,7 +66,7 @@ def measured_traffic(kernel_hash: str):
             d = json.load(fp)
     except (OSError, ValueError):
         return None
-    if d.get("kernels_hip_sha256_16") != kernel_hash:
+    if d.get("kernel_sources_sha256_16") != kernel_hash:
         return None
     return d.get("bytes_per_launch")
 
@@ -93,8 +109,13 @@ def main():
     ap.add_argument("--resid-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve"])
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--active-points", type=float, default=2e8,
+                    help="serve: admission target for active interior points (0: no limit)")
+    ap.add_argument("--rtol", type=float, default=1e-8, help="mixed: target relative residual")
     ap.add_argument("--tile", default=None,
-                    help="pin the tile shape as rows,planes,variant,persistent instead of autotuning")
+                    help="pin the tile shape as rows,planes,variant,persistent,order instead of autotuning")
     ap.add_argument("--probe", action="store_true",
                     help="also time the copy kernel on 2 x 1 GiB (achievable-bandwidth ceiling)")
     args = ap.parse_args()
@@ -110,6 +131,10 @@ def main():
     from paper_2409_18824_amd import j3d
 
     torch.cuda.set_device(0)
+    if args.workload != "plain":
+        out = {"mixed": run_mixed, "batch": run_batch, "serve": run_serve}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
     n, S, E = args.n, args.sweeps, args.resid_every
     h = 1.0 / (n + 1)
     print("[bench] allocating %d^3 FP64 (u_a, u_b, f)" % n, file=sys.stderr, flush=True)
@@ -216,6 +241,160 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _base(args, metric, value, unit, ms, dtype, workload, higher=True, extra=None):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak",
+         "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": {"workload": workload}}
+    if extra:
+        d["config"].update(extra)
+    return d
+
+
+def run_mixed(args):
+    """Time to a 1e-8 relative residual: plain FP64 Jacobi vs FP32 sweeps with
+    FP64 defect correction every 50 sweeps, same problem, same GPU."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    n = args.n if "--n" in sys.argv else 256
+    h = 1.0 / (n + 1)
+    f = synth.manufactured_f(n, n, n, h)
+    df = j3d.FArray.from_numpy(f)
+    u = j3d.FArray.empty(n, n, n)
+    for dt in (j3d.F64, j3d.F32):
+        j3d.j3d_autotune_single(dt, n, n, n)
+    res = {}
+    for mode, name in ((j3d.MODE_MIXED, "mixed"), (j3d.MODE_FP64, "fp64")):
+        j3d.j3d_fill_uniform(u, 2, synth.STREAM_U0, 0.0, 1.0)
+        torch.cuda.synchronize()
+        print("[bench] %s solve to %g on %d^3" % (name, args.rtol, n), file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        r = j3d.poisson_solve(u, df, h, mode=mode, rtol=args.rtol, max_sweeps=10 ** 8,
+                              check_every=50, inner_sweeps=50, history_cap=1 << 21)
+        el = time.perf_counter() - t0
+        # the oracle's one-pass FP64 residual of the returned solution
+        uo = u.to_numpy()
+        rr = oracle.residual_l2(uo, f, h)
+        res[name] = {"seconds": round(el, 3), "sweeps": r.sweeps, "converged": r.converged,
+                     "rel_resid_gpu": r.resid / r.norm_f, "rel_resid_oracle": rr / oracle.norm2(f),
+                     "glups": round(float(n) ** 3 * r.sweeps / el / 1e9, 2)}
+        print("[bench] %s: %s" % (name, res[name]), file=sys.stderr, flush=True)
+        del uo
+    speedup = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    return _base(args, "time to 1e-8 relative residual (mixed vs FP64)", round(speedup, 3), "x speedup",
+                 res["mixed"]["seconds"] * 1e3, "f32+f64", "poisson-manufactured-%dcubed-mixed-vs-fp64" % n,
+                 extra={"grid": [n, n, n], "rtol": args.rtol, "inner_sweeps": 50, "check_every": 50,
+                        "results": res})
+
+
+def run_batch(args):
+    """256 uneven grids, 200 sweeps each with residuals every 10, one graph."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    shapes = synth.batch_shapes(256, 4)
+    grids = []
+    for g in shapes:
+        ua = j3d.FArray.empty(g.nx, g.ny, g.nz)
+        ub = j3d.FArray.empty(g.nx, g.ny, g.nz)
+        f = j3d.FArray.empty(g.nx, g.ny, g.nz)
+        j3d.j3d_fill_uniform(f, g.seed, synth.STREAM_F, -1.0, 1.0)
+        grids.append((ua, ub, f, g.h))
+    torch.cuda.synchronize()
+    pts = sum(g.nx * g.ny * g.nz for g in shapes)
+    nsw, every = 200, 10
+    out = torch.zeros((len(grids), nsw // every + 1), dtype=torch.float64, device="cuda")
+    print("[bench] batch of %d grids, %.3g points; autotuning" % (len(grids), pts), file=sys.stderr, flush=True)
+    tune = j3d.j3d_autotune(grids)
+    for _ in range(args.warmup):
+        j3d.jacobi3d_sweep_batch(grids, nsw, every, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        j3d.jacobi3d_sweep_batch(grids, nsw, every, out)
+    e1.record()
+    torch.cuda.synchronize()
+    el = max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
+    glups = pts * nsw * args.steps / el / 1e9
+    r = out.cpu().numpy()
+    assert np.all(np.isfinite(r)) and np.all(r[:, -1] < r[:, 0])
+    return _base(args, "GLUP/s (batched uneven grids)", round(glups, 3), "GLUP/s", round(el / args.steps * 1e3, 3),
+                 "f64", "batch-256-grids-32to256-200sweeps-resid10",
+                 extra={"grids": len(grids), "points": pts, "tile": tune,
+                        "hbm_gbs_algorithmic": round(glups * 24.0, 1),
+                        "hbm_frac_of_step": round(glups * 24.0 / HBM_PEAK_GBS, 4)})
+
+
+def run_serve(args):
+    """Poisson arrivals at 200/s through the continuous-batching server."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    reqs = synth.serve_requests(args.requests, rate=200.0, seed=5)
+    # warm the kernels with one small solve
+    with j3d.Server(hbm_budget_bytes=8 << 30, max_slots=4, cycle_sweeps=50) as s:
+        s.submit(32, 1 / 33, 1e-6, 100, seed=1)
+        s.drain(60)
+        s.poll()
+    budget = 200 * 10 ** 9
+    results = {}
+    print("[bench] serving %d requests" % len(reqs), file=sys.stderr, flush=True)
+    with j3d.Server(hbm_budget_bytes=budget, max_slots=2048, cycle_sweeps=50,
+                    max_active_points=int(args.active_points)) as s:
+        t_start = time.perf_counter()
+        tick = {}
+        for r in reqs:
+            now = time.perf_counter() - t_start
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            tick[s.submit(r.n, r.h, r.rtol, r.max_sweeps, seed=r.seed)] = r
+            for x in s.poll():
+                results[x["ticket"]] = x
+        last = time.perf_counter()
+        while len(results) < len(reqs):
+            for x in s.poll():
+                results[x["ticket"]] = x
+            if time.perf_counter() - last > 5:
+                st = s.stats()
+                print("[bench] serve: %d done, %d active, %d queued" % (len(results), st["active"], st["queued"]),
+                      file=sys.stderr, flush=True)
+                last = time.perf_counter()
+            time.sleep(0.01)
+        s.drain(600)
+    lat = np.array([x["t_done"] - x["t_submit"] for x in results.values()])
+    t0 = min(x["t_submit"] for x in results.values())
+    t1 = max(x["t_done"] for x in results.values())
+    conv = np.array([x["converged"] for x in results.values()])
+    tol8 = np.array([tick[k].rtol == 1e-8 for k in results])
+    sweeps = np.array([x["sweeps"] for x in results.values()])
+    ns = np.array([tick[k].n for k in results])
+    lups = float(np.sum(ns.astype(np.float64) ** 3 * sweeps))
+    out = _base(args, "served solves/s (mixed precision, continuous batching)", round(len(results) / (t1 - t0), 3),
+                "solves/s", round((t1 - t0) * 1e3, 1), "f32+f64",
+                "serve-poisson-200rps-n32to384-tol1e-6or1e-8-cap5000",
+                extra={"requests": len(results), "offered_rate_per_s": 200.0, "hbm_budget_bytes": budget,
+                       "max_active_points": int(args.active_points)})
+    out["latency_s"] = {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                        "p50_tol1e-8": round(float(np.percentile(lat[tol8], 50)), 3) if tol8.any() else None,
+                        "p99_tol1e-8": round(float(np.percentile(lat[tol8], 99)), 3) if tol8.any() else None}
+    out["converged_fraction"] = round(float(conv.mean()), 3)
+    out["converged_fraction_tol1e-8"] = round(float(conv[tol8].mean()), 3) if tol8.any() else None
+    out["glups_served"] = round(lups / (t1 - t0) / 1e9, 2)
+    return out
 
 
 if __name__ == "__main__":

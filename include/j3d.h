@@ -196,24 +196,24 @@ typedef struct j3d_grid {
 } j3d_grid;
 
 /*
- * Tile shape of the sweep kernels.  A workgroup sweeps 64 x-points (one
- * 64-lane wavefront per row) x `rows` y-rows x `planes` z-planes, marching
- * through z with the previous, current and next plane in registers.
- * variant is a bit set: 1 stages each plane in LDS (else x/y neighbours are
- * read through the cache); 2 and 16 give each thread 2^(bit 2 + 2 x bit 16)
- * consecutive rows (register blocking in y: the tile then has rows x that
- * many y-rows); 4 writes outputs with nontemporal stores; 8 keeps the
- * launch's workgroup order (else each of the 8 XCDs receives one contiguous
- * block of tiles).  persistent = 1 launches a fixed
- * grid of workgroups that stride over the tile list; 0 launches one
- * workgroup per tile.
- * The supported combinations are listed by j3d_tune_list().
+ * Tile shape of the sweep kernels.  A workgroup of `rows` 64-lane wavefronts
+ * sweeps 64 x-points x (rows x rows-per-thread) y-rows x `planes` z-planes,
+ * marching through z with the previous, current and next plane in
+ * registers.  variant is a bit set: 1 stages each plane in LDS (else x/y
+ * neighbours are read through the cache); 2 and 16 give each thread
+ * 2^(bit 2 + 2 x bit 16) consecutive rows (register blocking in y); 4 writes
+ * outputs with nontemporal stores (8 is not used).  persistent = 1 launches a
+ * fixed grid of workgroups that stride over the tile list, 0 one workgroup
+ * per tile.  order maps dispatch order to tiles: 0 gives each of the 8 XCDs
+ * one contiguous block of tiles, 1 keeps the launch order, 2 cuts each z-slab
+ * into 8 contiguous chunks, one per XCD.
  */
 typedef struct j3d_tune {
   int32_t rows;
   int32_t planes;
   int32_t variant;
   int32_t persistent;
+  int32_t order;
 } j3d_tune;
 
 /* Number of supported tile shapes, and the i-th one (host-only). */
@@ -263,6 +263,9 @@ typedef struct j3d_serve_opts {
   int32_t cycle_sweeps;       /* FP32 sweeps per defect-correction cycle (e.g. 50) */
   int32_t device;             /* HIP device ordinal */
   int32_t queue_cap;          /* maximum queued (not yet admitted) requests */
+  uint64_t max_active_points; /* admit while active interior points stay at or below
+                                 this (a request is admitted regardless when nothing is
+                                 active); 0: no limit */
 } j3d_serve_opts;
 
 typedef struct j3d_request {
@@ -292,8 +295,10 @@ uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz);
 
 /*
  * Create a server with its own worker thread and HIP stream on opts->device.
- * Requests are admitted in arrival order while their state fits the budget
- * and a slot is free; every active request is a slot in one batched
+ * Requests are admitted in arrival order while their state fits the budget,
+ * a slot is free and the active points stay within max_active_points (enough
+ * to fill the GPU: more only delays every request); every active request is
+ * a slot in one batched
  * mixed-precision cycle (FP64 defect step + cycle_sweeps FP32 sweeps over
  * all slots' tiles).  At every cycle boundary converged or capped requests
  * retire and waiting ones are admitted (continuous batching).  A request's

@@ -69,7 +69,7 @@ void tune_load_locked() {
   if (!fp) return;
   char key[128];
   TileCfg c;
-  while (fscanf(fp, "%127s %d %d %d %d", key, &c.rows, &c.planes, &c.variant, &c.persistent) == 5)
+  while (fscanf(fp, "%127s %d %d %d %d %d", key, &c.rows, &c.planes, &c.variant, &c.persistent, &c.order) == 6)
     if (tile_cfg_supported(c)) g_tune[key] = c;
   fclose(fp);
 }
@@ -83,8 +83,8 @@ void tune_store(const std::string& key, const TileCfg& c) {
   FILE* fp = fopen(path, "w");
   if (!fp) return;
   for (auto& kv : g_tune)
-    fprintf(fp, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.rows, kv.second.planes,
-            kv.second.variant, kv.second.persistent);
+    fprintf(fp, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.rows, kv.second.planes,
+            kv.second.variant, kv.second.persistent, kv.second.order);
   fclose(fp);
 }
 
@@ -292,24 +292,24 @@ std::vector<TileCfg> candidates() {
   for (int i = 0; i < n; ++i) {
     j3d_tune t;
     j3d_tune_get(i, &t);
-    v.push_back(TileCfg{t.rows, t.planes, t.variant, t.persistent});
+    v.push_back(TileCfg{t.rows, t.planes, t.variant, t.persistent, t.order});
   }
   return v;
 }
 
 // Time F_WRITE passes of tile shapes and return the fastest.  The search is
-// staged rather than exhaustive: rows x planes with the plain variant, then
-// every variant and persistence setting at the best rows x planes, then rows x
-// planes again at the best variant.  `launch` enqueues one pass for a shape.
+// staged rather than exhaustive: rows x planes with a default variant, then
+// every variant x persistence x order at the best rows x planes, then rows x
+// planes again at the best of those.  `launch` enqueues one pass for a shape.
 template <typename Launcher>
 int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
   hipEvent_t e0, e1;
   J3D_HIP(hipEventCreate(&e0));
   J3D_HIP(hipEventCreate(&e1));
-  std::map<std::tuple<int, int, int, int>, float> seen;
+  std::map<std::tuple<int, int, int, int, int>, float> seen;
   int rc = J3D_OK;
   auto time_of = [&](const TileCfg& c, float* out) -> int {
-    auto key = std::make_tuple(c.rows, c.planes, c.variant, c.persistent);
+    auto key = std::make_tuple(c.rows, c.planes, c.variant, c.persistent, c.order);
     auto it = seen.find(key);
     if (it != seen.end()) {
       *out = it->second;
@@ -338,7 +338,7 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
       planes_set.push_back(c.planes);
     if (std::find(var_set.begin(), var_set.end(), c.variant) == var_set.end()) var_set.push_back(c.variant);
   }
-  TileCfg b{4, 32, 0, 0};
+  TileCfg b{1, 16, 20, 0, 1};
   float bt = 1e30f;
   auto consider = [&](const TileCfg& c) -> int {
     float t = 0.f;
@@ -353,12 +353,13 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
     const TileCfg base = b;
     if (stage == 1) {
       for (int v : var_set)
-        for (int p = 0; p < 2 && rc == J3D_OK; ++p) rc = consider(TileCfg{base.rows, base.planes, v, p});
+        for (int p = 0; p < 2; ++p)
+          for (int o = 0; o < 3 && rc == J3D_OK; ++o) rc = consider(TileCfg{base.rows, base.planes, v, p, o});
     } else {
       for (int r : rows_set)
         for (int pl : planes_set) {
           if (rc != J3D_OK) break;
-          rc = consider(TileCfg{r, pl, stage == 0 ? 0 : base.variant, stage == 0 ? 0 : base.persistent});
+          rc = consider(TileCfg{r, pl, base.variant, base.persistent, base.order});
         }
     }
   }
@@ -437,7 +438,7 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
   hipStream_t st = static_cast<hipStream_t>(stream);
   TileCfg c;
   if (tune != nullptr) {
-    c = TileCfg{tune->rows, tune->planes, tune->variant, tune->persistent};
+    c = TileCfg{tune->rows, tune->planes, tune->variant, tune->persistent, tune->order};
     if (!tile_cfg_supported(c)) return fail(J3D_EINVAL, "unsupported tile shape");
   } else {
     const std::string bk = batch_key(ngrids, bf.a.data());
@@ -453,8 +454,8 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
   int dev = 0;
   J3D_HIP(hipGetDevice(&dev));
   const long long meta[8] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
-                             c.rows * 1000000LL + c.planes * 100 + c.variant * 10 + c.persistent,
-                             dev, 0, 0};
+                             c.rows * 1000000LL + c.planes * 1000 + c.variant * 10 + c.persistent,
+                             dev, c.order, 0};
   key.append(reinterpret_cast<const char*>(meta), sizeof meta);
   Plan* plan = nullptr;
   {
@@ -494,6 +495,7 @@ extern "C" int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* bes
   best->planes = c.planes;
   best->variant = c.variant;
   best->persistent = c.persistent;
+  best->order = c.order;
   return J3D_OK;
 }
 
@@ -542,12 +544,13 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
   best->planes = c.planes;
   best->variant = c.variant;
   best->persistent = c.persistent;
+  best->order = c.order;
   return J3D_OK;
 }
 
 extern "C" int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t) {
   if (t == nullptr) return fail(J3D_EINVAL, "tune: null pointer");
-  TileCfg c{t->rows, t->planes, t->variant, t->persistent};
+  TileCfg c{t->rows, t->planes, t->variant, t->persistent, t->order};
   if (!tile_cfg_supported(c)) return fail(J3D_EINVAL, "unsupported tile shape");
   if (dtype != J3D_F64 && dtype != J3D_F32) return fail(J3D_EDTYPE, "dtype must be F64 or F32");
   tune_store(single_key(dtype, nx, ny, nz), c);

@@ -14,15 +14,19 @@ bool tune_cache_lookup_single(int dtype, int nx, int ny, int nz, TileCfg* out);
 namespace {
 const int kRows[] = {1, 2, 4, 8};
 const int kPlanes[] = {1, 2, 4, 8, 16, 32, 64, 128};
+const int kVariants[] = {0, 1, 2, 3, 4, 5, 6, 7, 16, 17, 18, 19, 20, 21, 22, 23};
 constexpr int kNumPlanes = 8;
-constexpr int kNumVariants = 32;
-constexpr int kNumTunes = 4 * kNumPlanes * kNumVariants * 2;
+constexpr int kNumVariants = 16;
+constexpr int kNumOrders = 3;
+constexpr int kNumTunes = 4 * kNumPlanes * kNumVariants * 2 * kNumOrders;
 
 TileCfg tune_at(int idx) {
   TileCfg c;
+  c.order = idx % kNumOrders;
+  idx /= kNumOrders;
   c.persistent = idx % 2;
   idx /= 2;
-  c.variant = idx % kNumVariants;
+  c.variant = kVariants[idx % kNumVariants];
   idx /= kNumVariants;
   c.planes = kPlanes[idx % kNumPlanes];
   idx /= kNumPlanes;
@@ -34,10 +38,11 @@ TileCfg tune_at(int idx) {
 TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   TileCfg c;
   if (tune_cache_lookup_single(dtype, nx, ny, nz, &c)) return c;
-  c.rows = 4;
-  c.planes = 32;
-  c.variant = 0;
+  c.rows = 1;
+  c.planes = 16;
+  c.variant = 20;  // four rows per thread, nontemporal stores
   c.persistent = 0;
+  c.order = 1;
   return c;
 }
 
@@ -90,6 +95,7 @@ int j3d_tune_get(int32_t index, j3d_tune* out) {
   out->planes = c.planes;
   out->variant = c.variant;
   out->persistent = c.persistent;
+  out->order = c.order;
   return J3D_OK;
 }
 

@@ -29,7 +29,8 @@ struct GridArgs {
   int id;           // index of this grid's flags and norms in per-grid arrays
   double h2;        // h*h in FP64
   float h2f;        // (float)(h*h)
-  int order;        // 0: XCD-blocked dispatch order, 1: dispatch order as launched
+  int order;        // tile order: 0 XCD-blocked, 1 as launched, 2 chunked per XCD
+  int chunk;        // order 2: tiles per XCD chunk
 };
 
 // Kernel pass flags (compile-time).
@@ -43,11 +44,11 @@ enum : unsigned {
 };
 
 struct TileCfg {
-  int rows;       // y-rows per workgroup = wavefronts per workgroup
+  int rows;       // wavefronts per workgroup
   int planes;     // z-planes per tile
-  int variant;    // bit set: 1 LDS plane, 2 prefetch, 4 nontemporal stores,
-                  // 8 keep the launch's dispatch order (no XCD blocking)
+  int variant;    // bit set: 1 LDS plane; 2, 16 rows per thread; 4 nontemporal stores
   int persistent; // 1: fixed grid striding over tiles
+  int order;      // 0 XCD-blocked, 1 as launched, 2 chunked per XCD within each slab
 };
 
 // Supported rows values and variants (kernels are instantiated for these).

@@ -181,7 +181,8 @@ using sweep_detail::device_cus;
 
 bool tile_cfg_supported(const TileCfg& c) {
   const bool rows_ok = c.rows == 1 || c.rows == 2 || c.rows == 4 || c.rows == 8;
-  return rows_ok && c.variant >= 0 && c.variant <= 31 && c.planes >= 1 && c.planes <= 4096 &&
+  const bool var_ok = c.variant >= 0 && c.variant <= 23 && (c.variant & 8) == 0;
+  return rows_ok && var_ok && c.order >= 0 && c.order <= 2 && c.planes >= 1 && c.planes <= 4096 &&
          (c.persistent == 0 || c.persistent == 1);
 }
 
@@ -257,8 +258,10 @@ hipError_t launch_fill_const(void* a, int dtype, int ex, int ey, int ez, long lo
 }
 
 hipError_t launch_copy(const double* src, double* dst, long long n, hipStream_t st) {
+  // One 16-byte element per thread and one short-lived wavefront per 1 KiB:
+  // on MI355X this streams faster than persistent grid-stride copies.
   const long long n2 = n / 2;
-  const int grid = static_cast<int>(min(n2 / 256 + 1, (long long)device_cus() * 16));
+  const int grid = static_cast<int>(min(n2 / 256 + 1, (long long)(1 << 30)));
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, reinterpret_cast<const double2*>(src),
                      reinterpret_cast<double2*>(dst), n2);
   hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, st, src, dst, n);

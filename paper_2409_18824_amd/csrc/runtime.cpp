@@ -127,7 +127,8 @@ GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* 
   g.planes = c.planes;
   g.h2 = h * h;
   g.h2f = static_cast<float>(h * h);
-  g.order = (c.variant & 8) ? 1 : 0;
+  g.order = c.order;
+  g.chunk = (g.tiles_x * g.tiles_y + 7) / 8;
   return g;
 }
 

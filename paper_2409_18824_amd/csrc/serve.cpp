@@ -80,6 +80,7 @@ struct Request {
   double t_submit = 0, t_admit = 0;
   int64_t max_sweeps = 0;
   size_t bytes = 0;
+  uint64_t points = 0;
 };
 
 struct Slot {
@@ -108,6 +109,7 @@ struct j3d_server {
   int64_t n_submitted = 0;
   int64_t n_finished = 0;
   size_t used_bytes = 0;
+  uint64_t active_points = 0;
   double t0 = 0;
   int error = J3D_OK;
   std::string error_text;
@@ -242,10 +244,14 @@ int admit(j3d_server* s) {
       if (s->queue.empty() || s->free_ids.empty()) return J3D_OK;
       Request* head = s->queue.front();
       if (s->used_bytes + head->bytes > s->o.hbm_budget_bytes) return J3D_OK;
+      if (s->o.max_active_points != 0 && s->active_points != 0 &&
+          s->active_points + head->points > s->o.max_active_points)
+        return J3D_OK;
       s->queue.pop_front();
       id = s->free_ids.back();
       s->free_ids.pop_back();
       s->used_bytes += head->bytes;
+      s->active_points += head->points;
       q = head;
     }
     Slot* sl = new Slot();
@@ -259,6 +265,7 @@ int admit(j3d_server* s) {
       s->queue.push_front(q);
       s->free_ids.push_back(id);
       s->used_bytes -= q->bytes;
+      s->active_points -= q->points;
       delete sl;
       return s->active.empty() ? rc : J3D_OK;
     }
@@ -365,6 +372,7 @@ int retire(j3d_server* s, Slot* sl, bool converged, bool nonfinite, double resid
     s->finished.push_back(r);
     s->n_finished++;
     s->used_bytes -= q->bytes;
+    s->active_points -= q->points;
     s->free_ids.push_back(sl->id);
   }
   s->cv_done.notify_all();
@@ -471,6 +479,7 @@ int poisson_serve_submit(j3d_server* s, const j3d_request* req, uint64_t* ticket
   Request* q = new Request();
   q->r = *req;
   q->bytes = bytes;
+  q->points = (uint64_t)req->nx * (uint64_t)req->ny * (uint64_t)req->nz;
   const int64_t c = s->o.cycle_sweeps;
   q->max_sweeps = (req->max_sweeps + c - 1) / c * c;
   if (req->f_host != nullptr) q->f.assign(req->f_host, req->f_host + ex * ey * ez);

@@ -21,8 +21,6 @@
 //      8): register blocking in y, which multiplies the independent HBM
 //      loads each wavefront has in flight per plane;
 //   4  outputs are written with nontemporal stores (streamed past L2).
-// Variant bit 8 (a run-time choice, not a template parameter) keeps the
-// launch's workgroup order instead of giving each XCD a contiguous block.
 //
 // Arithmetic order is fixed and the library is built with contraction off:
 //   S  = ((((u[i-1] + u[i+1]) + u[j-1]) + u[j+1]) + u[k-1]) + u[k+1]
@@ -46,12 +44,28 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Map dispatch order to logical tile order so that each XCD receives
-// one contiguous block of tiles: neighbouring tiles then share halo rows in
-// the same L2.
+// L2); dispatch index b runs on XCD b % 8.  Three orders map dispatch
+// indices to tiles:
+//   0  each XCD receives one contiguous block of all tiles (halo rows stay in
+//      one L2, but the XCDs stream from 8 distant regions);
+//   1  as launched (all XCDs stream one region together; neighbouring tiles
+//      land on different XCDs);
+//   2  the tiles are cut into groups of 8*chunk (about one z-slab of one
+//      grid); within a group XCD x takes the contiguous chunk x, so all XCDs
+//      stream the same slab while each keeps its own neighbours in its L2.
 __device__ __forceinline__ int xcd_remap(int b, int n) {
   const int q = n >> 3, r = n & 7, x = b & 7, idx = b >> 3;
   return x * q + min(x, r) + idx;
+}
+
+__device__ __forceinline__ int xcd_chunked(int vb, int chunk) {
+  const int x = vb & 7, idx = vb >> 3;
+  return (idx / chunk) * 8 * chunk + x * chunk + (idx % chunk);
+}
+
+// Number of dispatch indices that cover ntiles tiles under an order.
+__host__ __device__ __forceinline__ int virtual_tiles(int ntiles, int order, int chunk) {
+  return order == 2 ? (ntiles + 8 * chunk - 1) / (8 * chunk) * (8 * chunk) : ntiles;
 }
 
 template <typename T>
@@ -247,17 +261,28 @@ __global__ void __launch_bounds__(WAVE * BY)
   if (done != nullptr && *done != 0) return;
   __shared__ Smem<T, BY, VAR> sm;
   const int ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
-  const int first = g.order ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-  for (int t = first; t < ntiles; t += gridDim.x) sweep_tile<T, BY, VAR, FL>(g, t, partials, sm);
+  if (g.order == 0) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
+      sweep_tile<T, BY, VAR, FL>(g, t, partials, sm);
+  } else {
+    const int nv = virtual_tiles(ntiles, g.order, g.chunk);
+    for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
+      const int t = g.order == 2 ? xcd_chunked(vb, g.chunk) : vb;
+      if (t < ntiles) sweep_tile<T, BY, VAR, FL>(g, t, partials, sm);
+    }
+  }
 }
 
 template <typename T, int BY, int VAR, unsigned FL>
 __global__ void __launch_bounds__(WAVE * BY)
     k_pass_batch(const GridArgs* __restrict__ table, int ngrids, int ntiles,
-                 double* __restrict__ partials, const int* __restrict__ done, int order) {
+                 double* __restrict__ partials, const int* __restrict__ done, int order, int chunk) {
   __shared__ Smem<T, BY, VAR> sm;
-  const int first = order ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-  for (int t = first; t < ntiles; t += gridDim.x) {
+  const int nv = order == 0 ? ntiles : virtual_tiles(ntiles, order, chunk);
+  const int first = order == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  for (int vb = first; vb < nv; vb += gridDim.x) {
+    const int t = order == 2 ? xcd_chunked(vb, chunk) : vb;
+    if (t >= ntiles) continue;
     int lo = 0, hi = ngrids - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -283,6 +308,9 @@ int resident_blocks(K kernel, int threads) {
   return nb * device_cus();
 }
 
+// Chunk length of order 2 for batched launches (tiles per XCD per group).
+constexpr int kBatchChunk = 32;
+
 struct Launch {
   bool batch;
   const TileCfg* c;
@@ -298,7 +326,8 @@ template <typename T, int BY, int VAR, unsigned FL>
 hipError_t go(const Launch& L) {
   int grid;
   if (L.batch) {
-    grid = L.ntiles;
+    const int chunk = kBatchChunk;
+    grid = virtual_tiles(L.ntiles, L.c->order, chunk);
     if (L.c->persistent) {
       static int cap = 0;
       if (cap == 0) cap = resident_blocks(k_pass_batch<T, BY, VAR, FL>, WAVE * BY);
@@ -306,10 +335,10 @@ hipError_t go(const Launch& L) {
     }
     if (grid <= 0 || L.ngrids <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_pass_batch<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, L.st, L.table,
-                       L.ngrids, L.ntiles, L.partials, L.done, (L.c->variant & 8) ? 1 : 0);
+                       L.ngrids, L.ntiles, L.partials, L.done, L.c->order, chunk);
   } else {
     const GridArgs& g = *L.one;
-    grid = g.tiles_x * g.tiles_y * g.tiles_z;
+    grid = virtual_tiles(g.tiles_x * g.tiles_y * g.tiles_z, g.order, g.chunk);
     if (L.c->persistent) {
       static int cap = 0;
       if (cap == 0) cap = resident_blocks(k_pass_one<T, BY, VAR, FL>, WAVE * BY);
@@ -324,7 +353,7 @@ hipError_t go(const Launch& L) {
 
 template <typename T, int BY, unsigned FL>
 hipError_t by_variant(const Launch& L) {
-  switch (L.c->variant & 0x17) {
+  switch (L.c->variant) {
     case 0: return go<T, BY, 0, FL>(L);
     case 1: return go<T, BY, 1, FL>(L);
     case 2: return go<T, BY, 2, FL>(L);

@@ -67,16 +67,18 @@ class Grid(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
+    """(rows, planes, variant, persistent, order); see j3d_tune in include/j3d.h."""
     _fields_ = [("rows", ctypes.c_int32), ("planes", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("order", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.rows, self.planes, self.variant, self.persistent)
+        return (self.rows, self.planes, self.variant, self.persistent, self.order)
 
 
 class ServeOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
-                ("cycle_sweeps", ctypes.c_int32), ("device", ctypes.c_int32), ("queue_cap", ctypes.c_int32)]
+                ("cycle_sweeps", ctypes.c_int32), ("device", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("max_active_points", ctypes.c_uint64)]
 
 
 class Request(ctypes.Structure):
@@ -408,9 +410,9 @@ class Server:
     """poisson_serve_* over a server handle."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, cycle_sweeps: int = 50,
-                 device: int = 0, queue_cap: int = 100000):
+                 device: int = 0, queue_cap: int = 100000, max_active_points: int = 0):
         self._h = ctypes.c_void_p()
-        o = ServeOpts(int(hbm_budget_bytes), max_slots, cycle_sweeps, device, queue_cap)
+        o = ServeOpts(int(hbm_budget_bytes), max_slots, cycle_sweeps, device, queue_cap, int(max_active_points))
         _check(_lib.poisson_serve_create(ctypes.byref(o), ctypes.byref(self._h)), "poisson_serve_create")
         self._keep = {}
 

@@ -172,15 +172,16 @@ def test_solve_and_batch_validation_codes():
     # two grids may share one read-only f
     g[1].u_b = fake_desc(n, n, n, base=0x300000 + 4 * span)
     g[1].f = g[0].f
-    t = j3d.Tune(3, 32, 0, 0)  # unsupported rows -> rejected before any device work
+    t = j3d.Tune(3, 32, 0, 0, 0)  # unsupported rows -> rejected before any device work
     assert lib.jacobi3d_sweep_batch(2, g, 10, 1, None, ctypes.byref(t), None) == j3d.EINVAL
     assert lib.jacobi3d_sweep_batch(0, g, 10, 1, None, None, None) == j3d.EINVAL
 
 
 def test_tune_list_and_request_bytes():
     tl = j3d.tune_list()
-    assert len(tl) == 2048 and len(set(tl)) == 2048
-    assert all(r in (1, 2, 4, 8) and 0 <= v <= 31 and p in (0, 1) for r, _, v, p in tl)
+    assert len(tl) == 3072 and len(set(tl)) == 3072
+    assert all(r in (1, 2, 4, 8) and 0 <= v <= 23 and not v & 8 and p in (0, 1) and o in (0, 1, 2)
+               for r, _, v, p, o in tl)
     # 28 bytes per padded point (u, f FP64; r32, e0, e1 FP32) plus row padding
     b = j3d.j3d_request_bytes(384, 384, 384)
     assert 28 * 386 ** 3 <= b <= 1.1 * 28 * 386 ** 3

@@ -27,7 +27,8 @@ def make_batch(shapes, seed=4):
 SHAPES = [(33, 40, 35), (64, 17, 90), (5, 70, 3), (128, 32, 33), (1, 1, 1), (70, 70, 70)]
 
 
-@pytest.mark.parametrize("tune", [(4, 32, 0, 0), (2, 16, 1, 1), (8, 8, 6, 1), (1, 16, 7, 0)])
+@pytest.mark.parametrize("tune", [(4, 32, 0, 0, 0), (2, 16, 1, 1, 0), (8, 8, 6, 1, 0), (1, 16, 7, 0, 0),
+                                  (1, 8, 20, 0, 2), (2, 4, 22, 1, 1), (1, 16, 28 - 8, 0, 2)])
 @pytest.mark.parametrize("nsweeps,every", [(20, 5), (7, 3)])
 def test_batch_matches_oracle(tune, nsweeps, every):
     say("batch", tune, nsweeps, every)
@@ -52,7 +53,7 @@ def test_batch_matches_oracle(tune, nsweeps, every):
 
 
 def test_batch_equals_solo_bitwise_and_replays():
-    tune = (4, 16, 0, 1)
+    tune = (4, 16, 0, 1, 0)
     say("batch vs solo")
     grids, host = make_batch(SHAPES, seed=7)
     nres = 10 // 2 + 1

@@ -88,3 +88,17 @@ def test_continuous_batching_late_arrivals_join():
         # each short request was admitted and finished while the long one was still running
         assert res[k]["t_admit"] < long["t_done"]
         assert res[k]["t_done"] < long["t_done"]
+
+
+def test_active_points_target_limits_concurrency():
+    pts = 20 ** 3
+    say("active points target")
+    with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=8, cycle_sweeps=10, max_active_points=2 * pts) as s:
+        reqs = [(20, 1e-12, 40, 60 + k, False) for k in range(5)]
+        res, _ = run(s, reqs)
+    order = sorted(res.values(), key=lambda r: r["t_admit"])
+    for k in range(2, 5):
+        earlier_done = sorted(r["t_done"] for r in order[:k])
+        assert order[k]["t_admit"] >= earlier_done[k - 2] - 1e-3
+    # FIFO: admitted in submission order
+    assert [r["ticket"] for r in order] == sorted(r["ticket"] for r in order)

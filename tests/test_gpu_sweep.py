@@ -16,10 +16,11 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 from paper_2409_18824_amd import j3d  # noqa: E402
 
 SHAPES = [(1, 1, 1), (4, 4, 4), (3, 4, 5), (17, 9, 33), (64, 64, 64), (130, 67, 45), (65, 3, 70)]
-# (rows, planes, variant bits: 1 LDS, 2 prefetch, 4 nontemporal; persistent)
-TUNES = [(1, 8, 0, 0), (2, 16, 1, 0), (4, 32, 2, 0), (4, 32, 3, 1), (8, 64, 4, 1), (8, 128, 7, 0),
-         (1, 16, 6, 0), (2, 8, 5, 1), (1, 1, 12, 0), (2, 4, 9, 1), (8, 2, 15, 0),
-         (1, 8, 30, 0), (4, 32, 22, 0), (2, 2, 31, 1), (8, 16, 19, 0), (1, 3 + 1, 28, 0)]
+# (rows, planes, variant bits: 1 LDS, 2/16 rows per thread, 4 nontemporal; persistent; order)
+TUNES = [(1, 8, 0, 0, 0), (2, 16, 1, 0, 0), (4, 32, 2, 0, 0), (4, 32, 3, 1, 0), (8, 64, 4, 1, 0), (8, 128, 7, 0, 0),
+         (1, 16, 6, 0, 0), (2, 8, 5, 1, 0), (1, 1, 4, 0, 1), (2, 4, 1, 1, 1), (8, 2, 7, 0, 1),
+         (1, 8, 22, 0, 1), (4, 32, 22, 0, 0), (2, 2, 23, 1, 1), (8, 16, 19, 0, 0), (1, 4, 20, 0, 1),
+         (1, 8, 20, 0, 2), (4, 16, 6, 1, 2), (2, 4, 21, 0, 2), (1, 1, 18, 1, 2)]
 
 
 def make_inputs(nx, ny, nz, seed=1):
@@ -71,8 +72,8 @@ def test_sweep_fp64_parity(shape, tune):
     assert j3d.residual_l2(du, df, h) == float(r.item())
 
 
-@pytest.mark.parametrize("tune", [(1, 8, 0, 0), (4, 32, 1, 0), (8, 16, 0, 1), (2, 16, 6, 0), (4, 64, 7, 1),
-                                  (1, 8, 30, 0), (2, 4, 23, 1)])
+@pytest.mark.parametrize("tune", [(1, 8, 0, 0, 0), (4, 32, 1, 0, 0), (8, 16, 0, 1, 0), (2, 16, 6, 0, 2), (4, 64, 7, 1, 0),
+                                  (1, 8, 22, 0, 1), (2, 4, 23, 1, 0)])
 def test_sweep_fp32_parity(tune):
     nx, ny, nz = 70, 13, 21
     say("sweep fp32", tune)
@@ -107,7 +108,7 @@ def test_strided_views_and_lbounds():
     say("strided views")
     u, f, h = make_inputs(nx, ny, nz, seed=3)
     want = oracle.sweep(u, f, h)
-    j3d.j3d_tune_set_single(j3d.F64, nx, ny, nz, (4, 8, 1, 0))
+    j3d.j3d_tune_set_single(j3d.F64, nx, ny, nz, (4, 8, 1, 0, 0))
     du = j3d.FArray.from_numpy(u, lbound=(-3, 5, 2), ld_extra=7, plane_extra=5)
     dv = j3d.FArray.from_numpy(u, lbound=(1, 1, 1), align_bytes=8)
     df = j3d.FArray.from_numpy(f, lbound=(0, 0, 0), ld_extra=1, plane_extra=123)
