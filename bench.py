@@ -3,14 +3,19 @@
 Default workload: 512^3 interior + halo, FP64, two ping-pong arrays plus f,
 u0 ~ U[0,1) (seed 2), f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z), h = 1/513;
 one step = 500 sweeps with the L2 residual fused into every 10th sweep
-(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  Throughput is
-grid-point updates per second (GLUP/s) over the timed steps.
+(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  The sweeps run as
+250 two-sweep passes (jacobi3d_sweep2: the intermediate iterate stays on
+chip; --passes 1 runs 500 single sweeps instead).  Throughput is grid-point
+updates per second (GLUP/s) over the timed steps.
 
 The JSON line also carries
-  roofline:     the dominant kernel (the plain FP64 sweep, 450 of the 500
-                launches of a step), its average duration from HIP events on
-                the stream it runs on, and its algorithmic bandwidth
-                (24 bytes per point update) against the MI355X HBM peak;
+  roofline:     the dominant kernel (the pass without a fused residual, 225
+                of the 250 launches of a step), its average duration from HIP
+                events on the stream it runs on, and its algorithmic bandwidth
+                against the MI355X HBM peak.  Algorithmic bytes per launch:
+                24 per interior point (read u, read f, write the result) for
+                either pass; a two-sweep pass does two updates per point for
+                them (12 bytes per update), a single sweep one (24);
   cpu_baseline: the CPU oracle timed on a bounded sample of the same
                 workload (a few of the 500 sweeps, on all host threads).
 
@@ -57,10 +62,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash: str):
+def measured_traffic(kernel_hash: str, passes: int):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "sweep_fp64_512_counters.json")
+    path = os.path.join(ROOT, "profiles", "sweep%s_fp64_512_counters.json" % ("2" if passes == 2 else ""))
     try:
         with open(path) as fp:
             d = json.load(fp)
@@ -107,6 +112,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--resid-every", type=int, default=10)
+    ap.add_argument("--passes", type=int, default=2, choices=[1, 2],
+                    help="sweeps per pass over memory (2: temporally blocked pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve"])
@@ -144,18 +151,25 @@ def main():
     j3d.j3d_fill_const(ub, 0.0)
     df = j3d.FArray.from_numpy(synth.manufactured_f(n, n, n, h))
     torch.cuda.synchronize()
+    P = args.passes
+    if P == 2 and (E % 2 != 0 or S % 2 != 0):
+        raise SystemExit("two-sweep passes need even --sweeps and --resid-every")
+    kind = j3d.KIND_F64X2 if P == 2 else j3d.F64
     if args.tile:
         tune = tuple(int(x) for x in args.tile.split(","))
-        j3d.j3d_tune_set_single(j3d.F64, n, n, n, tune)
+        j3d.j3d_tune_set_single(kind, n, n, n, tune)
     elif args.no_tune:
         tune = None
     else:
-        tune = j3d.j3d_autotune_single(j3d.F64, n, n, n)
+        tune = j3d.j3d_autotune_single(kind, n, n, n)
+        if P == 2:
+            j3d.j3d_autotune_single(j3d.F64, n, n, n)  # the standalone residual pass
     print("[bench] tile shape (rows, planes, variant, persistent) = %s" % (tune,), file=sys.stderr, flush=True)
 
     nres = S // E + 1
     resid = torch.zeros(nres, dtype=torch.float64, device="cuda")
-    n_plain = sum(1 for s in range(S) if s % E != 0)
+    sweep = j3d.jacobi3d_sweep2 if P == 2 else j3d.jacobi3d_sweep
+    n_plain = sum(1 for s in range(0, S, P) if s % E != 0)
     events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(n_plain)] for _ in range(args.steps)]
 
@@ -165,13 +179,13 @@ def main():
         cur, nxt = state["cur"], state["nxt"]
         timed = ev is not None
         q = 0
-        for s in range(S):
+        for s in range(0, S, P):
             if s % E == 0:
-                j3d.jacobi3d_sweep(cur, nxt, df, h, resid_out=resid[s // E:s // E + 1])
+                sweep(cur, nxt, df, h, resid_out=resid[s // E:s // E + 1])
             else:
                 if timed:
                     ev[q][0].record()
-                j3d.jacobi3d_sweep(cur, nxt, df, h)
+                sweep(cur, nxt, df, h)
                 if timed:
                     ev[q][1].record()
                     q += 1
@@ -207,12 +221,16 @@ def main():
     assert np.all(np.isfinite(r)) and r[-1] < r[0], "residual did not decrease"
 
     avg_ms = float(np.mean(kernel_ms))
-    achieved = BYTES_PER_LUP_F64 * n ** 3 / (avg_ms * 1e-3) / 1e9
+    bytes_launch = BYTES_PER_LUP_F64 * n ** 3  # read u, read f, write the result
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
+    kname = ("k_sweep2_one<F_WRITE> (two FP64 sweeps per pass)" if P == 2
+             else "k_pass_one<double, F_WRITE> (FP64 sweep)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash),
-            "kernel": "k_pass_one<double, F_WRITE> (FP64 sweep)", "avg_launch_us": round(avg_ms * 1e3, 2),
-            "launches": len(kernel_ms), "bytes_per_launch_algorithmic": int(BYTES_PER_LUP_F64 * n ** 3)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, P),
+            "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "launches": len(kernel_ms), "bytes_per_launch_algorithmic": int(bytes_launch),
+            "updates_per_point_per_launch": P}
 
     probe = None
     if args.probe:
@@ -235,8 +253,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "jacobi3d-7pt-fp64-%dcubed-%dsweeps-resid%d" % (n, S, E),
                    "grid": [n, n, n], "halo": 1, "layout": "fortran-column-major",
-                   "sweeps_per_step": S, "resid_every": E, "tile": tune,
-                   "hbm_frac_of_step": round(glups * BYTES_PER_LUP_F64 / HBM_PEAK_GBS, 4)},
+                   "sweeps_per_step": S, "resid_every": E, "sweeps_per_pass": P, "tile": tune,
+                   "single_sweep_equivalent_gbs": round(glups * BYTES_PER_LUP_F64, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

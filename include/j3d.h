@@ -132,6 +132,17 @@ int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_arra
                    double h, uint32_t flags, double* resid_out, void* stream);
 
 /*
+ * Two Jacobi sweeps in one pass over memory: u_out = J(J(u_in; f, h)), all
+ * three arrays FP64.  The intermediate iterate stays on chip (temporal
+ * blocking in z), so the pass streams u_in and f once and writes u_out once
+ * for two sweeps' worth of updates; every point is computed exactly as two
+ * jacobi3d_sweep calls would (bit-identical).  resid_out and flags are as in
+ * jacobi3d_sweep: the fused residual is that of u_in.
+ */
+int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
+                    double h, uint32_t flags, double* resid_out, void* stream);
+
+/*
  * ||f - A u||_2 over the interior, in FP64 (u and f FP64).  `out` is a
  * device address (or host, with J3D_HOST_RESULT in flags).
  */
@@ -242,14 +253,22 @@ int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
  * Blocks until done. */
 int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* stream);
 
-/* Autotune the single-grid sweep of this element type and interior shape on
+/* Kernel kinds for the single-grid tuning calls: J3D_F64 and J3D_F32 name
+ * the one-sweep passes of that element type, J3D_KIND_F64X2 the two-sweep
+ * FP64 pass of jacobi3d_sweep2 (rows x rows-per-thread between 4 and 32:
+ * a block of that many rows has that many minus 2 output rows; variant
+ * bits 2, 4, 16 as above, no LDS bit since the pass always uses LDS). */
+#define J3D_KIND_F64X2 2
+
+/* Autotune the single-grid pass of this kind and interior shape on
  * library-allocated scratch arrays; the choice is used by jacobi3d_sweep,
- * residual_l2 and poisson_solve for this shape from then on.  Blocks. */
-int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
+ * jacobi3d_sweep2, residual_l2 and poisson_solve for this shape from then
+ * on.  Blocks. */
+int j3d_autotune_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
                         void* stream);
 
-/* Pin the tile shape used for single-grid calls on this dtype and shape. */
-int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t);
+/* Pin the tile shape used for single-grid calls of this kind and shape. */
+int j3d_tune_set_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t);
 
 /* ------------------------------------------------------------------ */
 /* Serving: continuous batching of Poisson solves under a memory budget */

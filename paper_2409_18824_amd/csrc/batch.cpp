@@ -369,6 +369,52 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
   return rc;
 }
 
+// Time F_WRITE passes of every listed tile shape; return the fastest.
+template <typename Launcher>
+int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, Launcher&& launch) {
+  hipEvent_t e0, e1;
+  J3D_HIP(hipEventCreate(&e0));
+  J3D_HIP(hipEventCreate(&e1));
+  float bt = 1e30f;
+  int rc = J3D_OK;
+  for (const TileCfg& c : list) {
+    rc = launch(c);
+    float ms_min = 1e30f;
+    for (int r = 0; r < 3 && rc == J3D_OK; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(J3D_EHIP, "event record"); break; }
+      rc = launch(c);
+      if (rc != J3D_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(J3D_EHIP, "event sync");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (rc != J3D_OK) break;
+    if (ms_min < bt) {
+      bt = ms_min;
+      *best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+std::vector<TileCfg> sweep2_candidates() {
+  std::vector<TileCfg> v;
+  for (int rows : {1, 2, 4, 8})
+    for (int var : {0, 4, 2, 6, 16, 20})
+      for (int planes : {8, 16, 32, 64})
+        for (int order : {0, 1, 2}) {
+          TileCfg c{rows, planes, var, 0, order};
+          if (tile2_cfg_supported(c)) v.push_back(c);
+        }
+  return v;
+}
+
 }  // namespace
 
 bool tune_cache_lookup_single(int dtype, int nx, int ny, int nz, TileCfg* out) {
@@ -501,14 +547,16 @@ extern "C" int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* bes
 
 extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
                                    void* stream) {
-  if (dtype != J3D_F64 && dtype != J3D_F32) return fail(J3D_EDTYPE, "dtype must be F64 or F32");
+  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2)
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or J3D_KIND_F64X2");
   if (nx < 1 || ny < 1 || nz < 1) return fail(J3D_EINVAL, "extents must be >= 1");
   if (best == nullptr) return fail(J3D_EINVAL, "best: null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int es = dtype == J3D_F64 ? 8 : 4;
+  const bool pair = dtype == J3D_KIND_F64X2;
+  const int es = dtype == J3D_F32 ? 4 : 8;
   const int align = 128 / es;
   Field a;
-  a.dtype = dtype;
+  a.dtype = pair ? J3D_F64 : dtype;
   a.esize = es;
   a.ex = nx + 2;
   a.ey = ny + 2;
@@ -534,8 +582,13 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
     J3D_HIP(launch_pass_one(dtype, F_WRITE, c, g, nullptr, nullptr, st));
     return J3D_OK;
   };
+  auto launch2 = [&](const TileCfg& c) -> int {
+    GridArgs g = make_args2(&u, &o, &f, 0.01, c);
+    J3D_HIP(launch_sweep2_one(F_WRITE, c, g, nullptr, nullptr, st));
+    return J3D_OK;
+  };
   TileCfg c{};
-  int rc = time_candidates(st, &c, launch);
+  int rc = pair ? time_list(st, &c, sweep2_candidates(), launch2) : time_candidates(st, &c, launch);
   (void)hipStreamSynchronize(st);
   (void)hipFree(mem);
   if (rc != J3D_OK) return rc;
@@ -551,8 +604,10 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
 extern "C" int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t) {
   if (t == nullptr) return fail(J3D_EINVAL, "tune: null pointer");
   TileCfg c{t->rows, t->planes, t->variant, t->persistent, t->order};
-  if (!tile_cfg_supported(c)) return fail(J3D_EINVAL, "unsupported tile shape");
-  if (dtype != J3D_F64 && dtype != J3D_F32) return fail(J3D_EDTYPE, "dtype must be F64 or F32");
+  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2)
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or J3D_KIND_F64X2");
+  if (!(dtype == J3D_KIND_F64X2 ? tile2_cfg_supported(c) : tile_cfg_supported(c)))
+    return fail(J3D_EINVAL, "unsupported tile shape");
   tune_store(single_key(dtype, nx, ny, nz), c);
   return J3D_OK;
 }

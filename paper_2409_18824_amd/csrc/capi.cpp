@@ -46,6 +46,17 @@ TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   return c;
 }
 
+TileCfg default_cfg2(int nx, int ny, int nz) {
+  TileCfg c;
+  if (tune_cache_lookup_single(J3D_KIND_F64X2, nx, ny, nz, &c)) return c;
+  c.rows = 8;
+  c.planes = 32;
+  c.variant = 4;
+  c.persistent = 0;
+  c.order = 1;
+  return c;
+}
+
 // Sum-of-squares pass over (u, f) followed by the deterministic reduce into
 // `out` (device).  flags is F_RES (residual of u) or F_NORM (norm of f).
 static int norm_pass(unsigned flags, const Field& u, const Field& f, const Field* o, double h,
@@ -125,6 +136,42 @@ int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_arra
   const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
   J3D_HIP(launch_pass_one(J3D_F64, F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
+  const bool host = (flags & J3D_HOST_RESULT) != 0;
+  double* dst = host ? &s->ctl->value : resid_out;
+  J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));
+  if (host) {
+    J3D_HIP(hipMemcpyAsync(&s->ctl_host->value, &s->ctl->value, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    *resid_out = s->ctl_host->value;
+  }
+  return J3D_OK;
+}
+
+int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+                    uint32_t flags, double* resid_out, void* stream) {
+  Field a, b, c;
+  J3D_TRY(check_field(u_in, J3D_F64, &a, "u_in"));
+  J3D_TRY(check_field(u_out, J3D_F64, &b, "u_out"));
+  J3D_TRY(check_field(f, J3D_F64, &c, "f"));
+  J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
+  J3D_TRY(check_same_interior(a, c, "u_in", "f"));
+  J3D_TRY(check_h(h));
+  if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
+  if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const TileCfg cfg = default_cfg2(a.nx(), a.ny(), a.nz());
+  GridArgs g = make_args2(&a, &b, &c, h, cfg);
+  if (resid_out == nullptr) {
+    J3D_HIP(launch_sweep2_one(F_WRITE, cfg, g, nullptr, nullptr, st));
+    return J3D_OK;
+  }
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  J3D_HIP(launch_sweep2_one(F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
   const bool host = (flags & J3D_HOST_RESULT) != 0;
   double* dst = host ? &s->ctl->value : resid_out;
   J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));

@@ -57,6 +57,16 @@ bool tile_cfg_supported(const TileCfg& c);
 // Number of tiles of one grid under a tile shape.
 void tile_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
 
+// Tile shapes of the two-sweep pass: rows in {4, 8, 16} (a block of 64 x rows
+// columns with 62 x (rows - 2) outputs), variant 0 or 4 (nontemporal stores).
+bool tile2_cfg_supported(const TileCfg& c);
+void tile2_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
+
+// Two FP64 sweeps in one pass: g.o = J(J(g.u)); flags F_WRITE, optionally
+// with F_RES (residual of g.u into partials, one slot per tile).
+hipError_t launch_sweep2_one(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
+                             const int* done, hipStream_t st);
+
 // Number of resident workgroups used for persistent launches.
 int persistent_grid(const TileCfg& c);
 

@@ -11,7 +11,7 @@
 // batch it was computed in.
 #include <math.h>
 
-#include "sweep.h"
+#include "sweep2.h"
 
 namespace j3d {
 namespace {
@@ -191,6 +191,30 @@ void tile_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int
   *tx = (nx + WAVE - 1) / WAVE;
   *ty = (ny + tr - 1) / tr;
   *tz = (nz + c.planes - 1) / c.planes;
+}
+
+bool tile2_cfg_supported(const TileCfg& c) {
+  const bool var_ok = c.variant == 0 || c.variant == 4 || c.variant == 2 || c.variant == 6 ||
+                      c.variant == 16 || c.variant == 20;
+  const bool rows_ok = c.rows == 1 || c.rows == 2 || c.rows == 4 || c.rows == 8;
+  if (!var_ok || !rows_ok) return false;
+  const int tr = c.rows * sweep_detail::rows_per_thread(c.variant);
+  return tr >= 4 && tr <= 32 && c.order >= 0 && c.order <= 2 && c.planes >= 1 && c.planes <= 4096 &&
+         (c.persistent == 0 || c.persistent == 1);
+}
+
+void tile2_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz) {
+  const int w = sweep_detail::kSweep2Cols, h = c.rows * sweep_detail::rows_per_thread(c.variant) - 2;
+  *tx = (nx + w - 1) / w;
+  *ty = (ny + h - 1) / h;
+  *tz = (nz + c.planes - 1) / c.planes;
+}
+
+hipError_t launch_sweep2_one(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
+                             const int* done, hipStream_t st) {
+  if (!tile2_cfg_supported(c)) return hipErrorInvalidValue;
+  sweep_detail::Launch L{false, &c, &g, nullptr, 1, 0, partials, done, st};
+  return sweep_detail::dispatch_sweep2(flags, L);
 }
 
 int persistent_grid(const TileCfg& c) {

@@ -132,6 +132,13 @@ GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* 
   return g;
 }
 
+GridArgs make_args2(const Field* u, const Field* o, const Field* f, double h, const TileCfg& c) {
+  GridArgs g = make_args(u, o, f, nullptr, nullptr, h, c, 0);
+  tile2_counts(g.nx, g.ny, g.nz, c, &g.tiles_x, &g.tiles_y, &g.tiles_z);
+  g.chunk = (g.tiles_x * g.tiles_y + 7) / 8;
+  return g;
+}
+
 int dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
   hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);

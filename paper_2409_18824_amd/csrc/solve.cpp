@@ -89,8 +89,11 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   Scratch* s = nullptr;
   J3D_TRY(get_scratch(st, &s));
   const TileCfg cfg = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());
+  const TileCfg cfg2 = default_cfg2(u.nx(), u.ny(), u.nz());
   const long long S = o.max_sweeps;
   const long long c = o.check_every;
+  // Two-sweep passes when every check falls on an even sweep count.
+  const bool pairs = (c % 2) == 0;
 
   // The second ping-pong array has u's layout and starts as a copy of u
   // (which gives it the same halo).
@@ -99,10 +102,16 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   w.base = static_cast<char*>(s->work);
   J3D_HIP(hipMemcpyAsync(w.base, u.base, u.span_bytes(), hipMemcpyDeviceToDevice, st));
 
-  const GridArgs fwd = make_args(&u, &w, &f, nullptr, nullptr, h, cfg, 0);  // u -> w
-  const GridArgs bwd = make_args(&w, &u, &f, nullptr, nullptr, h, cfg, 0);  // w -> u
-  const int nt = fwd.tiles_x * fwd.tiles_y * fwd.tiles_z;
-  J3D_TRY(ensure_partials(s, nt));
+  const Field* buf[2] = {&u, &w};
+  GridArgs one[2], two[2], resid[2];
+  for (int b = 0; b < 2; ++b) {
+    one[b] = make_args(buf[b], buf[1 - b], &f, nullptr, nullptr, h, cfg, 0);
+    two[b] = make_args2(buf[b], buf[1 - b], &f, h, cfg2);
+    resid[b] = make_args(buf[b], nullptr, &f, nullptr, nullptr, h, cfg, 0);
+  }
+  const int nt1 = one[0].tiles_x * one[0].tiles_y * one[0].tiles_z;
+  const int nt2 = two[0].tiles_x * two[0].tiles_y * two[0].tiles_z;
+  J3D_TRY(ensure_partials(s, std::max(nt1, nt2)));
   const long long nchecks = S / c + 1;
   J3D_TRY(ensure_hist(s, (size_t)nchecks));
 
@@ -110,56 +119,75 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   J3D_TRY(norm_f(f, cfg, s, st));
   int* done = &s->ctl->done;
 
+  // which_at[q]: buffer holding the iterate whose residual is check q
+  std::vector<unsigned char> which_at((size_t)nchecks, 0);
   const long long points = (long long)u.nx() * u.ny() * u.nz();
-  const long long chunk = chunk_sweeps(points, 24.0, c);
+  const long long chunk = chunk_sweeps(points, pairs ? 12.0 : 24.0, c);
   long long sw = 0;
+  int cur = 0;
   int slot = 0;
   bool seen = false;
   while (sw < S && !seen) {
     const long long end = std::min(S, sw + chunk);
-    for (; sw < end; ++sw) {
+    while (sw < end) {
       const bool check = (sw % c) == 0;
-      const GridArgs& g = (sw & 1) ? bwd : fwd;
-      J3D_HIP(launch_pass_one(J3D_F64, F_WRITE | (check ? F_RES : 0u), cfg, g, s->partials, done, st));
-      if (check)
-        J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + sw / c, &s->ctl->normf, o.rtol,
-                                  sw / c, done, &s->ctl->conv_at, &s->ctl->nonfinite, st));
+      const long long q = sw / c;  // check index served by this pass's fused residual
+      if (check) which_at[(size_t)q] = (unsigned char)cur;
+      const unsigned fl = F_WRITE | (check ? F_RES : 0u);
+      int nt;
+      if (pairs && sw + 2 <= S) {
+        J3D_HIP(launch_sweep2_one(fl, cfg2, two[cur], s->partials, done, st));
+        nt = nt2;
+        sw += 2;
+      } else {
+        J3D_HIP(launch_pass_one(J3D_F64, fl, cfg, one[cur], s->partials, done, st));
+        nt = nt1;
+        sw += 1;
+      }
+      if (check) {
+        J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + q, &s->ctl->normf, o.rtol, q, done,
+                                  &s->ctl->conv_at, &s->ctl->nonfinite, st));
+      }
+      cur = 1 - cur;
     }
     J3D_TRY(publish_done(s, slot, st));
     if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
     ++slot;
   }
   // Residual of the iterate after the last sweep (a check when S % c == 0).
+  // When the loop stopped early (converged), every kernel below is skipped.
   {
-    const Field& cur = (S & 1) ? w : u;
-    GridArgs g = make_args(&cur, nullptr, &f, nullptr, nullptr, h, cfg, 0);
-    J3D_HIP(launch_pass_one(J3D_F64, F_RES, cfg, g, s->partials, done, st));
+    if (S % c == 0) which_at[(size_t)(S / c)] = (unsigned char)cur;
+    J3D_HIP(launch_pass_one(J3D_F64, F_RES, cfg, resid[cur], s->partials, done, st));
     if (S % c == 0)
-      J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + S / c, &s->ctl->normf, o.rtol, S / c,
+      J3D_HIP(launch_reduce_one(s->partials, 0, nt1, s->hist + S / c, &s->ctl->normf, o.rtol, S / c,
                                 done, &s->ctl->conv_at, &s->ctl->nonfinite, st));
     else
-      J3D_HIP(launch_reduce_one(s->partials, 0, nt, &s->ctl->value, nullptr, 0.0, 0, done, nullptr,
+      J3D_HIP(launch_reduce_one(s->partials, 0, nt1, &s->ctl->value, nullptr, 0.0, 0, done, nullptr,
                                 nullptr, st));
   }
   Control ctl;
   J3D_TRY(read_control(s, &ctl, st));
   long long sweeps, nh;
+  int at;
   if (ctl.done) {
     sweeps = ctl.conv_at * c;
     nh = ctl.conv_at + 1;
+    at = which_at[(size_t)ctl.conv_at];
   } else {
     sweeps = S;
     nh = S / c + 1;
+    at = cur;
   }
   std::vector<double> hist;
   J3D_TRY(read_history(s, nh, &hist, st));
-  const double resid = (ctl.done || S % c == 0) ? hist[(size_t)nh - 1] : ctl.value;
-  if (sweeps & 1) {
+  const double resid_v = (ctl.done || S % c == 0) ? hist[(size_t)nh - 1] : ctl.value;
+  if (at == 1) {
     J3D_HIP(launch_copy_interior(reinterpret_cast<const double*>(w.base), reinterpret_cast<double*>(u.base),
                                  u.nx(), u.ny(), u.nz(), w.sy, w.sz, u.sy, u.sz, st));
     J3D_HIP(hipStreamSynchronize(st));
   }
-  fill_result(res, sweeps, resid, hist, ctl.normf, ctl.done != 0, ctl.nonfinite != 0, o);
+  fill_result(res, sweeps, resid_v, hist, ctl.normf, ctl.done != 0, ctl.nonfinite != 0, o);
   return ctl.nonfinite ? fail(J3D_ENONFINITE, "residual became non-finite") : J3D_OK;
 }
 

@@ -32,6 +32,7 @@ F64, F32 = 0, 1
 OK, EINVAL, EDTYPE, EALIAS, ENOMEM, EBUDGET, EHIP, ENONFINITE, EAGAIN, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 HOST_RESULT = 1
 MODE_FP64, MODE_MIXED = 0, 1
+KIND_F64X2 = 2  # tuning kind of the two-sweep FP64 pass
 
 _ERRNAMES = {0: "OK", -1: "EINVAL", -2: "EDTYPE", -3: "EALIAS", -4: "ENOMEM", -5: "EBUDGET",
              -6: "EHIP", -7: "ENONFINITE", -8: "EAGAIN", -9: "ESTATE"}
@@ -105,6 +106,7 @@ _SIGS = {
     "j3d_element_offset": ([_P(J3DArray), _I64, _I64, _I64, _P(_I64)], ctypes.c_int),
     "j3d_check_array": ([_P(J3DArray), _I32], ctypes.c_int),
     "jacobi3d_sweep": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
+    "jacobi3d_sweep2": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "residual_l2": ([_P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "poisson_solve": ([_P(J3DArray), _P(J3DArray), _D, _P(SolveOpts), _P(SolveResult), _V], ctypes.c_int),
     "j3d_tune_count": ([], ctypes.c_int),
@@ -276,6 +278,23 @@ def jacobi3d_sweep(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=N
     ptr = None if resid_out is None else ctypes.c_void_p(resid_out.data_ptr())
     _check(_lib.jacobi3d_sweep(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h), flags, ptr, st),
            "jacobi3d_sweep")
+    return None
+
+
+def jacobi3d_sweep2(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=None, host_result=False,
+                    stream=None, flags: int = 0):
+    """Two sweeps in one pass: u_out = J(J(u_in)).  Residual (of u_in) as in jacobi3d_sweep."""
+    a, b, c = u_in.desc(), u_out.desc(), f.desc()
+    st = _stream_handle(stream)
+    if host_result:
+        out = ctypes.c_double()
+        _check(_lib.jacobi3d_sweep2(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h),
+                                    flags | HOST_RESULT, ctypes.cast(ctypes.byref(out), ctypes.c_void_p), st),
+               "jacobi3d_sweep2")
+        return out.value
+    ptr = None if resid_out is None else ctypes.c_void_p(resid_out.data_ptr())
+    _check(_lib.jacobi3d_sweep2(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h), flags, ptr, st),
+           "jacobi3d_sweep2")
     return None
 
 

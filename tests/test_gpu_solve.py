@@ -29,7 +29,8 @@ def test_small_plain_100_sweeps_residual_every_sweep():
     assert np.array_equal(du.to_numpy(), uo)
 
 
-@pytest.mark.parametrize("max_sweeps,check_every", [(0, 1), (7, 3), (10, 5), (1, 1)])
+@pytest.mark.parametrize("max_sweeps,check_every", [(0, 1), (7, 3), (10, 5), (1, 1), (10, 2), (9, 4), (1, 2),
+                                                   (3, 2), (0, 2)])
 def test_plain_cadence_edges(max_sweeps, check_every):
     n = (9, 11, 6)
     say("cadence", max_sweeps, check_every)

@@ -72,6 +72,51 @@ def test_sweep_fp64_parity(shape, tune):
     assert j3d.residual_l2(du, df, h) == float(r.item())
 
 
+TUNES2 = [(4, 8, 0, 0, 0), (8, 32, 4, 0, 1), (4, 16, 4, 0, 2), (4, 1, 0, 1, 1), (8, 3, 0, 1, 2),
+          (2, 128, 2, 0, 0), (1, 16, 20, 0, 1), (4, 8, 16, 1, 2), (8, 16, 6, 0, 0), (2, 32, 20, 0, 2)]
+SHAPES2 = [(1, 1, 1), (3, 4, 5), (62, 6, 9), (63, 7, 10), (130, 30, 17), (17, 45, 64), (200, 14, 3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES2)
+@pytest.mark.parametrize("tune", TUNES2)
+def test_sweep2_equals_two_sweeps(shape, tune):
+    nx, ny, nz = shape
+    say("sweep2", shape, tune)
+    u, f, h = make_inputs(nx, ny, nz, seed=4)
+    j3d.j3d_tune_set_single(j3d.KIND_F64X2, nx, ny, nz, tune)
+    du = j3d.FArray.from_numpy(u)
+    dv = j3d.FArray.from_numpy(u)
+    dv.view()[1:-1, 1:-1, 1:-1] = -7.0
+    df = j3d.FArray.from_numpy(f, ld_extra=3)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep2(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    want = oracle.sweep(oracle.sweep(u, f, h), f, h)
+    got = dv.to_numpy()
+    assert np.array_equal(got, want), "max diff %g" % np.max(np.abs(got - want))
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+    assert np.array_equal(du.to_numpy(), u)  # input untouched
+
+
+def test_sweep2_full_size_512():
+    n = 512
+    say("512^3 sweep2")
+    h = 1.0 / (n + 1)
+    f = synth.manufactured_f(n, n, n, h)
+    du = j3d.FArray.empty(n, n, n)
+    j3d.j3d_fill_uniform(du, 2, synth.STREAM_U0, 0.0, 1.0)
+    dv = j3d.FArray.empty(n, n, n)
+    df = j3d.FArray.from_numpy(f)
+    j3d.j3d_autotune_single(j3d.KIND_F64X2, n, n, n)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep2(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    u = du.to_numpy()
+    want = oracle.sweep(oracle.sweep(u, f, h), f, h)
+    assert np.array_equal(dv.to_numpy()[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1])
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+
+
 @pytest.mark.parametrize("tune", [(1, 8, 0, 0, 0), (4, 32, 1, 0, 0), (8, 16, 0, 1, 0), (2, 16, 6, 0, 2), (4, 64, 7, 1, 0),
                                   (1, 8, 22, 0, 1), (2, 4, 23, 1, 0)])
 def test_sweep_fp32_parity(tune):
