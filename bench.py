@@ -50,7 +50,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP_F64 = 24.0
 
 
-KERNEL_SOURCES = ("sweep.h", "kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "j3d_internal.h")
+KERNEL_SOURCES = ("sweep.h", "sweep2.h", "kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip",
+                  "j3d_internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -122,7 +123,7 @@ def main():
                     help="serve: admission target for active interior points (0: no limit)")
     ap.add_argument("--rtol", type=float, default=1e-8, help="mixed: target relative residual")
     ap.add_argument("--tile", default=None,
-                    help="pin the tile shape as rows,planes,variant,persistent,order instead of autotuning")
+                    help="pin the tile shape as rows,planes,variant,persistent,order[,cols] instead of autotuning")
     ap.add_argument("--probe", action="store_true",
                     help="also time the copy kernel on 2 x 1 GiB (achievable-bandwidth ceiling)")
     args = ap.parse_args()
@@ -164,7 +165,7 @@ def main():
         tune = j3d.j3d_autotune_single(kind, n, n, n)
         if P == 2:
             j3d.j3d_autotune_single(j3d.F64, n, n, n)  # the standalone residual pass
-    print("[bench] tile shape (rows, planes, variant, persistent) = %s" % (tune,), file=sys.stderr, flush=True)
+    print("[bench] tile shape (rows, planes, variant, persistent, order, cols) = %s" % (tune,), file=sys.stderr, flush=True)
 
     nres = S // E + 1
     resid = torch.zeros(nres, dtype=torch.float64, device="cuda")

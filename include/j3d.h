@@ -133,11 +133,12 @@ int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_arra
 
 /*
  * Two Jacobi sweeps in one pass over memory: u_out = J(J(u_in; f, h)), all
- * three arrays FP64.  The intermediate iterate stays on chip (temporal
- * blocking in z), so the pass streams u_in and f once and writes u_out once
- * for two sweeps' worth of updates; every point is computed exactly as two
- * jacobi3d_sweep calls would (bit-identical).  resid_out and flags are as in
- * jacobi3d_sweep: the fused residual is that of u_in.
+ * three arrays FP64 or all FP32.  The intermediate iterate stays on chip
+ * (temporal blocking in z), so the pass streams u_in and f once and writes
+ * u_out once for two sweeps' worth of updates; every point is computed
+ * exactly as two jacobi3d_sweep calls would (bit-identical).  resid_out and
+ * flags are as in jacobi3d_sweep: the fused residual is that of u_in and
+ * needs FP64 arrays.
  */
 int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
                     double h, uint32_t flags, double* resid_out, void* stream);
@@ -207,8 +208,9 @@ typedef struct j3d_grid {
 } j3d_grid;
 
 /*
- * Tile shape of the sweep kernels.  A workgroup of `rows` 64-lane wavefronts
- * sweeps 64 x-points x (rows x rows-per-thread) y-rows x `planes` z-planes,
+ * Tile shape of the sweep kernels.  A workgroup of rows x cols 64-lane
+ * wavefronts sweeps 64*cols x-points x (rows x rows-per-thread) y-rows x
+ * `planes` z-planes,
  * marching through z with the previous, current and next plane in
  * registers.  variant is a bit set: 1 stages each plane in LDS (else x/y
  * neighbours are read through the cache); 2 and 16 give each thread
@@ -217,7 +219,8 @@ typedef struct j3d_grid {
  * fixed grid of workgroups that stride over the tile list, 0 one workgroup
  * per tile.  order maps dispatch order to tiles: 0 gives each of the 8 XCDs
  * one contiguous block of tiles, 1 keeps the launch order, 2 cuts each z-slab
- * into 8 contiguous chunks, one per XCD.
+ * into 8 contiguous chunks, one per XCD.  cols is the number of wavefronts
+ * side by side along x (1, 2 or 4): a tile is 64 x cols points wide.
  */
 typedef struct j3d_tune {
   int32_t rows;
@@ -225,6 +228,7 @@ typedef struct j3d_tune {
   int32_t variant;
   int32_t persistent;
   int32_t order;
+  int32_t cols;
 } j3d_tune;
 
 /* Number of supported tile shapes, and the i-th one (host-only). */
@@ -240,9 +244,16 @@ int j3d_tune_get(int32_t index, j3d_tune* out);
  * ngrids * (nsweeps/resid_every + 1) doubles: row g holds ||f - A u||_2 of
  * grid g after sweeps 0, e, 2e, ... (e = resid_every), fused into the
  * following sweep where there is one.  Each grid's numbers equal those of
- * the same grid swept alone with the same tile shape, bit for bit.
+ * the same grid swept alone with the same tile shapes and pass kind (one or
+ * two sweeps per pass, below), bit for bit; the iterates are the same bit
+ * for bit in every case.
  * tune = NULL selects the tile shape with the autotuner (timed once per
  * batch shape class and cached; J3D_TUNE_CACHE names an optional file).
+ * When nsweeps >= 2 and resid_every is even (or resid_out is NULL), sweeps
+ * run two per pass over memory (as jacobi3d_sweep2) if that is faster on
+ * this batch shape class, timed once per process; the environment variable
+ * J3D_BATCH_PAIRS=0 or =1 forces one-sweep or two-sweep passes.  Results
+ * are the same bit for bit either way.
  */
 int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
                          int32_t resid_every, double* resid_out, const j3d_tune* tune,
@@ -254,11 +265,14 @@ int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
 int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* stream);
 
 /* Kernel kinds for the single-grid tuning calls: J3D_F64 and J3D_F32 name
- * the one-sweep passes of that element type, J3D_KIND_F64X2 the two-sweep
- * FP64 pass of jacobi3d_sweep2 (rows x rows-per-thread between 4 and 32:
- * a block of that many rows has that many minus 2 output rows; variant
- * bits 2, 4, 16 as above, no LDS bit since the pass always uses LDS). */
+ * the one-sweep passes of that element type, J3D_KIND_F64X2 and
+ * J3D_KIND_F32X2 the two-sweep passes of jacobi3d_sweep2 (the FP32 one also
+ * runs the correction sweeps of the mixed solve).  Two-sweep shapes have
+ * rows x rows-per-thread between 4 and 32 (a block of that many rows has
+ * that many minus 2 output rows, and 64*cols - 2 output columns); variant
+ * bits 2, 4, 16 as above, no LDS bit since the pass always uses LDS. */
 #define J3D_KIND_F64X2 2
+#define J3D_KIND_F32X2 3
 
 /* Autotune the single-grid pass of this kind and interior shape on
  * library-allocated scratch arrays; the choice is used by jacobi3d_sweep,

@@ -69,7 +69,8 @@ void tune_load_locked() {
   if (!fp) return;
   char key[128];
   TileCfg c;
-  while (fscanf(fp, "%127s %d %d %d %d %d", key, &c.rows, &c.planes, &c.variant, &c.persistent, &c.order) == 6)
+  while (fscanf(fp, "%127s %d %d %d %d %d %d", key, &c.rows, &c.planes, &c.variant, &c.persistent, &c.order,
+                &c.cols) == 7)
     if (tile_cfg_supported(c)) g_tune[key] = c;
   fclose(fp);
 }
@@ -83,8 +84,8 @@ void tune_store(const std::string& key, const TileCfg& c) {
   FILE* fp = fopen(path, "w");
   if (!fp) return;
   for (auto& kv : g_tune)
-    fprintf(fp, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.rows, kv.second.planes,
-            kv.second.variant, kv.second.persistent, kv.second.order);
+    fprintf(fp, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.rows, kv.second.planes,
+            kv.second.variant, kv.second.persistent, kv.second.order, kv.second.cols);
   fclose(fp);
 }
 
@@ -95,6 +96,24 @@ bool tune_lookup(const std::string& key, TileCfg* out) {
   if (it == g_tune.end()) return false;
   *out = it->second;
   return true;
+}
+
+// Two-sweep choice per batch shape class: the shape and whether it beats
+// one-sweep passes (kept for the life of the process).
+std::map<std::string, std::pair<TileCfg, bool>> g_pair;
+
+bool pair_lookup(const std::string& key, TileCfg* c2, bool* use) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_pair.find(key);
+  if (it == g_pair.end()) return false;
+  *c2 = it->second.first;
+  *use = it->second.second;
+  return true;
+}
+
+void pair_store(const std::string& key, const TileCfg& c2, bool use) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_pair[key] = std::make_pair(c2, use);
 }
 
 // ---------------------------------------------------------------------
@@ -167,14 +186,31 @@ void build_tables(const BatchFields& bf, const TileCfg& c, std::vector<GridArgs>
   *ntiles = tile0;
 }
 
+// Two-sweep tables (their own tile numbering): tab2[0]: u_a -> u_b,
+// tab2[1]: u_b -> u_a.
+void build_tables2(const BatchFields& bf, const TileCfg& c2, std::vector<GridArgs> tab2[2], int* ntiles) {
+  const int n = (int)bf.a.size();
+  for (int t = 0; t < 2; ++t) tab2[t].resize(n);
+  int tile0 = 0;
+  for (int g = 0; g < n; ++g) {
+    tab2[0][g] = make_args2(&bf.a[g], &bf.b[g], &bf.f[g], nullptr, bf.h[g], c2, tile0);
+    tab2[1][g] = make_args2(&bf.b[g], &bf.a[g], &bf.f[g], nullptr, bf.h[g], c2, tile0);
+    tab2[0][g].id = tab2[1][g].id = g;
+    tile0 += tab2[0][g].tiles_x * tab2[0][g].tiles_y * tab2[0][g].tiles_z;
+  }
+  *ntiles = tile0;
+}
+
 // ---------------------------------------------------------------------
 // Plans (device tables + captured graph), cached per call signature
 // ---------------------------------------------------------------------
 struct Plan {
   std::string key;
   int device = 0;
-  int ngrids = 0, ntiles = 0;
-  GridArgs* tab = nullptr;  // device, 4 * ngrids
+  int ngrids = 0, ntiles = 0, ntiles2 = 0;
+  bool pairs = false;       // two sweeps per pass where the cadence allows
+  TileCfg c2{};             // tile shape of the two-sweep passes
+  GridArgs* tab = nullptr;  // device: 4 * ngrids one-sweep, then 2 * ngrids two-sweep entries
   double* partials = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -202,23 +238,50 @@ int capture_stream(int dev, hipStream_t* out) {
   return J3D_OK;
 }
 
-// Enqueue the whole batch on `st` (used for capture).
+// Enqueue the whole batch on `st` (used for capture).  With pairs, sweeps
+// run two per pass; when the number of pairs is odd the first pair runs as
+// two one-sweep passes, so that the number of passes has the parity of
+// nsweeps and the result lands in u_a exactly when nsweeps is even.
 int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, double* resid_out,
                   hipStream_t st) {
-  const GridArgs* tab = p.tab;
   const int n = p.ngrids;
   const int nres = resid_out ? nsweeps / every + 1 : 0;
-  for (int s = 0; s < nsweeps; ++s) {
+  int s = 0;
+  int buf = 0;  // 0: the current iterate is in u_a
+  auto one = [&]() -> int {
     const bool check = resid_out && (s % every) == 0;
-    const GridArgs* t = tab + (size_t)(s & 1) * n;
+    const GridArgs* t = p.tab + (size_t)buf * n;
     J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), c, t, n, p.ntiles, p.partials,
                               nullptr, st));
     if (check)
       J3D_HIP(launch_reduce_batch(p.partials, t, n, resid_out, nres, s / every, nullptr, nullptr, 0,
                                   nullptr, nullptr, nullptr, st));
+    s += 1;
+    buf ^= 1;
+    return J3D_OK;
+  };
+  auto two = [&]() -> int {
+    const bool check = resid_out && (s % every) == 0;
+    const GridArgs* t = p.tab + (size_t)(4 + buf) * n;
+    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), p.c2, t, n, p.ntiles2, p.partials,
+                                nullptr, st));
+    if (check)
+      J3D_HIP(launch_reduce_batch(p.partials, t, n, resid_out, nres, s / every, nullptr, nullptr, 0,
+                                  nullptr, nullptr, nullptr, st));
+    s += 2;
+    buf ^= 1;
+    return J3D_OK;
+  };
+  int npairs = p.pairs ? nsweeps / 2 : 0;
+  if (npairs & 1) {
+    J3D_TRY(one());
+    J3D_TRY(one());
+    --npairs;
   }
+  for (int q = 0; q < npairs; ++q) J3D_TRY(two());
+  while (s < nsweeps) J3D_TRY(one());
   if (resid_out && nsweeps % every == 0) {
-    const GridArgs* t = tab + (size_t)(2 + (nsweeps & 1)) * n;
+    const GridArgs* t = p.tab + (size_t)(2 + buf) * n;
     J3D_HIP(launch_pass_batch(J3D_F64, F_RES, c, t, n, p.ntiles, p.partials, nullptr, st));
     J3D_HIP(launch_reduce_batch(p.partials, t, n, resid_out, nres, nsweeps / every, nullptr, nullptr,
                                 0, nullptr, nullptr, nullptr, st));
@@ -226,23 +289,27 @@ int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, doubl
   return J3D_OK;
 }
 
-int make_plan(const std::string& key, const BatchFields& bf, const TileCfg& c, int nsweeps, int every,
-              double* resid_out, Plan** out) {
+int make_plan(const std::string& key, const BatchFields& bf, const TileCfg& c, bool pairs, const TileCfg& c2,
+              int nsweeps, int every, double* resid_out, Plan** out) {
   int dev = 0;
   J3D_HIP(hipGetDevice(&dev));
   Plan* p = new Plan();
   p->key = key;
   p->device = dev;
   p->ngrids = (int)bf.a.size();
-  std::vector<GridArgs> tab[4];
+  p->pairs = pairs;
+  p->c2 = c2;
+  std::vector<GridArgs> tab[4], tab2[2];
   build_tables(bf, c, tab, &p->ntiles);
+  build_tables2(bf, c2, tab2, &p->ntiles2);
   std::vector<GridArgs> flat;
   for (int t = 0; t < 4; ++t) flat.insert(flat.end(), tab[t].begin(), tab[t].end());
+  for (int t = 0; t < 2; ++t) flat.insert(flat.end(), tab2[t].begin(), tab2[t].end());
   void* mem = nullptr;
   int rc = dev_alloc(&mem, flat.size() * sizeof(GridArgs), "batch table");
   if (rc == J3D_OK) {
     p->tab = static_cast<GridArgs*>(mem);
-    rc = dev_alloc(&mem, (size_t)p->ntiles * sizeof(double), "batch partials");
+    rc = dev_alloc(&mem, (size_t)std::max(p->ntiles, p->ntiles2) * sizeof(double), "batch partials");
   }
   if (rc == J3D_OK) p->partials = static_cast<double*>(mem);
   if (rc != J3D_OK) {
@@ -292,7 +359,7 @@ std::vector<TileCfg> candidates() {
   for (int i = 0; i < n; ++i) {
     j3d_tune t;
     j3d_tune_get(i, &t);
-    v.push_back(TileCfg{t.rows, t.planes, t.variant, t.persistent, t.order});
+    v.push_back(TileCfg{t.rows, t.planes, t.variant, t.persistent, t.order, t.cols});
   }
   return v;
 }
@@ -306,10 +373,10 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
   hipEvent_t e0, e1;
   J3D_HIP(hipEventCreate(&e0));
   J3D_HIP(hipEventCreate(&e1));
-  std::map<std::tuple<int, int, int, int, int>, float> seen;
+  std::map<std::tuple<int, int, int, int, int, int>, float> seen;
   int rc = J3D_OK;
   auto time_of = [&](const TileCfg& c, float* out) -> int {
-    auto key = std::make_tuple(c.rows, c.planes, c.variant, c.persistent, c.order);
+    auto key = std::make_tuple(c.rows, c.planes, c.variant, c.persistent, c.order, c.cols);
     auto it = seen.find(key);
     if (it != seen.end()) {
       *out = it->second;
@@ -338,7 +405,7 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
       planes_set.push_back(c.planes);
     if (std::find(var_set.begin(), var_set.end(), c.variant) == var_set.end()) var_set.push_back(c.variant);
   }
-  TileCfg b{1, 16, 20, 0, 1};
+  TileCfg b{1, 16, 20, 0, 1, 1};
   float bt = 1e30f;
   auto consider = [&](const TileCfg& c) -> int {
     float t = 0.f;
@@ -354,12 +421,18 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
     if (stage == 1) {
       for (int v : var_set)
         for (int p = 0; p < 2; ++p)
-          for (int o = 0; o < 3 && rc == J3D_OK; ++o) rc = consider(TileCfg{base.rows, base.planes, v, p, o});
+          for (int o = 0; o < 3; ++o)
+            for (int cx : {1, 2, 4}) {
+              if (rc != J3D_OK) break;
+              const TileCfg cand{base.rows, base.planes, v, p, o, cx};
+              if (tile_cfg_supported(cand)) rc = consider(cand);
+            }
     } else {
       for (int r : rows_set)
         for (int pl : planes_set) {
           if (rc != J3D_OK) break;
-          rc = consider(TileCfg{r, pl, base.variant, base.persistent, base.order});
+          const TileCfg cand{r, pl, base.variant, base.persistent, base.order, base.cols};
+          if (tile_cfg_supported(cand)) rc = consider(cand);
         }
     }
   }
@@ -371,7 +444,8 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
 
 // Time F_WRITE passes of every listed tile shape; return the fastest.
 template <typename Launcher>
-int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, Launcher&& launch) {
+int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, Launcher&& launch,
+              float* best_ms = nullptr) {
   hipEvent_t e0, e1;
   J3D_HIP(hipEventCreate(&e0));
   J3D_HIP(hipEventCreate(&e1));
@@ -400,18 +474,20 @@ int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, L
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (best_ms != nullptr) *best_ms = bt;
   return rc;
 }
 
-std::vector<TileCfg> sweep2_candidates() {
+std::vector<TileCfg> sweep2_candidates(int dtype) {
   std::vector<TileCfg> v;
   for (int rows : {1, 2, 4, 8})
-    for (int var : {0, 4, 2, 6, 16, 20})
-      for (int planes : {8, 16, 32, 64})
-        for (int order : {0, 1, 2}) {
-          TileCfg c{rows, planes, var, 0, order};
-          if (tile2_cfg_supported(c)) v.push_back(c);
-        }
+    for (int cols : {1, 2, 4})
+      for (int var : {0, 4, 2, 6, 16, 20})
+        for (int planes : {16, 32, 64})
+          for (int order : {0, 1, 2}) {
+            TileCfg c{rows, planes, var, 0, order, cols};
+            if (tile2_cfg_supported(dtype, c)) v.push_back(c);
+          }
   return v;
 }
 
@@ -469,6 +545,54 @@ int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st) 
   return rc;
 }
 
+// Tunes the two-sweep batched pass and decides whether it beats two
+// one-sweep passes of shape c on these grids.
+int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, TileCfg* best2, bool* pairs,
+                           hipStream_t st) {
+  const int n = (int)bf.a.size();
+  GridArgs* dtab = nullptr;
+  double* parts = nullptr;
+  int part_cap = 0;
+  int rc = dev_alloc(reinterpret_cast<void**>(&dtab), (size_t)n * sizeof(GridArgs), "tune table");
+  if (rc != J3D_OK) return rc;
+  auto upload = [&](const std::vector<GridArgs>& tab, int nt) -> int {
+    if (nt > part_cap) {
+      if (parts) (void)hipFree(parts);
+      parts = nullptr;
+      J3D_TRY(dev_alloc(reinterpret_cast<void**>(&parts), (size_t)nt * sizeof(double), "tune partials"));
+      part_cap = nt;
+    }
+    J3D_HIP(hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(GridArgs), hipMemcpyHostToDevice, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    return J3D_OK;
+  };
+  auto launch2 = [&](const TileCfg& c2) -> int {
+    std::vector<GridArgs> tab2[2];
+    int nt = 0;
+    build_tables2(bf, c2, tab2, &nt);
+    J3D_TRY(upload(tab2[0], nt));
+    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE, c2, dtab, n, nt, parts, nullptr, st));
+    return J3D_OK;
+  };
+  auto launch1 = [&](const TileCfg& c1) -> int {
+    std::vector<GridArgs> tab[4];
+    int nt = 0;
+    build_tables(bf, c1, tab, &nt);
+    J3D_TRY(upload(tab[0], nt));
+    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, c1, dtab, n, nt, parts, nullptr, st));
+    return J3D_OK;
+  };
+  float t2 = 0.f, t1 = 0.f;
+  TileCfg one = c;
+  rc = time_list(st, best2, sweep2_candidates(J3D_F64), launch2, &t2);
+  if (rc == J3D_OK) rc = time_list(st, &one, std::vector<TileCfg>{c}, launch1, &t1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(dtab);
+  if (parts) (void)hipFree(parts);
+  *pairs = t2 < 2.f * t1;
+  return rc;
+}
+
 }  // namespace j3d
 
 using namespace j3d;
@@ -484,7 +608,7 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
   hipStream_t st = static_cast<hipStream_t>(stream);
   TileCfg c;
   if (tune != nullptr) {
-    c = TileCfg{tune->rows, tune->planes, tune->variant, tune->persistent, tune->order};
+    c = TileCfg{tune->rows, tune->planes, tune->variant, tune->persistent, tune->order, tune->cols};
     if (!tile_cfg_supported(c)) return fail(J3D_EINVAL, "unsupported tile shape");
   } else {
     const std::string bk = batch_key(ngrids, bf.a.data());
@@ -494,14 +618,32 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
     }
   }
   if (nsweeps == 0 && resid_out == nullptr) return J3D_OK;
-  // Plan key: every descriptor, h, counts, output and tile shape.
+  // Two sweeps per pass when every residual falls on an even sweep count and
+  // the two-sweep pass is the faster one on this batch (decided once per
+  // batch shape class).
+  // J3D_BATCH_PAIRS=0 / =1 turns the choice off / on regardless of timing.
+  bool pairs = false;
+  TileCfg c2 = default_cfg2(J3D_F64, 64, 64, 64);
+  const char* force = getenv("J3D_BATCH_PAIRS");
+  const int mode = (force && *force == '0') ? 0 : (force && *force == '1') ? 1 : -1;
+  if (mode != 0 && nsweeps >= 2 && (resid_out == nullptr || resid_every % 2 == 0)) {
+    const std::string k2 = batch_key(ngrids, bf.a.data()) + ":x2";
+    if (!pair_lookup(k2, &c2, &pairs)) {
+      J3D_TRY(autotune_batch2_fields(bf, c, &c2, &pairs, st));
+      pair_store(k2, c2, pairs);
+    }
+    if (mode == 1) pairs = true;
+  }
+  // Plan key: every descriptor, h, counts, output and tile shapes.
   std::string key;
   key.append(reinterpret_cast<const char*>(grids), sizeof(j3d_grid) * (size_t)ngrids);
   int dev = 0;
   J3D_HIP(hipGetDevice(&dev));
-  const long long meta[8] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
-                             c.rows * 1000000LL + c.planes * 1000 + c.variant * 10 + c.persistent,
-                             dev, c.order, 0};
+  const long long meta[10] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
+                              c.rows * 1000000LL + c.planes * 1000 + c.variant * 10 + c.persistent,
+                              dev, c.order, c.cols,
+                              pairs ? 1 + c2.rows * 1000000LL + c2.planes * 1000 + c2.variant * 10 : 0,
+                              c2.order * 10 + c2.cols};
   key.append(reinterpret_cast<const char*>(meta), sizeof meta);
   Plan* plan = nullptr;
   {
@@ -512,7 +654,7 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
         break;
       }
     if (plan == nullptr) {
-      J3D_TRY(make_plan(key, bf, c, nsweeps, resid_every, resid_out, &plan));
+      J3D_TRY(make_plan(key, bf, c, pairs, c2, nsweeps, resid_every, resid_out, &plan));
       if (g_plans.size() >= kMaxPlans) {
         auto it = std::min_element(g_plans.begin(), g_plans.end(),
                                    [](Plan* x, Plan* y) { return x->stamp < y->stamp; });
@@ -542,21 +684,23 @@ extern "C" int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* bes
   best->variant = c.variant;
   best->persistent = c.persistent;
   best->order = c.order;
+  best->cols = c.cols;
   return J3D_OK;
 }
 
 extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
                                    void* stream) {
-  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2)
-    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or J3D_KIND_F64X2");
+  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2 && dtype != J3D_KIND_F32X2)
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32, J3D_KIND_F64X2 or J3D_KIND_F32X2");
   if (nx < 1 || ny < 1 || nz < 1) return fail(J3D_EINVAL, "extents must be >= 1");
   if (best == nullptr) return fail(J3D_EINVAL, "best: null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const bool pair = dtype == J3D_KIND_F64X2;
-  const int es = dtype == J3D_F32 ? 4 : 8;
+  const bool pair = dtype == J3D_KIND_F64X2 || dtype == J3D_KIND_F32X2;
+  const int et = (dtype == J3D_F32 || dtype == J3D_KIND_F32X2) ? J3D_F32 : J3D_F64;
+  const int es = et == J3D_F32 ? 4 : 8;
   const int align = 128 / es;
   Field a;
-  a.dtype = pair ? J3D_F64 : dtype;
+  a.dtype = et;
   a.esize = es;
   a.ex = nx + 2;
   a.ey = ny + 2;
@@ -579,16 +723,16 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
   f.base = m + 2 * bytes + (align - 1) * es;
   auto launch = [&](const TileCfg& c) -> int {
     GridArgs g = make_args(&u, &o, &f, nullptr, nullptr, 0.01, c, 0);
-    J3D_HIP(launch_pass_one(dtype, F_WRITE, c, g, nullptr, nullptr, st));
+    J3D_HIP(launch_pass_one(et, F_WRITE, c, g, nullptr, nullptr, st));
     return J3D_OK;
   };
   auto launch2 = [&](const TileCfg& c) -> int {
-    GridArgs g = make_args2(&u, &o, &f, 0.01, c);
-    J3D_HIP(launch_sweep2_one(F_WRITE, c, g, nullptr, nullptr, st));
+    GridArgs g = make_args2(&u, &o, &f, nullptr, 0.01, c, 0);
+    J3D_HIP(launch_sweep2_one(et, F_WRITE, c, g, nullptr, nullptr, st));
     return J3D_OK;
   };
   TileCfg c{};
-  int rc = pair ? time_list(st, &c, sweep2_candidates(), launch2) : time_candidates(st, &c, launch);
+  int rc = pair ? time_list(st, &c, sweep2_candidates(et), launch2) : time_candidates(st, &c, launch);
   (void)hipStreamSynchronize(st);
   (void)hipFree(mem);
   if (rc != J3D_OK) return rc;
@@ -598,16 +742,19 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
   best->variant = c.variant;
   best->persistent = c.persistent;
   best->order = c.order;
+  best->cols = c.cols;
   return J3D_OK;
 }
 
 extern "C" int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t) {
   if (t == nullptr) return fail(J3D_EINVAL, "tune: null pointer");
-  TileCfg c{t->rows, t->planes, t->variant, t->persistent, t->order};
-  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2)
-    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or J3D_KIND_F64X2");
-  if (!(dtype == J3D_KIND_F64X2 ? tile2_cfg_supported(c) : tile_cfg_supported(c)))
-    return fail(J3D_EINVAL, "unsupported tile shape");
+  TileCfg c{t->rows, t->planes, t->variant, t->persistent, t->order, t->cols};
+  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2 && dtype != J3D_KIND_F32X2)
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32, J3D_KIND_F64X2 or J3D_KIND_F32X2");
+  const bool ok = dtype == J3D_KIND_F64X2   ? tile2_cfg_supported(J3D_F64, c)
+                  : dtype == J3D_KIND_F32X2 ? tile2_cfg_supported(J3D_F32, c)
+                                            : tile_cfg_supported(c);
+  if (!ok) return fail(J3D_EINVAL, "unsupported tile shape");
   tune_store(single_key(dtype, nx, ny, nz), c);
   return J3D_OK;
 }

@@ -29,7 +29,8 @@ DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
           "-fno-gpu-flush-denormals-to-zero",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_SOURCES = ["runtime.cpp", "capi.cpp", "solve.cpp", "batch.cpp", "serve.cpp"]
-DEVICE_SOURCES = ["kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip"]
+DEVICE_SOURCES = ["kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip",
+                  "kernels_sweep2_f32.hip"]
 
 
 def _run(cmd):

@@ -3,6 +3,7 @@
 // solve.cpp, batch.cpp and serve.cpp.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "runtime.h"
 
@@ -12,26 +13,23 @@ int release_all_scratch();
 bool tune_cache_lookup_single(int dtype, int nx, int ny, int nz, TileCfg* out);
 
 namespace {
-const int kRows[] = {1, 2, 4, 8};
-const int kPlanes[] = {1, 2, 4, 8, 16, 32, 64, 128};
-const int kVariants[] = {0, 1, 2, 3, 4, 5, 6, 7, 16, 17, 18, 19, 20, 21, 22, 23};
-constexpr int kNumPlanes = 8;
-constexpr int kNumVariants = 16;
-constexpr int kNumOrders = 3;
-constexpr int kNumTunes = 4 * kNumPlanes * kNumVariants * 2 * kNumOrders;
-
-TileCfg tune_at(int idx) {
-  TileCfg c;
-  c.order = idx % kNumOrders;
-  idx /= kNumOrders;
-  c.persistent = idx % 2;
-  idx /= 2;
-  c.variant = kVariants[idx % kNumVariants];
-  idx /= kNumVariants;
-  c.planes = kPlanes[idx % kNumPlanes];
-  idx /= kNumPlanes;
-  c.rows = kRows[idx % 4];
-  return c;
+// The supported tile shapes, enumerated once: every (rows, planes, variant,
+// persistent, order, cols) that tile_cfg_supported accepts.
+const std::vector<TileCfg>& tune_table() {
+  static const std::vector<TileCfg> table = [] {
+    std::vector<TileCfg> v;
+    for (int rows : {1, 2, 4, 8})
+      for (int planes : {1, 2, 4, 8, 16, 32, 64, 128})
+        for (int var : {0, 1, 2, 3, 4, 5, 6, 7, 16, 17, 18, 19, 20, 21, 22, 23})
+          for (int pers : {0, 1})
+            for (int order : {0, 1, 2})
+              for (int cols : {1, 2, 4}) {
+                TileCfg c{rows, planes, var, pers, order, cols};
+                if (tile_cfg_supported(c)) v.push_back(c);
+              }
+    return v;
+  }();
+  return table;
 }
 }  // namespace
 
@@ -43,17 +41,19 @@ TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   c.variant = 20;  // four rows per thread, nontemporal stores
   c.persistent = 0;
   c.order = 1;
+  c.cols = 1;
   return c;
 }
 
-TileCfg default_cfg2(int nx, int ny, int nz) {
+TileCfg default_cfg2(int dtype, int nx, int ny, int nz) {
   TileCfg c;
-  if (tune_cache_lookup_single(J3D_KIND_F64X2, nx, ny, nz, &c)) return c;
-  c.rows = 8;
+  if (tune_cache_lookup_single(dtype == J3D_F32 ? J3D_KIND_F32X2 : J3D_KIND_F64X2, nx, ny, nz, &c)) return c;
+  c.rows = 4;  // 16 rows per block (4 per thread), nontemporal stores
   c.planes = 32;
-  c.variant = 4;
+  c.variant = 20;
   c.persistent = 0;
   c.order = 1;
+  c.cols = 1;
   return c;
 }
 
@@ -97,16 +97,18 @@ int j3d_element_offset(const j3d_array* a, int64_t i, int64_t j, int64_t k, int6
 
 int j3d_check_array(const j3d_array* a, int32_t dtype) { return check_field(a, dtype, nullptr, "array"); }
 
-int j3d_tune_count(void) { return kNumTunes; }
+int j3d_tune_count(void) { return (int)tune_table().size(); }
 
 int j3d_tune_get(int32_t index, j3d_tune* out) {
-  if (out == nullptr || index < 0 || index >= kNumTunes) return fail(J3D_EINVAL, "tune index out of range");
-  TileCfg c = tune_at(index);
+  if (out == nullptr || index < 0 || index >= (int)tune_table().size())
+    return fail(J3D_EINVAL, "tune index out of range");
+  const TileCfg& c = tune_table()[(size_t)index];
   out->rows = c.rows;
   out->planes = c.planes;
   out->variant = c.variant;
   out->persistent = c.persistent;
   out->order = c.order;
+  out->cols = c.cols;
   return J3D_OK;
 }
 
@@ -151,27 +153,29 @@ int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_arra
 int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
                     uint32_t flags, double* resid_out, void* stream) {
   Field a, b, c;
-  J3D_TRY(check_field(u_in, J3D_F64, &a, "u_in"));
-  J3D_TRY(check_field(u_out, J3D_F64, &b, "u_out"));
-  J3D_TRY(check_field(f, J3D_F64, &c, "f"));
+  J3D_TRY(check_field(u_in, -1, &a, "u_in"));
+  J3D_TRY(check_field(u_out, a.dtype, &b, "u_out"));
+  J3D_TRY(check_field(f, a.dtype, &c, "f"));
   J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
   J3D_TRY(check_same_interior(a, c, "u_in", "f"));
   J3D_TRY(check_h(h));
   if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
   if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
   if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
+  if (resid_out != nullptr && a.dtype != J3D_F64)
+    return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const TileCfg cfg = default_cfg2(a.nx(), a.ny(), a.nz());
-  GridArgs g = make_args2(&a, &b, &c, h, cfg);
+  const TileCfg cfg = default_cfg2(a.dtype, a.nx(), a.ny(), a.nz());
+  GridArgs g = make_args2(&a, &b, &c, nullptr, h, cfg, 0);
   if (resid_out == nullptr) {
-    J3D_HIP(launch_sweep2_one(F_WRITE, cfg, g, nullptr, nullptr, st));
+    J3D_HIP(launch_sweep2_one(a.dtype, F_WRITE, cfg, g, nullptr, nullptr, st));
     return J3D_OK;
   }
   Scratch* s = nullptr;
   J3D_TRY(get_scratch(st, &s));
   const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
-  J3D_HIP(launch_sweep2_one(F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
+  J3D_HIP(launch_sweep2_one(J3D_F64, F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
   const bool host = (flags & J3D_HOST_RESULT) != 0;
   double* dst = host ? &s->ctl->value : resid_out;
   J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));

@@ -49,6 +49,7 @@ struct TileCfg {
   int variant;    // bit set: 1 LDS plane; 2, 16 rows per thread; 4 nontemporal stores
   int persistent; // 1: fixed grid striding over tiles
   int order;      // 0 XCD-blocked, 1 as launched, 2 chunked per XCD within each slab
+  int cols;       // wavefronts side by side along x (1, 2 or 4)
 };
 
 // Supported rows values and variants (kernels are instantiated for these).
@@ -57,15 +58,23 @@ bool tile_cfg_supported(const TileCfg& c);
 // Number of tiles of one grid under a tile shape.
 void tile_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
 
-// Tile shapes of the two-sweep pass: rows in {4, 8, 16} (a block of 64 x rows
-// columns with 62 x (rows - 2) outputs), variant 0 or 4 (nontemporal stores).
-bool tile2_cfg_supported(const TileCfg& c);
+// Tile shapes of the two-sweep pass of element type dtype: a block of
+// (64*cols) x (rows x rows-per-thread) columns with (64*cols - 2) x
+// (rows x rows-per-thread - 2) outputs.
+bool tile2_cfg_supported(int dtype, const TileCfg& c);
 void tile2_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
 
-// Two FP64 sweeps in one pass: g.o = J(J(g.u)); flags F_WRITE, optionally
-// with F_RES (residual of g.u into partials, one slot per tile).
-hipError_t launch_sweep2_one(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
-                             const int* done, hipStream_t st);
+// Two sweeps in one pass: g.o = J(J(g.u)).  FP64 flags: F_WRITE, optionally
+// with F_RES (residual of g.u into partials, one slot per tile).  FP32
+// flags: F_WRITE or F_LAST (add to g.u64), optionally with F_FIRST (g.u is
+// zero and not read).
+hipError_t launch_sweep2_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                             double* partials, const int* done, hipStream_t st);
+// The same over a table of grids (as launch_pass_batch; tile counts from
+// tile2_counts).
+hipError_t launch_sweep2_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table,
+                               int ngrids, int ntiles, double* partials, const int* done,
+                               hipStream_t st);
 
 // Number of resident workgroups used for persistent launches.
 int persistent_grid(const TileCfg& c);

@@ -181,40 +181,55 @@ using sweep_detail::device_cus;
 
 bool tile_cfg_supported(const TileCfg& c) {
   const bool rows_ok = c.rows == 1 || c.rows == 2 || c.rows == 4 || c.rows == 8;
+  const bool cols_ok = c.cols == 1 || c.cols == 2 || c.cols == 4;
   const bool var_ok = c.variant >= 0 && c.variant <= 23 && (c.variant & 8) == 0;
-  return rows_ok && var_ok && c.order >= 0 && c.order <= 2 && c.planes >= 1 && c.planes <= 4096 &&
+  return rows_ok && cols_ok && var_ok && sweep_detail::shape_instantiated(c.rows, c.cols, c.variant) &&
+         c.order >= 0 && c.order <= 2 && c.planes >= 1 && c.planes <= 4096 &&
          (c.persistent == 0 || c.persistent == 1);
 }
 
 void tile_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz) {
   const int tr = c.rows * sweep_detail::rows_per_thread(c.variant);
-  *tx = (nx + WAVE - 1) / WAVE;
+  const int tc = WAVE * c.cols;
+  *tx = (nx + tc - 1) / tc;
   *ty = (ny + tr - 1) / tr;
   *tz = (nz + c.planes - 1) / c.planes;
 }
 
-bool tile2_cfg_supported(const TileCfg& c) {
-  const bool var_ok = c.variant == 0 || c.variant == 4 || c.variant == 2 || c.variant == 6 ||
-                      c.variant == 16 || c.variant == 20;
+bool tile2_cfg_supported(int dtype, const TileCfg& c) {
   const bool rows_ok = c.rows == 1 || c.rows == 2 || c.rows == 4 || c.rows == 8;
-  if (!var_ok || !rows_ok) return false;
-  const int tr = c.rows * sweep_detail::rows_per_thread(c.variant);
-  return tr >= 4 && tr <= 32 && c.order >= 0 && c.order <= 2 && c.planes >= 1 && c.planes <= 4096 &&
-         (c.persistent == 0 || c.persistent == 1);
+  const bool cols_ok = c.cols == 1 || c.cols == 2 || c.cols == 4;
+  if (!rows_ok || !cols_ok || c.variant < 0 || c.variant > 23) return false;
+  if (dtype != J3D_F64 && dtype != J3D_F32) return false;
+  const int es = dtype == J3D_F64 ? 8 : 4;
+  return sweep_detail::shape2_instantiated(es, c.rows, c.cols, c.variant) && c.order >= 0 && c.order <= 2 &&
+         c.planes >= 1 && c.planes <= 4096 && (c.persistent == 0 || c.persistent == 1);
 }
 
 void tile2_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz) {
-  const int w = sweep_detail::kSweep2Cols, h = c.rows * sweep_detail::rows_per_thread(c.variant) - 2;
+  const int w = sweep_detail::sweep2_cols(c.cols), h = c.rows * sweep_detail::rows_per_thread(c.variant) - 2;
   *tx = (nx + w - 1) / w;
   *ty = (ny + h - 1) / h;
   *tz = (nz + c.planes - 1) / c.planes;
 }
 
-hipError_t launch_sweep2_one(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
-                             const int* done, hipStream_t st) {
-  if (!tile2_cfg_supported(c)) return hipErrorInvalidValue;
+static hipError_t dispatch2(int dtype, unsigned flags, const sweep_detail::Launch& L) {
+  if (!tile2_cfg_supported(dtype, *L.c)) return hipErrorInvalidValue;
+  if (dtype == J3D_F64) return sweep_detail::dispatch_sweep2_f64(flags, L);
+  return sweep_detail::dispatch_sweep2_f32(flags, L);
+}
+
+hipError_t launch_sweep2_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                             double* partials, const int* done, hipStream_t st) {
   sweep_detail::Launch L{false, &c, &g, nullptr, 1, 0, partials, done, st};
-  return sweep_detail::dispatch_sweep2(flags, L);
+  return dispatch2(dtype, flags, L);
+}
+
+hipError_t launch_sweep2_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table,
+                               int ngrids, int ntiles, double* partials, const int* done,
+                               hipStream_t st) {
+  sweep_detail::Launch L{true, &c, nullptr, table, ngrids, ntiles, partials, done, st};
+  return dispatch2(dtype, flags, L);
 }
 
 int persistent_grid(const TileCfg& c) {

@@ -132,8 +132,9 @@ GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* 
   return g;
 }
 
-GridArgs make_args2(const Field* u, const Field* o, const Field* f, double h, const TileCfg& c) {
-  GridArgs g = make_args(u, o, f, nullptr, nullptr, h, c, 0);
+GridArgs make_args2(const Field* u, const Field* o, const Field* f, const Field* u64, double h,
+                    const TileCfg& c, int tile0) {
+  GridArgs g = make_args(u, o, f, u64, nullptr, h, c, tile0);
   tile2_counts(g.nx, g.ny, g.nz, c, &g.tiles_x, &g.tiles_y, &g.tiles_z);
   g.chunk = (g.tiles_x * g.tiles_y + 7) / 8;
   return g;

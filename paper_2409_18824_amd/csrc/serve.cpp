@@ -6,8 +6,9 @@
 //      r32 = (float) r, per-tile sums of r^2), one batched reduce that writes
 //      each slot's ||r|| and raises its done flag when ||r|| <= rtol ||f||;
 //   2. cycle_sweeps batched FP32 correction sweeps over the slots that still
-//      have sweeps left (done slots are skipped by flag); the last one adds
-//      the correction to u.
+//      have sweeps left (done slots are skipped by flag), two sweeps per pass
+//      over memory where the count allows; the last pass adds the correction
+//      to u.
 // While a cycle runs on the GPU the worker admits queued requests (in
 // arrival order, while their state fits the memory budget and a slot is
 // free): it allocates their state and queues their set-up behind the cycle.
@@ -130,14 +131,18 @@ struct j3d_server {
   double* h_out = nullptr;    // pinned: resid[max_slots]
   int* h_flags = nullptr;     // pinned: done[max_slots], nonfinite[max_slots]
   hipEvent_t ev = nullptr;
-  TileCfg cd{}, cs{};
+  TileCfg cd{}, cs{}, cs2{};  // defect, one-sweep and two-sweep FP32 passes
 
   double now() const { return now_seconds() - t0; }
 };
 
 namespace {
 
-enum Kind { K_DEF = 0, K_FIRST, K_MID01, K_MID10, K_LAST0, K_LAST1, K_NKINDS };
+// Launch tables of a cycle: the defect step, the one-sweep FP32 passes
+// (first sweep into e0; first and last sweep at once) and the two-sweep FP32
+// passes (first pair into e0; first and last pair at once; middle pairs
+// e0 -> e1 and e1 -> e0; last pairs from e0 and from e1).
+enum Kind { K_DEF = 0, K_FIRST1, K_FL1, K_FIRST2, K_FL2, K_MID2A, K_MID2B, K_LAST2A, K_LAST2B, K_NKINDS };
 
 int serve_fail(j3d_server* s, int code, const char* what) {
   std::lock_guard<std::mutex> lk(s->mu);
@@ -170,8 +175,10 @@ int setup_device(j3d_server* s) {
   J3D_HIP(hipMemsetAsync(s->d_done, 0, 2 * n * sizeof(int), s->st));
   s->cd = default_cfg(J3D_F64, 128, 128, 128);
   s->cs = default_cfg(J3D_F32, 128, 128, 128);
+  s->cs2 = default_cfg2(J3D_F32, 128, 128, 128);
   s->cd.persistent = 0;
   s->cs.persistent = 0;
+  s->cs2.persistent = 0;
   return J3D_OK;
 }
 
@@ -283,7 +290,7 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   const int cyc = s->o.cycle_sweeps;
   GridArgs* T[K_NKINDS];
   for (int k = 0; k < K_NKINDS; ++k) T[k] = s->h_tab + (size_t)k * s->o.max_slots;
-  int nt_def = 0, nt_swp = 0, n_in = 0;
+  int nt_def = 0, nt_swp = 0, nt_swp2 = 0, n_in = 0;
   for (int g = 0; g < n; ++g) {
     Slot* sl = slots[g];
     const Layout& L = sl->L;
@@ -295,16 +302,20 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
     s->h_rtol[sl->id] = sl->req->r.rtol;
     if (sl->sweeps >= sl->req->max_sweeps) continue;  // final defect only
     GridArgs a[K_NKINDS];
-    a[K_FIRST] = make_args(nullptr, &L.e0, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
-    a[K_MID01] = make_args(&L.e0, &L.e1, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
-    a[K_MID10] = make_args(&L.e1, &L.e0, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
-    a[K_LAST0] = make_args(&L.e0, nullptr, &L.r32, &L.u, nullptr, h, s->cs, nt_swp);
-    a[K_LAST1] = make_args(&L.e1, nullptr, &L.r32, &L.u, nullptr, h, s->cs, nt_swp);
-    for (int k = K_FIRST; k < K_NKINDS; ++k) {
+    a[K_FIRST1] = make_args(nullptr, &L.e0, &L.r32, nullptr, nullptr, h, s->cs, nt_swp);
+    a[K_FL1] = make_args(nullptr, nullptr, &L.r32, &L.u, nullptr, h, s->cs, nt_swp);
+    a[K_FIRST2] = make_args2(nullptr, &L.e0, &L.r32, nullptr, h, s->cs2, nt_swp2);
+    a[K_FL2] = make_args2(nullptr, nullptr, &L.r32, &L.u, h, s->cs2, nt_swp2);
+    a[K_MID2A] = make_args2(&L.e0, &L.e1, &L.r32, nullptr, h, s->cs2, nt_swp2);
+    a[K_MID2B] = make_args2(&L.e1, &L.e0, &L.r32, nullptr, h, s->cs2, nt_swp2);
+    a[K_LAST2A] = make_args2(&L.e0, nullptr, &L.r32, &L.u, h, s->cs2, nt_swp2);
+    a[K_LAST2B] = make_args2(&L.e1, nullptr, &L.r32, &L.u, h, s->cs2, nt_swp2);
+    for (int k = K_FIRST1; k < K_NKINDS; ++k) {
       a[k].id = sl->id;
       T[k][n_in] = a[k];
     }
-    nt_swp += a[K_FIRST].tiles_x * a[K_FIRST].tiles_y * a[K_FIRST].tiles_z;
+    nt_swp += a[K_FIRST1].tiles_x * a[K_FIRST1].tiles_y * a[K_FIRST1].tiles_z;
+    nt_swp2 += a[K_FIRST2].tiles_x * a[K_FIRST2].tiles_y * a[K_FIRST2].tiles_z;
     ++n_in;
   }
   if ((size_t)nt_def > s->part_cap) {
@@ -326,19 +337,31 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   J3D_HIP(launch_pass_batch(J3D_F64, F_RES | F_R32, s->cd, D[K_DEF], n, nt_def, s->d_part, done, s->st));
   J3D_HIP(launch_reduce_batch(s->d_part, D[K_DEF], n, s->d_resid, 1, 0, s->d_normf, s->d_rtol, 0, done,
                               s->d_conv, s->d_nonfinite, s->st));
+  // The correction sweeps, scheduled as in a solo mixed solve: the first
+  // pass takes one sweep when the count is odd, two when even.
   if (n_in > 0) {
     if (cyc == 1) {
-      // A one-sweep cycle: first and last sweep at once.
-      J3D_HIP(launch_pass_batch(J3D_F32, F_LAST | F_FIRST, s->cs, D[K_LAST0], n_in, nt_swp, nullptr,
-                                done, s->st));
+      J3D_HIP(launch_pass_batch(J3D_F32, F_LAST | F_FIRST, s->cs, D[K_FL1], n_in, nt_swp, nullptr, done,
+                                s->st));
+    } else if (cyc == 2) {
+      J3D_HIP(launch_sweep2_batch(J3D_F32, F_LAST | F_FIRST, s->cs2, D[K_FL2], n_in, nt_swp2, nullptr, done,
+                                  s->st));
     } else {
-      J3D_HIP(launch_pass_batch(J3D_F32, F_WRITE | F_FIRST, s->cs, D[K_FIRST], n_in, nt_swp, nullptr,
-                                done, s->st));
-      for (int p = 1; p <= cyc - 2; ++p)
-        J3D_HIP(launch_pass_batch(J3D_F32, F_WRITE, s->cs, (p & 1) ? D[K_MID01] : D[K_MID10], n_in,
-                                  nt_swp, nullptr, done, s->st));
-      J3D_HIP(launch_pass_batch(J3D_F32, F_LAST, s->cs, ((cyc - 2) & 1) ? D[K_LAST1] : D[K_LAST0], n_in,
-                                nt_swp, nullptr, done, s->st));
+      if (cyc & 1)
+        J3D_HIP(launch_pass_batch(J3D_F32, F_WRITE | F_FIRST, s->cs, D[K_FIRST1], n_in, nt_swp, nullptr,
+                                  done, s->st));
+      else
+        J3D_HIP(launch_sweep2_batch(J3D_F32, F_WRITE | F_FIRST, s->cs2, D[K_FIRST2], n_in, nt_swp2,
+                                    nullptr, done, s->st));
+      const int pairs = (cyc - 2 + (cyc & 1)) / 2;  // passes after the first, >= 1
+      bool in_e0 = true;
+      for (int p = 1; p < pairs; ++p) {
+        J3D_HIP(launch_sweep2_batch(J3D_F32, F_WRITE, s->cs2, in_e0 ? D[K_MID2A] : D[K_MID2B], n_in, nt_swp2,
+                                    nullptr, done, s->st));
+        in_e0 = !in_e0;
+      }
+      J3D_HIP(launch_sweep2_batch(J3D_F32, F_LAST, s->cs2, in_e0 ? D[K_LAST2A] : D[K_LAST2B], n_in, nt_swp2,
+                                  nullptr, done, s->st));
     }
   }
   // Residuals and flags of this cycle's defect step, for the host.

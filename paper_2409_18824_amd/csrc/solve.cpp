@@ -89,7 +89,7 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   Scratch* s = nullptr;
   J3D_TRY(get_scratch(st, &s));
   const TileCfg cfg = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());
-  const TileCfg cfg2 = default_cfg2(u.nx(), u.ny(), u.nz());
+  const TileCfg cfg2 = default_cfg2(J3D_F64, u.nx(), u.ny(), u.nz());
   const long long S = o.max_sweeps;
   const long long c = o.check_every;
   // Two-sweep passes when every check falls on an even sweep count.
@@ -106,7 +106,7 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   GridArgs one[2], two[2], resid[2];
   for (int b = 0; b < 2; ++b) {
     one[b] = make_args(buf[b], buf[1 - b], &f, nullptr, nullptr, h, cfg, 0);
-    two[b] = make_args2(buf[b], buf[1 - b], &f, h, cfg2);
+    two[b] = make_args2(buf[b], buf[1 - b], &f, nullptr, h, cfg2, 0);
     resid[b] = make_args(buf[b], nullptr, &f, nullptr, nullptr, h, cfg, 0);
   }
   const int nt1 = one[0].tiles_x * one[0].tiles_y * one[0].tiles_z;
@@ -136,7 +136,7 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
       const unsigned fl = F_WRITE | (check ? F_RES : 0u);
       int nt;
       if (pairs && sw + 2 <= S) {
-        J3D_HIP(launch_sweep2_one(fl, cfg2, two[cur], s->partials, done, st));
+        J3D_HIP(launch_sweep2_one(J3D_F64, fl, cfg2, two[cur], s->partials, done, st));
         nt = nt2;
         sw += 2;
       } else {
@@ -232,13 +232,20 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   const Field e1 = f32_field(u, mem + 2 * b1, &tmp);
   J3D_HIP(hipMemsetAsync(mem, 0, 3 * b1, st));  // zero halos of the correction
 
+  // A cycle of m correction sweeps e_1 = J(0), e_{p+1} = J(e_p), u += e_m
+  // runs as two-sweep passes: the first pass starts from zero without
+  // reading it (one sweep when m is odd, two when even), the middle passes
+  // ping-pong between e0 and e1, and the last pass adds its result to u.
+  const TileCfg cs2 = default_cfg2(J3D_F32, u.nx(), u.ny(), u.nz());
   const GridArgs defect = make_args(&u, nullptr, &f, nullptr, &r32, h, cd, 0);
-  const GridArgs first = make_args(nullptr, &e0, &r32, nullptr, nullptr, h, cs, 0);
-  const GridArgs first_last = make_args(nullptr, nullptr, &r32, &u, nullptr, h, cs, 0);
-  const GridArgs mid01 = make_args(&e0, &e1, &r32, nullptr, nullptr, h, cs, 0);
-  const GridArgs mid10 = make_args(&e1, &e0, &r32, nullptr, nullptr, h, cs, 0);
-  const GridArgs last0 = make_args(&e0, nullptr, &r32, &u, nullptr, h, cs, 0);
-  const GridArgs last1 = make_args(&e1, nullptr, &r32, &u, nullptr, h, cs, 0);
+  const GridArgs first1 = make_args(nullptr, &e0, &r32, nullptr, nullptr, h, cs, 0);
+  const GridArgs first_last1 = make_args(nullptr, nullptr, &r32, &u, nullptr, h, cs, 0);
+  const GridArgs first2 = make_args2(nullptr, &e0, &r32, nullptr, h, cs2, 0);
+  const GridArgs first_last2 = make_args2(nullptr, nullptr, &r32, &u, h, cs2, 0);
+  const GridArgs mid2[2] = {make_args2(&e0, &e1, &r32, nullptr, h, cs2, 0),
+                            make_args2(&e1, &e0, &r32, nullptr, h, cs2, 0)};
+  const GridArgs last2[2] = {make_args2(&e0, nullptr, &r32, &u, h, cs2, 0),
+                             make_args2(&e1, nullptr, &r32, &u, h, cs2, 0)};
   const int nt = defect.tiles_x * defect.tiles_y * defect.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
   const long long ncyc = (S + m_in - 1) / m_in + 1;  // defect steps at most
@@ -249,7 +256,7 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   int* done = &s->ctl->done;
 
   const long long points = (long long)u.nx() * u.ny() * u.nz();
-  const long long chunk = chunk_sweeps(points, 12.6, m_in);
+  const long long chunk = chunk_sweeps(points, 6.6, m_in);
   long long sw = 0, q = 0, since = 0;
   int slot = 0;
   bool seen = false;
@@ -260,12 +267,21 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
     if (sw >= S) break;
     const long long m = std::min(m_in, S - sw);
     if (m == 1) {
-      J3D_HIP(launch_pass_one(J3D_F32, F_LAST | F_FIRST, cs, first_last, nullptr, done, st));
+      J3D_HIP(launch_pass_one(J3D_F32, F_LAST | F_FIRST, cs, first_last1, nullptr, done, st));
+    } else if (m == 2) {
+      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST | F_FIRST, cs2, first_last2, nullptr, done, st));
     } else {
-      J3D_HIP(launch_pass_one(J3D_F32, F_WRITE | F_FIRST, cs, first, nullptr, done, st));
-      for (long long p = 1; p <= m - 2; ++p)
-        J3D_HIP(launch_pass_one(J3D_F32, F_WRITE, cs, (p & 1) ? mid01 : mid10, nullptr, done, st));
-      J3D_HIP(launch_pass_one(J3D_F32, F_LAST, cs, ((m - 2) & 1) ? last1 : last0, nullptr, done, st));
+      if (m & 1)
+        J3D_HIP(launch_pass_one(J3D_F32, F_WRITE | F_FIRST, cs, first1, nullptr, done, st));
+      else
+        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE | F_FIRST, cs2, first2, nullptr, done, st));
+      const long long pairs = (m - 2 + (m & 1)) / 2;  // passes after the first, >= 1
+      int cur = 0;                                    // e0 holds the iterate
+      for (long long p = 1; p < pairs; ++p) {
+        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE, cs2, mid2[cur], nullptr, done, st));
+        cur = 1 - cur;
+      }
+      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST, cs2, last2[cur], nullptr, done, st));
     }
     sw += m;
     ++q;

@@ -5,8 +5,8 @@
 // instantiate it for their element type.
 //
 // Memory layout: Fortran column-major arrays with a one-cell halo; x is the
-// unit-stride axis.  A workgroup owns a tile of 64 x-points (one 64-lane
-// wavefront per row) by BY y-rows by `planes` z-planes and marches through
+// unit-stride axis.  A workgroup owns a tile of 64*WX x-points (WX 64-lane
+// wavefronts side by side) by BY*RY y-rows by `planes` z-planes and marches through
 // z, keeping the previous, current and next value of its column in
 // registers, so every plane of u and f is fetched from HBM once per tile.
 // The sweep streams about 24 bytes per FP64 point update and does 8 flops,
@@ -89,13 +89,30 @@ constexpr int rows_per_thread(int var) { return 1 << (((var >> 1) & 1) + 2 * ((v
 // Shared memory of a workgroup: the double-buffered plane with its x/y halo
 // ring (LDS variants only; one element otherwise) and one partial sum per
 // wavefront.
-template <typename T, int BY, int VAR>
+template <typename T, int BY, int WX, int VAR>
 struct Smem {
   static constexpr bool LDS = (VAR & 1) != 0;
   static constexpr int TR = BY * rows_per_thread(VAR);
-  T pl[LDS ? 2 : 1][LDS ? TR + 2 : 1][LDS ? WAVE + 2 : 1];
-  double red[BY];
+  T pl[LDS ? 2 : 1][LDS ? TR + 2 : 1][LDS ? WAVE * WX + 2 : 1];
+  double red[BY * WX];
 };
+
+// Sum of one double per wavefront of the workgroup: a fixed butterfly within
+// each wavefront, then the wavefront sums in wavefront order.  The result is
+// valid in thread (0, 0).
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.y * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = v;
+  __syncthreads();
+  double tot = 0.0;
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) tot += red[q];
+  }
+  return tot;
+}
 
 // One tile: local tile index t of grid g.  Writes the tile's partial sum
 // (F_RES / F_NORM) to partials[g.tile0 + t].
@@ -106,21 +123,22 @@ struct Smem {
 // lane loads from in-bounds addresses (lanes and rows past the interior are
 // clamped onto the last interior column/row), so loads need no per-lane
 // branches; only stores and sums are masked.
-template <typename T, int BY, int VAR, unsigned FL>
+template <typename T, int BY, int WX, int VAR, unsigned FL>
 __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __restrict__ partials,
-                                           Smem<T, BY, VAR>& sm) {
+                                           Smem<T, BY, WX, VAR>& sm) {
   constexpr bool STENCIL = !(FL & (F_FIRST | F_NORM));
   constexpr bool USE_LDS = (VAR & 1) && STENCIL;
   constexpr int RY = rows_per_thread(VAR);
-  constexpr int TR = BY * RY;  // rows per tile
+  constexpr int TR = BY * RY;      // rows per tile
+  constexpr int TX = WAVE * WX;    // columns per tile
   constexpr bool NT = (VAR & 4) != 0;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x;    // column within the tile
   const int wy = threadIdx.y;
   const int tx = t % g.tiles_x;
   const int t2 = t / g.tiles_x;
   const int ty = t2 % g.tiles_y;
   const int tz = t2 / g.tiles_y;
-  const int i = 1 + tx * WAVE + lane;
+  const int i = 1 + tx * TX + lane;
   const int jb = 1 + ty * TR + wy * RY;  // first row of this thread
   const int k0 = 1 + tz * g.planes;
   const int k1 = min(k0 + g.planes, g.nz + 1);
@@ -183,7 +201,7 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
           const int row = wy * RY + r + 1;
           pl[row][lane + 1] = uc[r];
           if (lane == 0) pl[row][0] = u_r[-1];
-          if (lane == WAVE - 1 || i == g.nx) pl[row][lane + 2] = u_r[1];
+          if (lane == TX - 1 || i == g.nx) pl[row][lane + 2] = u_r[1];
           if (row == 1) pl[0][lane + 1] = u_r[-g.su_y];
           if (row == TR || jb + r == g.ny) pl[row + 1][lane + 1] = u_r[g.su_y];
         }
@@ -241,43 +259,36 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
   }
 
   if (FL & (F_RES | F_NORM)) {
-    const double v = wave_sum(acc);
-    if (lane == 0) sm.red[wy] = v;
-    __syncthreads();
-    if (wy == 0 && lane == 0) {
-      double tot = 0.0;
-#pragma unroll
-      for (int q = 0; q < BY; ++q) tot += sm.red[q];
-      partials[g.tile0 + t] = tot;
-    }
+    const double tot = block_sum<BY * WX>(acc, sm.red);
+    if (wy == 0 && lane == 0) partials[g.tile0 + t] = tot;
   }
   // The next tile of a persistent workgroup reuses the shared buffers.
   __syncthreads();
 }
 
-template <typename T, int BY, int VAR, unsigned FL>
-__global__ void __launch_bounds__(WAVE * BY)
+template <typename T, int BY, int WX, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * WX * BY)
     k_pass_one(GridArgs g, double* __restrict__ partials, const int* __restrict__ done) {
   if (done != nullptr && *done != 0) return;
-  __shared__ Smem<T, BY, VAR> sm;
+  __shared__ Smem<T, BY, WX, VAR> sm;
   const int ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
   if (g.order == 0) {
     for (int t = xcd_remap(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
-      sweep_tile<T, BY, VAR, FL>(g, t, partials, sm);
+      sweep_tile<T, BY, WX, VAR, FL>(g, t, partials, sm);
   } else {
     const int nv = virtual_tiles(ntiles, g.order, g.chunk);
     for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
       const int t = g.order == 2 ? xcd_chunked(vb, g.chunk) : vb;
-      if (t < ntiles) sweep_tile<T, BY, VAR, FL>(g, t, partials, sm);
+      if (t < ntiles) sweep_tile<T, BY, WX, VAR, FL>(g, t, partials, sm);
     }
   }
 }
 
-template <typename T, int BY, int VAR, unsigned FL>
-__global__ void __launch_bounds__(WAVE * BY)
+template <typename T, int BY, int WX, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * WX * BY)
     k_pass_batch(const GridArgs* __restrict__ table, int ngrids, int ntiles,
                  double* __restrict__ partials, const int* __restrict__ done, int order, int chunk) {
-  __shared__ Smem<T, BY, VAR> sm;
+  __shared__ Smem<T, BY, WX, VAR> sm;
   const int nv = order == 0 ? ntiles : virtual_tiles(ntiles, order, chunk);
   const int first = order == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   for (int vb = first; vb < nv; vb += gridDim.x) {
@@ -290,7 +301,7 @@ __global__ void __launch_bounds__(WAVE * BY)
     }
     if (done != nullptr && done[table[lo].id] != 0) continue;
     const GridArgs g = table[lo];
-    sweep_tile<T, BY, VAR, FL>(g, t - g.tile0, partials, sm);
+    sweep_tile<T, BY, WX, VAR, FL>(g, t - g.tile0, partials, sm);
   }
 }
 
@@ -322,54 +333,66 @@ struct Launch {
   hipStream_t st;
 };
 
-template <typename T, int BY, int VAR, unsigned FL>
+template <typename T, int BY, int WX, int VAR, unsigned FL>
 hipError_t go(const Launch& L) {
+  constexpr int THREADS = WAVE * WX * BY;
   int grid;
   if (L.batch) {
     const int chunk = kBatchChunk;
     grid = virtual_tiles(L.ntiles, L.c->order, chunk);
     if (L.c->persistent) {
       static int cap = 0;
-      if (cap == 0) cap = resident_blocks(k_pass_batch<T, BY, VAR, FL>, WAVE * BY);
+      if (cap == 0) cap = resident_blocks(k_pass_batch<T, BY, WX, VAR, FL>, THREADS);
       grid = min(grid, cap);
     }
     if (grid <= 0 || L.ngrids <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pass_batch<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, L.st, L.table,
-                       L.ngrids, L.ntiles, L.partials, L.done, L.c->order, chunk);
+    hipLaunchKernelGGL((k_pass_batch<T, BY, WX, VAR, FL>), dim3(grid), dim3(WAVE * WX, BY), 0, L.st,
+                       L.table, L.ngrids, L.ntiles, L.partials, L.done, L.c->order, chunk);
   } else {
     const GridArgs& g = *L.one;
     grid = virtual_tiles(g.tiles_x * g.tiles_y * g.tiles_z, g.order, g.chunk);
     if (L.c->persistent) {
       static int cap = 0;
-      if (cap == 0) cap = resident_blocks(k_pass_one<T, BY, VAR, FL>, WAVE * BY);
+      if (cap == 0) cap = resident_blocks(k_pass_one<T, BY, WX, VAR, FL>, THREADS);
       grid = min(grid, cap);
     }
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_pass_one<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, L.st, g,
+    hipLaunchKernelGGL((k_pass_one<T, BY, WX, VAR, FL>), dim3(grid), dim3(WAVE * WX, BY), 0, L.st, g,
                        L.partials, L.done);
   }
   return hipGetLastError();
 }
 
-template <typename T, int BY, unsigned FL>
+// Instantiated shapes: one wavefront along x with every variant; two or four
+// wavefronts along x (at most 1024 threads) with the cache-fed variants that
+// use nontemporal stores and 1, 2 or 4 rows per thread.
+constexpr bool shape_instantiated(int by, int wx, int var) {
+  if (wx == 1) return true;
+  return by * wx <= 16 && (var == 4 || var == 6 || var == 20);
+}
+
+template <typename T, int BY, int WX, unsigned FL>
 hipError_t by_variant(const Launch& L) {
+#define J3D_VAR_CASE(V)                                                      \
+  case V:                                                                    \
+    if constexpr (shape_instantiated(BY, WX, V)) return go<T, BY, WX, V, FL>(L); \
+    else return hipErrorInvalidValue;
   switch (L.c->variant) {
-    case 0: return go<T, BY, 0, FL>(L);
-    case 1: return go<T, BY, 1, FL>(L);
-    case 2: return go<T, BY, 2, FL>(L);
-    case 3: return go<T, BY, 3, FL>(L);
-    case 4: return go<T, BY, 4, FL>(L);
-    case 5: return go<T, BY, 5, FL>(L);
-    case 6: return go<T, BY, 6, FL>(L);
-    case 7: return go<T, BY, 7, FL>(L);
-    case 16: return go<T, BY, 16, FL>(L);
-    case 17: return go<T, BY, 17, FL>(L);
-    case 18: return go<T, BY, 18, FL>(L);
-    case 19: return go<T, BY, 19, FL>(L);
-    case 20: return go<T, BY, 20, FL>(L);
-    case 21: return go<T, BY, 21, FL>(L);
-    case 22: return go<T, BY, 22, FL>(L);
-    case 23: return go<T, BY, 23, FL>(L);
+    J3D_VAR_CASE(0) J3D_VAR_CASE(1) J3D_VAR_CASE(2) J3D_VAR_CASE(3)
+    J3D_VAR_CASE(4) J3D_VAR_CASE(5) J3D_VAR_CASE(6) J3D_VAR_CASE(7)
+    J3D_VAR_CASE(16) J3D_VAR_CASE(17) J3D_VAR_CASE(18) J3D_VAR_CASE(19)
+    J3D_VAR_CASE(20) J3D_VAR_CASE(21) J3D_VAR_CASE(22) J3D_VAR_CASE(23)
+    default: return hipErrorInvalidValue;
+  }
+#undef J3D_VAR_CASE
+}
+
+template <typename T, int BY, unsigned FL>
+hipError_t by_cols(const Launch& L) {
+  switch (L.c->cols) {
+    case 1: return by_variant<T, BY, 1, FL>(L);
+    case 2: return by_variant<T, BY, 2, FL>(L);
+    case 4: return by_variant<T, BY, 4, FL>(L);
     default: return hipErrorInvalidValue;
   }
 }
@@ -377,10 +400,10 @@ hipError_t by_variant(const Launch& L) {
 template <typename T, unsigned FL>
 hipError_t by_shape(const Launch& L) {
   switch (L.c->rows) {
-    case 1: return by_variant<T, 1, FL>(L);
-    case 2: return by_variant<T, 2, FL>(L);
-    case 4: return by_variant<T, 4, FL>(L);
-    case 8: return by_variant<T, 8, FL>(L);
+    case 1: return by_cols<T, 1, FL>(L);
+    case 2: return by_cols<T, 2, FL>(L);
+    case 4: return by_cols<T, 4, FL>(L);
+    case 8: return by_cols<T, 8, FL>(L);
     default: return hipErrorInvalidValue;
   }
 }

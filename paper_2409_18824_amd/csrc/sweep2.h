@@ -1,11 +1,12 @@
-// Two Jacobi sweeps in one pass over HBM (temporal blocking in z).
+// Two Jacobi sweeps in one pass over HBM (temporal blocking in z), in FP64
+// or FP32.
 //
-// u2 = J(J(u0)).  A workgroup of BY 64-lane wavefronts, each thread owning
-// RY consecutive rows (register blocking in y), covers a block of
-// 64 x (BY*RY) columns: lane l, row r of wavefront w is column
-// (x0 - 1 + l, y0 - 1 + w*RY + r).  The inner 62 x (BY*RY - 2) columns are
-// the tile's outputs; the outer ring is recomputed redundantly by the
-// neighbouring tiles.  Marching through z, at
+// u2 = J(J(u0)).  A workgroup of BY rows of WX 64-lane wavefronts, each
+// thread owning RY consecutive rows (register blocking in y), covers a block
+// of 64*WX x (BY*RY) columns: thread (l, w), row r is column
+// (x0 - 1 + l, y0 - 1 + w*RY + r).  The inner (64*WX - 2) x (BY*RY - 2)
+// columns are the tile's outputs; the outer ring is recomputed redundantly by
+// the neighbouring tiles.  Marching through z, at
 // step k the block
 //   1. computes the intermediate iterate u1 at plane k on all its columns
 //      (from u0 planes k-1, k, k+1 held in registers and u0's x/y
@@ -29,26 +30,33 @@
 namespace j3d {
 namespace sweep_detail {
 
-constexpr int kSweep2Cols = WAVE - 2;  // output columns per tile in x
+// Output columns per tile in x for WX wavefronts side by side.
+constexpr int sweep2_cols(int wx) { return WAVE * wx - 2; }
 
 // Rows per thread of the two-sweep pass (variant bits 2 and 16, as in the
 // one-sweep pass).
-template <int BY, int VAR>
+template <typename T, int BY, int WX, int VAR>
 struct Smem2 {
   static constexpr int TR = BY * rows_per_thread(VAR);  // rows of the block
-  double pl[3][TR][WAVE];
-  double red[BY];
+  T pl[3][TR][WAVE * WX];
+  double red[BY * WX];
 };
 
-template <int BY, int VAR, unsigned FL>
+// Flags: F_WRITE (store u2 to g.o), F_RES (FP64: residual of u0), F_FIRST
+// (u0 is identically zero and not read; the first two sweeps of a correction
+// cycle), F_LAST (add (double) u2 to g.u64 instead of storing it; the last
+// two sweeps of a correction cycle).
+template <typename T, int BY, int WX, int VAR, unsigned FL>
 __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __restrict__ partials,
-                                            Smem2<BY, VAR>& sm) {
+                                            Smem2<T, BY, WX, VAR>& sm) {
   constexpr int RY = rows_per_thread(VAR);
   constexpr int TR = BY * RY;   // block rows
-  constexpr int W = kSweep2Cols;
+  constexpr int W = sweep2_cols(WX);
   constexpr int H = TR - 2;     // output rows per tile
   constexpr bool NT = (VAR & 4) != 0;
+  constexpr bool ZERO = (FL & F_FIRST) != 0;
   static_assert(TR >= 3, "a block needs at least one inner row");
+  static_assert(!(FL & F_RES) || sizeof(T) == 8, "the fused residual is an FP64 pass");
   const int lane = threadIdx.x;
   const int wy = threadIdx.y;
   const int tx = t % g.tiles_x;
@@ -63,10 +71,11 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
   // Every address is clamped into the array, halo included.
   const int xc = min(xi, g.nx + 1);
   const int xm = max(xc - 1, 0), xp = min(xc + 1, g.nx + 1);
-  const double* __restrict__ u0 = static_cast<const double*>(g.u);
-  const double* __restrict__ f = static_cast<const double*>(g.f);
-  double* __restrict__ out = static_cast<double*>(g.o);
-  const double h2 = g.h2;
+  const T* __restrict__ u0 = static_cast<const T*>(g.u);
+  const T* __restrict__ f = static_cast<const T*>(g.f);
+  T* __restrict__ out = static_cast<T*>(g.o);
+  double* __restrict__ u64 = g.u64;
+  const T h2 = h2_of<T>(g);
   const int ztop = g.nz + 1;
 
   int br[RY], cu[RY], cf[RY], co[RY];
@@ -78,7 +87,7 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
     const int yc = min(yj, g.ny + 1);
     cu[r] = xc + g.su_y * yc;
     cf[r] = xc + g.sf_y * yc;
-    co[r] = xc + g.so_y * yc;
+    co[r] = (FL & F_LAST) ? xc + g.s64_y * yc : xc + g.so_y * yc;
     inner[r] = lane_in && br[r] >= 1 && br[r] <= H;
     col_in[r] = x_in && yj >= 1 && yj <= g.ny;
   }
@@ -89,46 +98,50 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
   const int cym = xc + g.su_y * ylo, cyp = xc + g.su_y * yhi;
 
   double acc = 0.0;
-  double u0m[RY], u0c[RY], u1m2[RY], fprev[RY];
+  T u0m[RY], u0c[RY], u1m1[RY], u1m2[RY], fprev[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    u0m[r] = u0[cu[r] + g.su_z * max(k0 - 2, 0)];
-    u0c[r] = u0[cu[r] + g.su_z * (k0 - 1)];
-    u1m2[r] = 0.0;
-    fprev[r] = 0.0;
+    u0m[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 2, 0)];
+    u0c[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * (k0 - 1)];
+    u1m1[r] = T(0);
+    u1m2[r] = T(0);
+    fprev[r] = T(0);
   }
-  double u1m1[RY];
-#pragma unroll
-  for (int r = 0; r < RY; ++r) u1m1[r] = 0.0;
 
   for (int k = k0 - 1; k <= k1; ++k) {
     // Stage 1: u1 at plane k on every column of the block.
     const int kp = min(k + 1, ztop);
     const int kf = min(max(k, 1), g.nz);
     const int zk = g.su_z * k;
-    double u0p[RY], fk[RY], nxm[RY], nxp[RY];
+    T u0p[RY], fk[RY], nxm[RY], nxp[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      u0p[r] = u0[cu[r] + g.su_z * kp];
       fk[r] = f[cf[r] + g.sf_z * kf];
-      nxm[r] = u0[cu[r] - xc + xm + zk];
-      nxp[r] = u0[cu[r] - xc + xp + zk];
+      if (ZERO) {
+        u0p[r] = nxm[r] = nxp[r] = T(0);
+      } else {
+        u0p[r] = u0[cu[r] + g.su_z * kp];
+        nxm[r] = u0[cu[r] - xc + xm + zk];
+        nxp[r] = u0[cu[r] - xc + xp + zk];
+      }
     }
-    const double nylo = u0[cym + zk], nyhi = u0[cyp + zk];
-    double u1[RY];
+    const T nylo = ZERO ? T(0) : u0[cym + zk];
+    const T nyhi = ZERO ? T(0) : u0[cyp + zk];
+    T u1[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const double nym = r == 0 ? nylo : u0c[r - 1];
-      const double nyp = r == RY - 1 ? nyhi : u0c[r + 1];
+      const T nym = r == 0 ? nylo : u0c[r - 1];
+      const T nyp = r == RY - 1 ? nyhi : u0c[r + 1];
       const bool pt_in = col_in[r] && k >= 1 && k <= g.nz;
-      double s = nxm[r] + nxp[r];
+      T s = nxm[r] + nxp[r];
       s = s + nym;
       s = s + nyp;
       s = s + u0m[r];
       s = s + u0p[r];
-      u1[r] = pt_in ? (s + h2 * fk[r]) / 6.0 : u0c[r];
+      u1[r] = pt_in ? (s + h2 * fk[r]) / T(6) : u0c[r];
       if (FL & F_RES) {
-        const double res = fk[r] - (6.0 * u0c[r] - s) / h2;
+        const double res = static_cast<double>(fk[r]) -
+                           (6.0 * static_cast<double>(u0c[r]) - static_cast<double>(s)) / g.h2;
         acc += (inner[r] && pt_in && k >= k0 && k < k1) ? res * res : 0.0;
       }
       sm.pl[k % 3][br[r]][lane] = u1[r];
@@ -136,17 +149,24 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
     __syncthreads();
     // Stage 2: u2 at plane k-1 on the inner columns.
     if (k - 1 >= k0) {
-      const double(*p1)[WAVE] = sm.pl[(k + 2) % 3];  // slot of plane k-1
+      const T(*p1)[WAVE * WX] = sm.pl[(k + 2) % 3];  // slot of plane k-1
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         if (inner[r]) {
-          double s1 = p1[br[r]][lane - 1] + p1[br[r]][lane + 1];
+          T s1 = p1[br[r]][lane - 1] + p1[br[r]][lane + 1];
           s1 = s1 + p1[br[r] - 1][lane];
           s1 = s1 + p1[br[r] + 1][lane];
           s1 = s1 + u1m2[r];
           s1 = s1 + u1[r];
-          const double u2 = (s1 + h2 * fprev[r]) / 6.0;
-          if (col_in[r]) put<double, NT>(out + co[r] + g.so_z * (k - 1), u2);
+          const T u2 = (s1 + h2 * fprev[r]) / T(6);
+          if (col_in[r]) {
+            if (FL & F_LAST) {
+              double* q = u64 + co[r] + g.s64_z * (k - 1);
+              q[0] = q[0] + static_cast<double>(u2);
+            } else {
+              put<T, NT>(out + co[r] + g.so_z * (k - 1), u2);
+            }
+          }
         }
       }
     }
@@ -161,38 +181,139 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
   }
 
   if (FL & F_RES) {
-    const double v = wave_sum(acc);
-    if (lane == 0) sm.red[wy] = v;
-    __syncthreads();
-    if (wy == 0 && lane == 0) {
-      double tot = 0.0;
-#pragma unroll
-      for (int q = 0; q < BY; ++q) tot += sm.red[q];
-      partials[g.tile0 + t] = tot;
-    }
+    const double tot = block_sum<BY * WX>(acc, sm.red);
+    if (wy == 0 && lane == 0) partials[g.tile0 + t] = tot;
   }
   __syncthreads();
 }
 
-template <int BY, int VAR, unsigned FL>
-__global__ void __launch_bounds__(WAVE * BY)
+template <typename T, int BY, int WX, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * WX * BY)
     k_sweep2_one(GridArgs g, double* __restrict__ partials, const int* __restrict__ done) {
   if (done != nullptr && *done != 0) return;
-  __shared__ Smem2<BY, VAR> sm;
+  __shared__ Smem2<T, BY, WX, VAR> sm;
   const int ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
   if (g.order == 0) {
     for (int t = xcd_remap(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
-      sweep2_tile<BY, VAR, FL>(g, t, partials, sm);
+      sweep2_tile<T, BY, WX, VAR, FL>(g, t, partials, sm);
   } else {
     const int nv = virtual_tiles(ntiles, g.order, g.chunk);
     for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
       const int t = g.order == 2 ? xcd_chunked(vb, g.chunk) : vb;
-      if (t < ntiles) sweep2_tile<BY, VAR, FL>(g, t, partials, sm);
+      if (t < ntiles) sweep2_tile<T, BY, WX, VAR, FL>(g, t, partials, sm);
     }
   }
 }
 
-hipError_t dispatch_sweep2(unsigned flags, const Launch& L);
+// The two-sweep pass over a table of grids (as k_pass_batch).
+template <typename T, int BY, int WX, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * WX * BY)
+    k_sweep2_batch(const GridArgs* __restrict__ table, int ngrids, int ntiles,
+                   double* __restrict__ partials, const int* __restrict__ done, int order, int chunk) {
+  __shared__ Smem2<T, BY, WX, VAR> sm;
+  const int nv = order == 0 ? ntiles : virtual_tiles(ntiles, order, chunk);
+  const int first = order == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  for (int vb = first; vb < nv; vb += gridDim.x) {
+    const int t = order == 2 ? xcd_chunked(vb, chunk) : vb;
+    if (t >= ntiles) continue;
+    int lo = 0, hi = ngrids - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (table[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    if (done != nullptr && done[table[lo].id] != 0) continue;
+    const GridArgs g = table[lo];
+    sweep2_tile<T, BY, WX, VAR, FL>(g, t - g.tile0, partials, sm);
+  }
+}
+
+// Instantiated two-sweep shapes: blocks of 4 to 32 rows; with more than one
+// wavefront along x, only the nontemporal-store variants and at most 32
+// rows x wavefronts (LDS: 3 planes of rows x 64*WX elements).  FP32 passes
+// (the correction sweeps of the mixed solve) keep the nontemporal variants
+// only.
+constexpr bool shape2_instantiated(int esize, int by, int wx, int var) {
+  const int tr = by * rows_per_thread(var);
+  if (tr < 4 || tr > 32 || by * wx > 16) return false;
+  const bool nt_var = var == 4 || var == 6 || var == 20;
+  if (esize == 4) return nt_var && tr * wx <= 32;
+  if (wx == 1) return var == 0 || var == 4 || var == 2 || var == 6 || var == 16 || var == 20;
+  return tr * wx <= 32 && nt_var;
+}
+
+// ---------------------------------------------------------------------
+// Host-side launch templates of the two-sweep pass
+// ---------------------------------------------------------------------
+
+template <typename T, int BY, int WX, int VAR, unsigned FL>
+hipError_t go2(const Launch& L) {
+  if constexpr (!shape2_instantiated(sizeof(T), BY, WX, VAR)) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int THREADS = WAVE * WX * BY;
+    if (L.batch) {
+      const int chunk = kBatchChunk;
+      int grid = virtual_tiles(L.ntiles, L.c->order, chunk);
+      if (L.c->persistent) {
+        static int cap = 0;
+        if (cap == 0) cap = resident_blocks(k_sweep2_batch<T, BY, WX, VAR, FL>, THREADS);
+        grid = min(grid, cap);
+      }
+      if (grid <= 0 || L.ngrids <= 0) return hipSuccess;
+      hipLaunchKernelGGL((k_sweep2_batch<T, BY, WX, VAR, FL>), dim3(grid), dim3(WAVE * WX, BY), 0, L.st,
+                         L.table, L.ngrids, L.ntiles, L.partials, L.done, L.c->order, chunk);
+    } else {
+      const GridArgs& g = *L.one;
+      int grid = virtual_tiles(g.tiles_x * g.tiles_y * g.tiles_z, g.order, g.chunk);
+      if (L.c->persistent) {
+        static int cap = 0;
+        if (cap == 0) cap = resident_blocks(k_sweep2_one<T, BY, WX, VAR, FL>, THREADS);
+        grid = min(grid, cap);
+      }
+      if (grid <= 0) return hipSuccess;
+      hipLaunchKernelGGL((k_sweep2_one<T, BY, WX, VAR, FL>), dim3(grid), dim3(WAVE * WX, BY), 0, L.st, g,
+                         L.partials, L.done);
+    }
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int BY, int WX, unsigned FL>
+hipError_t by_variant2(const Launch& L) {
+  switch (L.c->variant) {
+    case 0: return go2<T, BY, WX, 0, FL>(L);
+    case 4: return go2<T, BY, WX, 4, FL>(L);
+    case 2: return go2<T, BY, WX, 2, FL>(L);
+    case 6: return go2<T, BY, WX, 6, FL>(L);
+    case 16: return go2<T, BY, WX, 16, FL>(L);
+    case 20: return go2<T, BY, WX, 20, FL>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int BY, unsigned FL>
+hipError_t by_cols2(const Launch& L) {
+  switch (L.c->cols) {
+    case 1: return by_variant2<T, BY, 1, FL>(L);
+    case 2: return by_variant2<T, BY, 2, FL>(L);
+    case 4: return by_variant2<T, BY, 4, FL>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, unsigned FL>
+hipError_t by_rows2(const Launch& L) {
+  switch (L.c->rows) {
+    case 1: return by_cols2<T, 1, FL>(L);
+    case 2: return by_cols2<T, 2, FL>(L);
+    case 4: return by_cols2<T, 4, FL>(L);
+    case 8: return by_cols2<T, 8, FL>(L);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t dispatch_sweep2_f64(unsigned flags, const Launch& L);
+hipError_t dispatch_sweep2_f32(unsigned flags, const Launch& L);
 
 }  // namespace sweep_detail
 }  // namespace j3d

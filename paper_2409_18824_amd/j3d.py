@@ -33,6 +33,7 @@ OK, EINVAL, EDTYPE, EALIAS, ENOMEM, EBUDGET, EHIP, ENONFINITE, EAGAIN, ESTATE = 
 HOST_RESULT = 1
 MODE_FP64, MODE_MIXED = 0, 1
 KIND_F64X2 = 2  # tuning kind of the two-sweep FP64 pass
+KIND_F32X2 = 3  # tuning kind of the two-sweep FP32 pass (also the mixed solve's correction sweeps)
 
 _ERRNAMES = {0: "OK", -1: "EINVAL", -2: "EDTYPE", -3: "EALIAS", -4: "ENOMEM", -5: "EBUDGET",
              -6: "EHIP", -7: "ENONFINITE", -8: "EAGAIN", -9: "ESTATE"}
@@ -68,12 +69,12 @@ class Grid(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    """(rows, planes, variant, persistent, order); see j3d_tune in include/j3d.h."""
+    """(rows, planes, variant, persistent, order, cols); see j3d_tune in include/j3d.h."""
     _fields_ = [("rows", ctypes.c_int32), ("planes", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("order", ctypes.c_int32), ("cols", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.rows, self.planes, self.variant, self.persistent, self.order)
+        return (self.rows, self.planes, self.variant, self.persistent, self.order, self.cols)
 
 
 class ServeOpts(ctypes.Structure):
@@ -356,6 +357,9 @@ def _tune(t):
         return None
     if isinstance(t, Tune):
         return t
+    t = tuple(int(v) for v in t)
+    if len(t) == 5:  # one wavefront along x
+        t = t + (1,)
     return Tune(*t)
 
 

@@ -179,9 +179,16 @@ def test_solve_and_batch_validation_codes():
 
 def test_tune_list_and_request_bytes():
     tl = j3d.tune_list()
-    assert len(tl) == 3072 and len(set(tl)) == 3072
+    assert len(set(tl)) == len(tl)
     assert all(r in (1, 2, 4, 8) and 0 <= v <= 23 and not v & 8 and p in (0, 1) and o in (0, 1, 2)
-               for r, _, v, p, o in tl)
+               and c in (1, 2, 4) for r, _, v, p, o, c in tl)
+    # one wavefront along x: every rows x planes x variant x persistent x order
+    assert sum(1 for t in tl if t[5] == 1) == 4 * 8 * 16 * 2 * 3
+    # several along x: the nontemporal no-LDS variants, at most 16 wavefronts
+    wide = [t for t in tl if t[5] > 1]
+    assert {t[2] for t in wide} == {4, 6, 20}
+    assert all(t[0] * t[5] <= 16 for t in wide)
+    assert len(wide) == (4 + 3) * 8 * 3 * 2 * 3
     # 28 bytes per padded point (u, f FP64; r32, e0, e1 FP32) plus row padding
     b = j3d.j3d_request_bytes(384, 384, 384)
     assert 28 * 386 ** 3 <= b <= 1.1 * 28 * 386 ** 3

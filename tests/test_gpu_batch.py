@@ -27,10 +27,22 @@ def make_batch(shapes, seed=4):
 SHAPES = [(33, 40, 35), (64, 17, 90), (5, 70, 3), (128, 32, 33), (1, 1, 1), (70, 70, 70)]
 
 
-@pytest.mark.parametrize("tune", [(4, 32, 0, 0, 0), (2, 16, 1, 1, 0), (8, 8, 6, 1, 0), (1, 16, 7, 0, 0),
+@pytest.mark.parametrize("tune", [(2, 16, 20, 0, 1, 2), (1, 8, 4, 1, 2, 4), (4, 32, 0, 0, 0), (2, 16, 1, 1, 0), (8, 8, 6, 1, 0), (1, 16, 7, 0, 0),
                                   (1, 8, 20, 0, 2), (2, 4, 22, 1, 1), (1, 16, 28 - 8, 0, 2)])
 @pytest.mark.parametrize("nsweeps,every", [(20, 5), (7, 3)])
 def test_batch_matches_oracle(tune, nsweeps, every):
+    check_batch_against_oracle(tune, nsweeps, every)
+
+
+@pytest.mark.parametrize("nsweeps,every", [(20, 4), (9, 2), (6, 2), (2, 2), (8, 8), (3, 2), (1, 2), (0, 2)])
+@pytest.mark.parametrize("tune", [(1, 16, 20, 0, 1, 1), (4, 8, 6, 1, 2, 2)])
+def test_batch_two_sweep_passes_match_oracle(monkeypatch, tune, nsweeps, every):
+    """Sweeps two per pass (forced): the schedule keeps u_a/u_b placement and the residual cadence."""
+    monkeypatch.setenv("J3D_BATCH_PAIRS", "1")
+    check_batch_against_oracle(tune, nsweeps, every)
+
+
+def check_batch_against_oracle(tune, nsweeps, every):
     say("batch", tune, nsweeps, every)
     grids, host = make_batch(SHAPES)
     nres = nsweeps // every + 1
@@ -52,9 +64,11 @@ def test_batch_matches_oracle(tune, nsweeps, every):
         assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res[g], want)), (g, res[g], want)
 
 
-def test_batch_equals_solo_bitwise_and_replays():
+@pytest.mark.parametrize("pairs", ["0", "1"])
+def test_batch_equals_solo_bitwise_and_replays(monkeypatch, pairs):
+    monkeypatch.setenv("J3D_BATCH_PAIRS", pairs)
     tune = (4, 16, 0, 1, 0)
-    say("batch vs solo")
+    say("batch vs solo", pairs)
     grids, host = make_batch(SHAPES, seed=7)
     nres = 10 // 2 + 1
     out = torch.zeros((len(grids), nres), dtype=torch.float64, device="cuda")

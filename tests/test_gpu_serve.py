@@ -33,6 +33,23 @@ def run(server, reqs, gaps=None):
     return results, outs
 
 
+@pytest.mark.parametrize("cycle", [1, 2, 3, 6])
+def test_served_cycle_lengths_match_oracle(cycle):
+    """Cycle lengths that take each branch of the correction-sweep schedule."""
+    reqs = [(10, 1e-8, 400, 21, True), (13, 1e-6, 400, 22, False)]
+    say("serve cycle", cycle)
+    with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=4, cycle_sweeps=cycle) as s:
+        got, got_u = run(s, reqs)
+    for k, (n, rtol, cap, seed, _) in enumerate(reqs):
+        f = rhs(n, seed)
+        cap_c = -(-cap // cycle) * cycle  # whole cycles
+        uo, ro = oracle.solve_mixed(np.zeros((n + 2,) * 3), f, 1.0 / (n + 1), rtol=rtol, inner=cycle,
+                                    max_sweeps=cap_c)
+        assert got[k]["converged"] == ro.converged and got[k]["sweeps"] == ro.sweeps
+        assert rel(got[k]["resid"], ro.resid) <= RESID_RTOL
+        assert np.array_equal(got_u[k], uo)
+
+
 def test_served_equals_oracle_and_solo():
     reqs = [(12, 1e-8, 5000, 11, True), (16, 1e-6, 5000, 12, False), (20, 1e-8, 300, 13, True),
             (9, 1e-10, 5000, 14, False), (24, 1e-6, 200, 15, True)]

@@ -63,7 +63,9 @@ def test_plain_early_exit_matches_oracle():
 
 
 @pytest.mark.parametrize("n,inner,rtol,cap", [(24, 50, 1e-8, 100000), (13, 7, 1e-10, 100000),
-                                              (16, 50, 1e-14, 120), (10, 1, 1e-3, 1000)])
+                                              (16, 50, 1e-14, 120), (10, 1, 1e-3, 1000), (11, 2, 1e-9, 100000),
+                                              (12, 3, 1e-9, 100000), (9, 4, 1e-9, 100000), (14, 6, 1e-12, 53),
+                                              (70, 50, 1e-7, 100000)])
 def test_mixed_matches_oracle(n, inner, rtol, cap):
     say("mixed", n, inner, rtol, cap)
     h = 1.0 / (n + 1)

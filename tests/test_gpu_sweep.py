@@ -16,8 +16,9 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 from paper_2409_18824_amd import j3d  # noqa: E402
 
 SHAPES = [(1, 1, 1), (4, 4, 4), (3, 4, 5), (17, 9, 33), (64, 64, 64), (130, 67, 45), (65, 3, 70)]
-# (rows, planes, variant bits: 1 LDS, 2/16 rows per thread, 4 nontemporal; persistent; order)
-TUNES = [(1, 8, 0, 0, 0), (2, 16, 1, 0, 0), (4, 32, 2, 0, 0), (4, 32, 3, 1, 0), (8, 64, 4, 1, 0), (8, 128, 7, 0, 0),
+# (rows, planes, variant bits: 1 LDS, 2/16 rows per thread, 4 nontemporal; persistent; order[; cols])
+TUNES = [(1, 16, 20, 0, 1, 2), (2, 8, 4, 1, 0, 4), (4, 32, 6, 0, 2, 2), (1, 4, 20, 0, 0, 4), (8, 16, 4, 0, 1, 2),
+         (4, 2, 20, 1, 2, 4), (1, 8, 0, 0, 0), (2, 16, 1, 0, 0), (4, 32, 2, 0, 0), (4, 32, 3, 1, 0), (8, 64, 4, 1, 0), (8, 128, 7, 0, 0),
          (1, 16, 6, 0, 0), (2, 8, 5, 1, 0), (1, 1, 4, 0, 1), (2, 4, 1, 1, 1), (8, 2, 7, 0, 1),
          (1, 8, 22, 0, 1), (4, 32, 22, 0, 0), (2, 2, 23, 1, 1), (8, 16, 19, 0, 0), (1, 4, 20, 0, 1),
          (1, 8, 20, 0, 2), (4, 16, 6, 1, 2), (2, 4, 21, 0, 2), (1, 1, 18, 1, 2)]
@@ -72,7 +73,7 @@ def test_sweep_fp64_parity(shape, tune):
     assert j3d.residual_l2(du, df, h) == float(r.item())
 
 
-TUNES2 = [(4, 8, 0, 0, 0), (8, 32, 4, 0, 1), (4, 16, 4, 0, 2), (4, 1, 0, 1, 1), (8, 3, 0, 1, 2),
+TUNES2 = [(1, 32, 20, 0, 1, 2), (4, 16, 4, 0, 2, 2), (2, 16, 20, 0, 1, 4), (8, 8, 6, 1, 0, 2), (4, 8, 0, 0, 0), (8, 32, 4, 0, 1), (4, 16, 4, 0, 2), (4, 1, 0, 1, 1), (8, 3, 0, 1, 2),
           (2, 128, 2, 0, 0), (1, 16, 20, 0, 1), (4, 8, 16, 1, 2), (8, 16, 6, 0, 0), (2, 32, 20, 0, 2)]
 SHAPES2 = [(1, 1, 1), (3, 4, 5), (62, 6, 9), (63, 7, 10), (130, 30, 17), (17, 45, 64), (200, 14, 3)]
 
@@ -117,7 +118,7 @@ def test_sweep2_full_size_512():
     assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
 
 
-@pytest.mark.parametrize("tune", [(1, 8, 0, 0, 0), (4, 32, 1, 0, 0), (8, 16, 0, 1, 0), (2, 16, 6, 0, 2), (4, 64, 7, 1, 0),
+@pytest.mark.parametrize("tune", [(2, 16, 20, 0, 1, 2), (1, 8, 6, 1, 0, 4), (1, 8, 0, 0, 0), (4, 32, 1, 0, 0), (8, 16, 0, 1, 0), (2, 16, 6, 0, 2), (4, 64, 7, 1, 0),
                                   (1, 8, 22, 0, 1), (2, 4, 23, 1, 0)])
 def test_sweep_fp32_parity(tune):
     nx, ny, nz = 70, 13, 21
@@ -136,6 +137,37 @@ def test_sweep_fp32_parity(tune):
     assert got.dtype == np.float32
     # same order, correctly rounded FP32 division, no contraction: bitwise
     assert np.array_equal(got, want)
+
+
+TUNES2_F32 = [(4, 32, 20, 0, 1, 1), (1, 16, 20, 0, 2, 2), (2, 8, 6, 1, 0, 2), (4, 16, 4, 0, 1, 2), (2, 4, 20, 0, 0, 4),
+              (8, 64, 6, 0, 2, 1), (1, 8, 20, 1, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", [(70, 13, 21), (1, 1, 1), (130, 40, 9), (62, 14, 33)])
+@pytest.mark.parametrize("tune", TUNES2_F32)
+def test_sweep2_fp32_equals_two_fp32_sweeps(shape, tune):
+    nx, ny, nz = shape
+    say("sweep2 fp32", shape, tune)
+    e = synth.uniform_field(nx, ny, nz, 6, 1, -1, 1).astype(np.float32)
+    r32 = synth.uniform_field(nx, ny, nz, 6, 2, -1, 1).astype(np.float32)
+    h = 1.0 / (max(shape) + 1)
+    h2 = np.float32(h * h)
+    j3d.j3d_tune_set_single(j3d.KIND_F32X2, nx, ny, nz, tune)
+    de = j3d.FArray.from_numpy(e, dtype=j3d.F32)
+    stale = e.copy()
+    stale[1:-1, 1:-1, 1:-1] = -3.0  # same halo, stale interior
+    do = j3d.FArray.from_numpy(stale, dtype=j3d.F32)
+    dr = j3d.FArray.from_numpy(r32, dtype=j3d.F32)
+    j3d.jacobi3d_sweep2(de, do, dr, h)
+    torch.cuda.synchronize()
+    got = do.to_numpy()
+    want = oracle.sweep_f32(oracle.sweep_f32(e, r32, h2), r32, h2)
+    assert got.dtype == np.float32
+    assert np.array_equal(got, want)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(j3d.J3DError) as ei:
+        j3d.jacobi3d_sweep2(de, do, dr, h, resid_out=r)
+    assert ei.value.code == j3d.EDTYPE
 
 
 def test_fp32_fused_residual_rejected():
