@@ -150,6 +150,29 @@ int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
 int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags,
                 double* out, void* stream);
 
+/*
+ * Fortran's sum and dot_product intrinsics over contiguous FP64 vectors
+ * (a whole contiguous array of any rank is the vector of its elements).
+ * The paper lowers both to a reduction initialised at zero that adds every
+ * element, or every elementwise product, into the accumulator (Sec.
+ * "Handling of other constructs"); its intrinsics table runs them on a
+ * 32768 x 32768 FP64 array (sum) and on FP64 vectors of 134 million
+ * elements (dot_product).
+ *
+ * x, y: device arrays of n doubles (borrowed, 8-byte aligned, read only; x
+ * and y may be the same array).  n >= 0 (n = 0 gives 0).  *out: a device
+ * address (must not overlap x or y), or a host address with
+ * J3D_HOST_RESULT in flags (then the call synchronises the stream).
+ * Products are rounded to FP64 before they are added (no fused
+ * multiply-add).  The additions follow a fixed partition of n into blocks
+ * and a fixed tree within and across blocks, so the result depends only on
+ * the inputs and n, bit for bit; its error is within the recursive-summation
+ * bound of that tree.  Errors: J3D_EINVAL (null or misaligned pointer,
+ * n < 0, unknown flags), J3D_EALIAS, J3D_EHIP.
+ */
+int j3d_sum(const double* x, int64_t n, uint32_t flags, double* out, void* stream);
+int j3d_dot(const double* x, const double* y, int64_t n, uint32_t flags, double* out, void* stream);
+
 /* Solver modes */
 #define J3D_MODE_FP64 0  /* FP64 Jacobi sweeps */
 #define J3D_MODE_MIXED 1 /* FP32 correction sweeps with FP64 defect correction */
@@ -267,10 +290,10 @@ int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* st
 /* Kernel kinds for the single-grid tuning calls: J3D_F64 and J3D_F32 name
  * the one-sweep passes of that element type, J3D_KIND_F64X2 and
  * J3D_KIND_F32X2 the two-sweep passes of jacobi3d_sweep2 (the FP32 one also
- * runs the correction sweeps of the mixed solve).  Two-sweep shapes have
- * rows x rows-per-thread between 4 and 32 (a block of that many rows has
- * that many minus 2 output rows, and 64*cols - 2 output columns); variant
- * bits 2, 4, 16 as above, no LDS bit since the pass always uses LDS. */
+ * runs the correction sweeps of the mixed solve).  Two-sweep shapes have one
+ * wavefront along x (cols = 1) and rows x rows-per-thread between 4 and 32
+ * (a block of that many rows has that many minus 2 output rows, and 60
+ * output columns); variant bits 2, 4, 16 as above, no LDS bit. */
 #define J3D_KIND_F64X2 2
 #define J3D_KIND_F32X2 3
 

@@ -545,9 +545,10 @@ int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st) 
   return rc;
 }
 
-// Tunes the two-sweep batched pass and decides whether it beats two
-// one-sweep passes of shape c on these grids.
-int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, TileCfg* best2, bool* pairs,
+// Tunes the two-sweep batched pass (or, with keep_c2, times the shape in
+// *best2 only) and decides whether it beats two one-sweep passes of shape c
+// on these grids.
+int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, bool keep_c2, TileCfg* best2, bool* pairs,
                            hipStream_t st) {
   const int n = (int)bf.a.size();
   GridArgs* dtab = nullptr;
@@ -584,7 +585,8 @@ int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, TileCfg* bes
   };
   float t2 = 0.f, t1 = 0.f;
   TileCfg one = c;
-  rc = time_list(st, best2, sweep2_candidates(J3D_F64), launch2, &t2);
+  const std::vector<TileCfg> cand2 = keep_c2 ? std::vector<TileCfg>{*best2} : sweep2_candidates(J3D_F64);
+  rc = time_list(st, best2, cand2, launch2, &t2);
   if (rc == J3D_OK) rc = time_list(st, &one, std::vector<TileCfg>{c}, launch1, &t1);
   (void)hipStreamSynchronize(st);
   (void)hipFree(dtab);
@@ -622,17 +624,27 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
   // the two-sweep pass is the faster one on this batch (decided once per
   // batch shape class).
   // J3D_BATCH_PAIRS=0 / =1 turns the choice off / on regardless of timing.
+  // With an explicit tile shape the two-sweep passes use that shape too when
+  // the two-sweep kernel has it (else the default two-sweep shape), so that
+  // a grid's numbers do not depend on the batch it is in.
   bool pairs = false;
   TileCfg c2 = default_cfg2(J3D_F64, 64, 64, 64);
+  if (tune != nullptr && tile2_cfg_supported(J3D_F64, c)) c2 = c;
   const char* force = getenv("J3D_BATCH_PAIRS");
   const int mode = (force && *force == '0') ? 0 : (force && *force == '1') ? 1 : -1;
   if (mode != 0 && nsweeps >= 2 && (resid_out == nullptr || resid_every % 2 == 0)) {
-    const std::string k2 = batch_key(ngrids, bf.a.data()) + ":x2";
-    if (!pair_lookup(k2, &c2, &pairs)) {
-      J3D_TRY(autotune_batch2_fields(bf, c, &c2, &pairs, st));
-      pair_store(k2, c2, pairs);
+    if (mode == 1 && tune != nullptr) {
+      pairs = true;
+    } else {
+      char sig[64];
+      snprintf(sig, sizeof sig, ":x2:%d", tune != nullptr ? 1 : 0);
+      const std::string k2 = batch_key(ngrids, bf.a.data()) + sig;
+      if (!pair_lookup(k2, &c2, &pairs)) {
+        J3D_TRY(autotune_batch2_fields(bf, c, tune != nullptr, &c2, &pairs, st));
+        pair_store(k2, c2, pairs);
+      }
+      if (mode == 1) pairs = true;
     }
-    if (mode == 1) pairs = true;
   }
   // Plan key: every descriptor, h, counts, output and tile shapes.
   std::string key;

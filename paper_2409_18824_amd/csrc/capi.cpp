@@ -47,7 +47,9 @@ TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
 
 TileCfg default_cfg2(int dtype, int nx, int ny, int nz) {
   TileCfg c;
-  if (tune_cache_lookup_single(dtype == J3D_F32 ? J3D_KIND_F32X2 : J3D_KIND_F64X2, nx, ny, nz, &c)) return c;
+  if (tune_cache_lookup_single(dtype == J3D_F32 ? J3D_KIND_F32X2 : J3D_KIND_F64X2, nx, ny, nz, &c) &&
+      tile2_cfg_supported(dtype == J3D_F32 ? J3D_F32 : J3D_F64, c))
+    return c;
   c.rows = 4;  // 16 rows per block (4 per thread), nontemporal stores
   c.planes = 32;
   c.variant = 20;
@@ -260,6 +262,44 @@ int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps,
   (void)hipEventDestroy(e1);
   *gbps = best;
   return J3D_OK;
+}
+
+// sum and dot_product share one path: y == nullptr selects the sum.
+static int reduce_vec(const double* x, const double* y, int64_t n, uint32_t flags, double* out, void* stream,
+                      const char* what) {
+  if (out == nullptr) return fail(J3D_EINVAL, "%s: out is a null pointer", what);
+  if (n < 0) return fail(J3D_EINVAL, "%s: n must be >= 0", what);
+  if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "%s: unknown flags 0x%x", what, flags);
+  if (n > 0 && x == nullptr) return fail(J3D_EINVAL, "%s: x is a null pointer", what);
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(out)) % 8 != 0)
+    return fail(J3D_EINVAL, "%s: pointers must be 8-byte aligned", what);
+  const bool host = (flags & J3D_HOST_RESULT) != 0;
+  if (!host && n > 0) {
+    const bool in_x = out >= x && out < x + n;
+    const bool in_y = y != nullptr && out >= y && out < y + n;
+    if (in_x || in_y) return fail(J3D_EALIAS, "%s: out overlaps an input", what);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  J3D_TRY(ensure_partials(s, (size_t)sum_blocks(n)));
+  double* dst = host ? &s->ctl->value : out;
+  J3D_HIP(launch_sum(x, y, n, s->partials, dst, st));
+  if (host) {
+    J3D_HIP(hipMemcpyAsync(&s->ctl_host->value, &s->ctl->value, sizeof(double), hipMemcpyDeviceToHost, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    *out = s->ctl_host->value;
+  }
+  return J3D_OK;
+}
+
+int j3d_sum(const double* x, int64_t n, uint32_t flags, double* out, void* stream) {
+  return reduce_vec(x, nullptr, n, flags, out, stream, "j3d_sum");
+}
+
+int j3d_dot(const double* x, const double* y, int64_t n, uint32_t flags, double* out, void* stream) {
+  if (n > 0 && y == nullptr) return fail(J3D_EINVAL, "j3d_dot: y is a null pointer");
+  return reduce_vec(x, y, n, flags, out, stream, "j3d_dot");
 }
 
 int j3d_release_cache(void) {

@@ -58,9 +58,9 @@ bool tile_cfg_supported(const TileCfg& c);
 // Number of tiles of one grid under a tile shape.
 void tile_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
 
-// Tile shapes of the two-sweep pass of element type dtype: a block of
-// (64*cols) x (rows x rows-per-thread) columns with (64*cols - 2) x
-// (rows x rows-per-thread - 2) outputs.
+// Tile shapes of the two-sweep pass of element type dtype (cols = 1): a block
+// of 64 x (rows x rows-per-thread) columns with 60 x (rows x rows-per-thread
+// - 2) outputs.
 bool tile2_cfg_supported(int dtype, const TileCfg& c);
 void tile2_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
 
@@ -111,6 +111,15 @@ hipError_t launch_reduce_batch(const double* partials, const GridArgs* table, in
                                double* out, int ostride, int q, const double* normf,
                                const double* rtol, long long s, int* done, long long* conv_at,
                                int* nonfinite, hipStream_t st);
+
+// sum / dot_product of FP64 vectors (y null: sum of x).  Blocks of the
+// fixed partition of n (sum_blocks(n) partial slots, at most kSumMaxBlocks),
+// then the fixed-pattern sum of the partials into *out (device).
+constexpr int kSumMaxBlocks = 65536;
+long long sum_chunk(long long n);
+int sum_blocks(long long n);
+hipError_t launch_sum(const double* x, const double* y, long long n, double* partials, double* out,
+                      hipStream_t st);
 
 hipError_t launch_fill_uniform(double* a, int ex, int ey, int ez, long long sy, long long sz,
                                unsigned long long key, double lo, double hi, double halo,

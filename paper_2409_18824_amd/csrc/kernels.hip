@@ -26,6 +26,8 @@ using sweep_detail::wave_sum;
 constexpr int RED_THREADS = 1024;
 constexpr int RED_WAVES = RED_THREADS / WAVE;
 constexpr int RED_UNROLL = 16;
+constexpr int SUM_THREADS = 256;
+constexpr int SUM_UNROLL = 8;
 
 // Thread q adds slots q, q + 1024, q + 2048, ... in that order (loads are
 // issued 16 at a time so they overlap, the additions stay in order), then the
@@ -92,6 +94,53 @@ __global__ void __launch_bounds__(RED_THREADS)
         if (bad) nonfinite[g] = 1;
       }
     }
+  }
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+    k_reduce_plain(const double* __restrict__ partials, int n, double* out) {
+  __shared__ double sred[RED_WAVES];
+  const double tot = reduce_slots(partials, n, sred);
+  if (threadIdx.x == 0) *out = tot;
+}
+
+// ---------------------------------------------------------------------
+// sum / dot_product over FP64 vectors
+// ---------------------------------------------------------------------
+
+// Block b adds the addends of [b*chunk, min(n, (b+1)*chunk)): thread t takes
+// elements t, t+256, t+512, ... in that order (eight loads issued at once,
+// additions in order), then the wavefront butterfly and the four wavefront
+// sums in order; the block's sum goes to partials[b].  The partition depends
+// on n only, so the result is reproducible bit for bit.
+template <bool DOT>
+__global__ void __launch_bounds__(SUM_THREADS)
+    k_sum_partials(const double* __restrict__ x, const double* __restrict__ y, long long n,
+                   long long chunk, double* __restrict__ partials) {
+  __shared__ double red[SUM_THREADS / WAVE];
+  const long long lo = (long long)blockIdx.x * chunk;
+  const long long hi = min(n, lo + chunk);
+  double a = 0.0;
+  long long i = lo + threadIdx.x;
+  for (; i + (SUM_UNROLL - 1) * SUM_THREADS < hi; i += SUM_UNROLL * SUM_THREADS) {
+    double v[SUM_UNROLL];
+#pragma unroll
+    for (int u = 0; u < SUM_UNROLL; ++u) {
+      v[u] = x[i + u * SUM_THREADS];
+      if (DOT) v[u] = v[u] * y[i + u * SUM_THREADS];
+    }
+#pragma unroll
+    for (int u = 0; u < SUM_UNROLL; ++u) a += v[u];
+  }
+  for (; i < hi; i += SUM_THREADS) a += DOT ? x[i] * y[i] : x[i];
+  a = wave_sum(a);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+#pragma unroll
+    for (int w = 1; w < SUM_THREADS / WAVE; ++w) t += red[w];
+    partials[blockIdx.x] = t;
   }
 }
 
@@ -207,7 +256,10 @@ bool tile2_cfg_supported(int dtype, const TileCfg& c) {
 }
 
 void tile2_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz) {
-  const int w = sweep_detail::sweep2_cols(c.cols), h = c.rows * sweep_detail::rows_per_thread(c.variant) - 2;
+  // Unsupported shapes (zero or negative extents) count one tile per axis; they
+  // are rejected before any launch.
+  const int w = max(1, sweep_detail::sweep2_cols(c.cols));
+  const int h = max(1, c.rows * sweep_detail::rows_per_thread(c.variant) - 2);
   *tx = (nx + w - 1) / w;
   *ty = (ny + h - 1) / h;
   *tz = (nz + c.planes - 1) / c.planes;
@@ -293,6 +345,29 @@ hipError_t launch_fill_const(void* a, int dtype, int ex, int ey, int ez, long lo
   else
     hipLaunchKernelGGL(k_fill_const<float>, grid, dim3(256), 0, st, static_cast<float*>(a), ex, sy,
                        sz, static_cast<float>(v));
+  return hipGetLastError();
+}
+
+long long sum_chunk(long long n) {
+  const long long step = (long long)SUM_THREADS * SUM_UNROLL;
+  const long long per = (n + (long long)kSumMaxBlocks * step - 1) / ((long long)kSumMaxBlocks * step);
+  return step * (per < 1 ? 1 : per);
+}
+
+int sum_blocks(long long n) { return n <= 0 ? 0 : (int)((n + sum_chunk(n) - 1) / sum_chunk(n)); }
+
+hipError_t launch_sum(const double* x, const double* y, long long n, double* partials, double* out,
+                      hipStream_t st) {
+  const int nb = sum_blocks(n);
+  if (nb > 0) {
+    if (y != nullptr)
+      hipLaunchKernelGGL(k_sum_partials<true>, dim3(nb), dim3(SUM_THREADS), 0, st, x, y, n, sum_chunk(n),
+                         partials);
+    else
+      hipLaunchKernelGGL(k_sum_partials<false>, dim3(nb), dim3(SUM_THREADS), 0, st, x, y, n, sum_chunk(n),
+                         partials);
+  }
+  hipLaunchKernelGGL(k_reduce_plain, dim3(1), dim3(RED_THREADS), 0, st, partials, nb, out);
   return hipGetLastError();
 }
 

@@ -1,28 +1,31 @@
 // Two Jacobi sweeps in one pass over HBM (temporal blocking in z), in FP64
 // or FP32.
 //
-// u2 = J(J(u0)).  A workgroup of BY rows of WX 64-lane wavefronts, each
-// thread owning RY consecutive rows (register blocking in y), covers a block
-// of 64*WX x (BY*RY) columns: thread (l, w), row r is column
-// (x0 - 1 + l, y0 - 1 + w*RY + r).  The inner (64*WX - 2) x (BY*RY - 2)
-// columns are the tile's outputs; the outer ring is recomputed redundantly by
-// the neighbouring tiles.  Marching through z, at
-// step k the block
-//   1. computes the intermediate iterate u1 at plane k on all its columns
-//      (from u0 planes k-1, k, k+1 held in registers and u0's x/y
-//      neighbours read through the cache), with u1 = u0 on the Dirichlet
-//      halo, and stores it in an LDS plane buffer;
-//   2. after one barrier, computes u2 at plane k-1 on the inner columns from
-//      u1's x/y neighbours in LDS and u1 at planes k-2 and k in registers.
-// u1 never reaches HBM: per pair of sweeps the pass streams u0 and f once and
-// writes u2 once.  The LDS plane buffers rotate over three slots so one
-// barrier per plane suffices (a slot is rewritten two steps after it was
-// last read, and every thread has passed the barrier in between).
+// u2 = J(J(u0)).  A workgroup of BY 64-lane wavefronts, each thread owning
+// RY consecutive rows (register blocking in y), covers a block of 64 x
+// (BY*RY) columns: thread (l, w), row r is column (x0 - 2 + l, y0 - 1 +
+// w*RY + r).  Marching through z, at step k the block
+//   1. computes the intermediate iterate u1 at plane k on lanes 1..62 of
+//      every row (u1 = u0 on the Dirichlet halo), from u0 planes k-1, k, k+1
+//      held in registers;
+//   2. computes u2 at plane k-1 on lanes 2..61 of the inner rows from u1
+//      planes k-2, k-1, k held in registers.
+// The x-neighbours in both stages come from the adjacent lanes of the same
+// wavefront by DPP wave shifts (no memory access: the lanes at the block's
+// x edges only feed columns that are not output), and the y-neighbours from
+// the thread's own rows, except at a wavefront's first and last row: stage
+// 1 loads those u0 rows through the cache, stage 2 exchanges the u1 edge rows
+// between wavefronts through LDS.  Only these edge rows take a barrier per
+// plane; they rotate over three LDS slots so one barrier per plane
+// suffices.  u1 never reaches HBM: per pair of sweeps the pass streams u0
+// and f once and writes u2 once.  The outputs of a block are its inner 60 x
+// (BY*RY - 2) columns; the ring around them is recomputed by the
+// neighbouring blocks.
 //
 // Each point of u1 and u2 is computed with exactly the arithmetic of a
 // single sweep (same neighbour order, no contraction), so the result equals
 // two separate sweeps bit for bit.  The fused residual, when requested, is
-// that of u0 (the input), accumulated by the inner columns only.
+// that of u0 (the input), accumulated by the output columns only.
 #pragma once
 
 #include "sweep.h"
@@ -30,16 +33,40 @@
 namespace j3d {
 namespace sweep_detail {
 
-// Output columns per tile in x for WX wavefronts side by side.
-constexpr int sweep2_cols(int wx) { return WAVE * wx - 2; }
+// Output columns per tile in x (one wavefront along x).
+constexpr int sweep2_cols(int wx) { return wx == 1 ? WAVE - 4 : 0; }
 
-// Rows per thread of the two-sweep pass (variant bits 2 and 16, as in the
-// one-sweep pass).
+typedef int dpp_i2 __attribute__((ext_vector_type(2)));
+
+// The value of lane l-1 (from_left) or l+1 (from_right) of the wavefront;
+// lane 0 (resp. 63) gets its own value.  DPP wave_shr:1 / wave_shl:1.
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
+                                                               __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
+                                                               __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x138, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x138, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x130, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+
 template <typename T, int BY, int WX, int VAR>
 struct Smem2 {
-  static constexpr int TR = BY * rows_per_thread(VAR);  // rows of the block
-  T pl[3][TR][WAVE * WX];
-  double red[BY * WX];
+  T edge[3][BY][2][WAVE];  // plane slot, wavefront, first/last row of u1
+  double red[BY];
 };
 
 // Flags: F_WRITE (store u2 to g.o), F_RES (FP64: residual of u0), F_FIRST
@@ -49,9 +76,10 @@ struct Smem2 {
 template <typename T, int BY, int WX, int VAR, unsigned FL>
 __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __restrict__ partials,
                                             Smem2<T, BY, WX, VAR>& sm) {
+  static_assert(WX == 1, "the two-sweep pass uses one wavefront along x");
   constexpr int RY = rows_per_thread(VAR);
   constexpr int TR = BY * RY;   // block rows
-  constexpr int W = sweep2_cols(WX);
+  constexpr int W = sweep2_cols(1);
   constexpr int H = TR - 2;     // output rows per tile
   constexpr bool NT = (VAR & 4) != 0;
   constexpr bool ZERO = (FL & F_FIRST) != 0;
@@ -63,14 +91,13 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
   const int t2 = t / g.tiles_x;
   const int ty = t2 % g.tiles_y;
   const int tz = t2 / g.tiles_y;
-  const int xi = tx * W + lane;  // column x (0 .. beyond nx+1 on the last tile)
+  const int xi = tx * W - 1 + lane;  // column x (-1 .. beyond nx+1 at the x ends)
   const int k0 = 1 + tz * g.planes;
   const int k1 = min(k0 + g.planes, g.nz + 1);
-  const bool lane_in = lane >= 1 && lane <= W;
+  const bool lane_out = lane >= 2 && lane <= W + 1;
   const bool x_in = xi >= 1 && xi <= g.nx;
   // Every address is clamped into the array, halo included.
-  const int xc = min(xi, g.nx + 1);
-  const int xm = max(xc - 1, 0), xp = min(xc + 1, g.nx + 1);
+  const int xc = min(max(xi, 0), g.nx + 1);
   const T* __restrict__ u0 = static_cast<const T*>(g.u);
   const T* __restrict__ f = static_cast<const T*>(g.f);
   T* __restrict__ out = static_cast<T*>(g.o);
@@ -88,7 +115,7 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
     cu[r] = xc + g.su_y * yc;
     cf[r] = xc + g.sf_y * yc;
     co[r] = (FL & F_LAST) ? xc + g.s64_y * yc : xc + g.so_y * yc;
-    inner[r] = lane_in && br[r] >= 1 && br[r] <= H;
+    inner[r] = lane_out && br[r] >= 1 && br[r] <= H;
     col_in[r] = x_in && yj >= 1 && yj <= g.ny;
   }
   // y-neighbour rows outside this thread's rows: one below the first, one
@@ -109,21 +136,15 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
   }
 
   for (int k = k0 - 1; k <= k1; ++k) {
-    // Stage 1: u1 at plane k on every column of the block.
+    // Stage 1: u1 at plane k on every row of the block.
     const int kp = min(k + 1, ztop);
     const int kf = min(max(k, 1), g.nz);
     const int zk = g.su_z * k;
-    T u0p[RY], fk[RY], nxm[RY], nxp[RY];
+    T u0p[RY], fk[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       fk[r] = f[cf[r] + g.sf_z * kf];
-      if (ZERO) {
-        u0p[r] = nxm[r] = nxp[r] = T(0);
-      } else {
-        u0p[r] = u0[cu[r] + g.su_z * kp];
-        nxm[r] = u0[cu[r] - xc + xm + zk];
-        nxp[r] = u0[cu[r] - xc + xp + zk];
-      }
+      u0p[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * kp];
     }
     const T nylo = ZERO ? T(0) : u0[cym + zk];
     const T nyhi = ZERO ? T(0) : u0[cyp + zk];
@@ -133,7 +154,7 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
       const T nym = r == 0 ? nylo : u0c[r - 1];
       const T nyp = r == RY - 1 ? nyhi : u0c[r + 1];
       const bool pt_in = col_in[r] && k >= 1 && k <= g.nz;
-      T s = nxm[r] + nxp[r];
+      T s = ZERO ? T(0) : from_left(u0c[r]) + from_right(u0c[r]);
       s = s + nym;
       s = s + nyp;
       s = s + u0m[r];
@@ -144,18 +165,25 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
                            (6.0 * static_cast<double>(u0c[r]) - static_cast<double>(s)) / g.h2;
         acc += (inner[r] && pt_in && k >= k0 && k < k1) ? res * res : 0.0;
       }
-      sm.pl[k % 3][br[r]][lane] = u1[r];
     }
+    sm.edge[k % 3][wy][0][lane] = u1[0];
+    sm.edge[k % 3][wy][1][lane] = u1[RY - 1];
     __syncthreads();
-    // Stage 2: u2 at plane k-1 on the inner columns.
+    // Stage 2: u2 at plane k-1 on the output columns.
     if (k - 1 >= k0) {
-      const T(*p1)[WAVE * WX] = sm.pl[(k + 2) % 3];  // slot of plane k-1
+      const int sl = (k + 2) % 3;  // slot of plane k-1
+      const T above = wy > 0 ? sm.edge[sl][wy - 1][1][lane] : T(0);
+      const T below = wy < BY - 1 ? sm.edge[sl][wy + 1][0][lane] : T(0);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
+        const T xm = from_left(u1m1[r]);
+        const T xp = from_right(u1m1[r]);
         if (inner[r]) {
-          T s1 = p1[br[r]][lane - 1] + p1[br[r]][lane + 1];
-          s1 = s1 + p1[br[r] - 1][lane];
-          s1 = s1 + p1[br[r] + 1][lane];
+          const T ym = r == 0 ? above : u1m1[r - 1];
+          const T yp = r == RY - 1 ? below : u1m1[r + 1];
+          T s1 = xm + xp;
+          s1 = s1 + ym;
+          s1 = s1 + yp;
           s1 = s1 + u1m2[r];
           s1 = s1 + u1[r];
           const T u2 = (s1 + h2 * fprev[r]) / T(6);
@@ -227,18 +255,15 @@ __global__ void __launch_bounds__(WAVE * WX * BY)
   }
 }
 
-// Instantiated two-sweep shapes: blocks of 4 to 32 rows; with more than one
-// wavefront along x, only the nontemporal-store variants and at most 32
-// rows x wavefronts (LDS: 3 planes of rows x 64*WX elements).  FP32 passes
-// (the correction sweeps of the mixed solve) keep the nontemporal variants
-// only.
+// Instantiated two-sweep shapes: one wavefront along x, blocks of 4 to 32
+// rows.  FP32 passes (the correction sweeps of the mixed solve) keep the
+// nontemporal-store variants only.
 constexpr bool shape2_instantiated(int esize, int by, int wx, int var) {
   const int tr = by * rows_per_thread(var);
-  if (tr < 4 || tr > 32 || by * wx > 16) return false;
+  if (wx != 1 || tr < 4 || tr > 32 || by > 16) return false;
   const bool nt_var = var == 4 || var == 6 || var == 20;
-  if (esize == 4) return nt_var && tr * wx <= 32;
-  if (wx == 1) return var == 0 || var == 4 || var == 2 || var == 6 || var == 16 || var == 20;
-  return tr * wx <= 32 && nt_var;
+  if (esize == 4) return nt_var;
+  return nt_var || var == 0 || var == 2 || var == 16;
 }
 
 // ---------------------------------------------------------------------

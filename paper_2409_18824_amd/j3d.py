@@ -126,6 +126,8 @@ _SIGS = {
     "j3d_fill_uniform": ([_P(J3DArray), _U64, _U32, _D, _D, _D, _V], ctypes.c_int),
     "j3d_fill_const": ([_P(J3DArray), _D, _V], ctypes.c_int),
     "j3d_bandwidth_probe": ([_V, _V, _I64, _I32, _P(_D), _V], ctypes.c_int),
+    "j3d_sum": ([_V, _I64, _U32, _V, _V], ctypes.c_int),
+    "j3d_dot": ([_V, _V, _I64, _U32, _V, _V], ctypes.c_int),
     "j3d_release_cache": ([], ctypes.c_int),
 }
 
@@ -310,6 +312,40 @@ def residual_l2(u: FArray, f: FArray, h: float, out=None, stream=None):
         return v.value
     _check(_lib.residual_l2(ctypes.byref(a), ctypes.byref(c), float(h), 0, ctypes.c_void_p(out.data_ptr()), st),
            "residual_l2")
+    return None
+
+
+def _vec(x, what):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+        raise TypeError("%s: a contiguous float64 CUDA tensor is required" % what)
+    return ctypes.c_void_p(x.data_ptr()), x.numel()
+
+
+def j3d_sum(x, out=None, stream=None):
+    """Fortran sum(x) of a contiguous float64 CUDA tensor.  With ``out`` (a
+    one-element device float64 tensor) asynchronous; else returns a float."""
+    px, n = _vec(x, "j3d_sum")
+    st = _stream_handle(stream)
+    if out is None:
+        v = ctypes.c_double()
+        _check(_lib.j3d_sum(px, n, HOST_RESULT, ctypes.cast(ctypes.byref(v), ctypes.c_void_p), st), "j3d_sum")
+        return v.value
+    _check(_lib.j3d_sum(px, n, 0, ctypes.c_void_p(out.data_ptr()), st), "j3d_sum")
+    return None
+
+
+def j3d_dot(x, y, out=None, stream=None):
+    """Fortran dot_product(x, y) of two contiguous float64 CUDA tensors of one size."""
+    px, n = _vec(x, "j3d_dot")
+    py, ny = _vec(y, "j3d_dot")
+    if ny != n:
+        raise ValueError("j3d_dot: x and y differ in size (%d vs %d)" % (n, ny))
+    st = _stream_handle(stream)
+    if out is None:
+        v = ctypes.c_double()
+        _check(_lib.j3d_dot(px, py, n, HOST_RESULT, ctypes.cast(ctypes.byref(v), ctypes.c_void_p), st), "j3d_dot")
+        return v.value
+    _check(_lib.j3d_dot(px, py, n, 0, ctypes.c_void_p(out.data_ptr()), st), "j3d_dot")
     return None
 
 

@@ -193,3 +193,19 @@ def test_tune_list_and_request_bytes():
     b = j3d.j3d_request_bytes(384, 384, 384)
     assert 28 * 386 ** 3 <= b <= 1.1 * 28 * 386 ** 3
     assert j3d.j3d_request_bytes(0, 4, 4) == 0
+
+
+def test_sum_dot_validation_before_device_work():
+    lib = j3d._lib
+    out = ctypes.c_double()
+    po = ctypes.cast(ctypes.byref(out), ctypes.c_void_p)
+    x = ctypes.c_void_p(0x100000)
+    assert lib.j3d_sum(x, 10, j3d.HOST_RESULT, None, None) == j3d.EINVAL  # no out
+    assert lib.j3d_sum(x, -1, j3d.HOST_RESULT, po, None) == j3d.EINVAL  # n < 0
+    assert lib.j3d_sum(None, 5, j3d.HOST_RESULT, po, None) == j3d.EINVAL  # null x
+    assert lib.j3d_sum(x, 5, 0x80, po, None) == j3d.EINVAL  # unknown flag
+    assert lib.j3d_sum(ctypes.c_void_p(0x100004), 5, j3d.HOST_RESULT, po, None) == j3d.EINVAL  # misaligned
+    assert lib.j3d_dot(x, None, 5, j3d.HOST_RESULT, po, None) == j3d.EINVAL  # null y
+    # a device result inside an input
+    assert lib.j3d_dot(x, ctypes.c_void_p(0x200000), 100, 0, ctypes.c_void_p(0x200000 + 80), None) == j3d.EALIAS
+    assert "overlaps" in j3d.last_error()

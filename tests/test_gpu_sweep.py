@@ -73,9 +73,9 @@ def test_sweep_fp64_parity(shape, tune):
     assert j3d.residual_l2(du, df, h) == float(r.item())
 
 
-TUNES2 = [(1, 32, 20, 0, 1, 2), (4, 16, 4, 0, 2, 2), (2, 16, 20, 0, 1, 4), (8, 8, 6, 1, 0, 2), (4, 8, 0, 0, 0), (8, 32, 4, 0, 1), (4, 16, 4, 0, 2), (4, 1, 0, 1, 1), (8, 3, 0, 1, 2),
+TUNES2 = [(1, 32, 20, 0, 1, 1), (4, 16, 4, 0, 2, 1), (2, 16, 20, 0, 1, 1), (8, 8, 6, 1, 0, 1), (4, 8, 0, 0, 0), (8, 32, 4, 0, 1), (4, 16, 4, 0, 2), (4, 1, 0, 1, 1), (8, 3, 0, 1, 2),
           (2, 128, 2, 0, 0), (1, 16, 20, 0, 1), (4, 8, 16, 1, 2), (8, 16, 6, 0, 0), (2, 32, 20, 0, 2)]
-SHAPES2 = [(1, 1, 1), (3, 4, 5), (62, 6, 9), (63, 7, 10), (130, 30, 17), (17, 45, 64), (200, 14, 3)]
+SHAPES2 = [(1, 1, 1), (3, 4, 5), (60, 6, 9), (61, 7, 10), (62, 6, 9), (121, 30, 17), (17, 45, 64), (200, 14, 3)]
 
 
 @pytest.mark.parametrize("shape", SHAPES2)
@@ -97,6 +97,16 @@ def test_sweep2_equals_two_sweeps(shape, tune):
     assert np.array_equal(got, want), "max diff %g" % np.max(np.abs(got - want))
     assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
     assert np.array_equal(du.to_numpy(), u)  # input untouched
+
+
+def test_sweep2_shapes_with_wide_tiles_rejected():
+    for kind in (j3d.KIND_F64X2, j3d.KIND_F32X2):
+        for t in [(4, 32, 20, 0, 1, 2), (2, 16, 20, 0, 1, 4), (4, 32, 1, 0, 1, 1), (1, 8, 0, 0, 1, 1)]:
+            with pytest.raises(j3d.J3DError) as ei:
+                j3d.j3d_tune_set_single(kind, 64, 64, 64, t)
+            assert ei.value.code == j3d.EINVAL
+    with pytest.raises(j3d.J3DError):
+        j3d.j3d_tune_set_single(j3d.KIND_F32X2, 64, 64, 64, (4, 32, 16, 0, 1, 1))  # FP32: nontemporal only
 
 
 def test_sweep2_full_size_512():
@@ -139,7 +149,7 @@ def test_sweep_fp32_parity(tune):
     assert np.array_equal(got, want)
 
 
-TUNES2_F32 = [(4, 32, 20, 0, 1, 1), (1, 16, 20, 0, 2, 2), (2, 8, 6, 1, 0, 2), (4, 16, 4, 0, 1, 2), (2, 4, 20, 0, 0, 4),
+TUNES2_F32 = [(4, 32, 20, 0, 1, 1), (1, 16, 20, 0, 2, 1), (2, 8, 6, 1, 0, 1), (4, 16, 4, 0, 1, 1), (2, 4, 20, 0, 0, 1),
               (8, 64, 6, 0, 2, 1), (1, 8, 20, 1, 1, 1)]
 
 
