@@ -63,9 +63,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash: str, passes: int):
+def measured_traffic(kernel_hash: str, passes: int, tile):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source with this tile
+    shape."""
     path = os.path.join(ROOT, "profiles", "sweep%s_fp64_512_counters.json" % ("2" if passes == 2 else ""))
     try:
         with open(path) as fp:
@@ -73,6 +74,8 @@ def measured_traffic(kernel_hash: str, passes: int):
     except (OSError, ValueError):
         return None
     if d.get("kernel_sources_sha256_16") != kernel_hash:
+        return None
+    if d.get("tile") != list(tile):
         return None
     return d.get("bytes_per_launch")
 
@@ -116,7 +119,9 @@ def main():
     ap.add_argument("--passes", type=int, default=2, choices=[1, 2],
                     help="sweeps per pass over memory (2: temporally blocked pass)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the tile shapes first and use the fastest (default: the library's default "
+                         "shape, the one the committed counter profiles were taken with)")
     ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve"])
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--active-points", type=float, default=2e8,
@@ -157,14 +162,12 @@ def main():
         raise SystemExit("two-sweep passes need even --sweeps and --resid-every")
     kind = j3d.KIND_F64X2 if P == 2 else j3d.F64
     if args.tile:
-        tune = tuple(int(x) for x in args.tile.split(","))
-        j3d.j3d_tune_set_single(kind, n, n, n, tune)
-    elif args.no_tune:
-        tune = None
-    else:
-        tune = j3d.j3d_autotune_single(kind, n, n, n)
+        j3d.j3d_tune_set_single(kind, n, n, n, tuple(int(x) for x in args.tile.split(",")))
+    elif args.autotune:
+        j3d.j3d_autotune_single(kind, n, n, n)
         if P == 2:
             j3d.j3d_autotune_single(j3d.F64, n, n, n)  # the standalone residual pass
+    tune = j3d.j3d_tune_query_single(kind, n, n, n)  # the shape the timed passes use
     print("[bench] tile shape (rows, planes, variant, persistent, order, cols) = %s" % (tune,), file=sys.stderr, flush=True)
 
     nres = S // E + 1
@@ -228,7 +231,7 @@ def main():
     kname = ("k_sweep2_one<F_WRITE> (two FP64 sweeps per pass)" if P == 2
              else "k_pass_one<double, F_WRITE> (FP64 sweep)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, P),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, P, tune),
             "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2),
             "launches": len(kernel_ms), "bytes_per_launch_algorithmic": int(bytes_launch),
             "updates_per_point_per_launch": P}

@@ -307,6 +307,10 @@ int j3d_autotune_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_tu
 /* Pin the tile shape used for single-grid calls of this kind and shape. */
 int j3d_tune_set_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t);
 
+/* The tile shape single-grid calls of this kind and interior shape use now:
+ * the pinned or autotuned one, else the library default (host-only). */
+int j3d_tune_query_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_tune* out);
+
 /* ------------------------------------------------------------------ */
 /* Serving: continuous batching of Poisson solves under a memory budget */
 /* ------------------------------------------------------------------ */

@@ -37,7 +37,7 @@ TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   TileCfg c;
   if (tune_cache_lookup_single(dtype, nx, ny, nz, &c)) return c;
   c.rows = 1;
-  c.planes = 16;
+  c.planes = 2;
   c.variant = 20;  // four rows per thread, nontemporal stores
   c.persistent = 0;
   c.order = 1;
@@ -51,7 +51,7 @@ TileCfg default_cfg2(int dtype, int nx, int ny, int nz) {
       tile2_cfg_supported(dtype == J3D_F32 ? J3D_F32 : J3D_F64, c))
     return c;
   c.rows = 4;  // 16 rows per block (4 per thread), nontemporal stores
-  c.planes = 32;
+  c.planes = 16;
   c.variant = 20;
   c.persistent = 0;
   c.order = 1;
@@ -98,6 +98,25 @@ int j3d_element_offset(const j3d_array* a, int64_t i, int64_t j, int64_t k, int6
 }
 
 int j3d_check_array(const j3d_array* a, int32_t dtype) { return check_field(a, dtype, nullptr, "array"); }
+
+int j3d_tune_query_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_tune* out) {
+  if (out == nullptr) return fail(J3D_EINVAL, "tune: null pointer");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(J3D_EINVAL, "extents must be >= 1");
+  TileCfg c;
+  if (kind == J3D_F64 || kind == J3D_F32)
+    c = default_cfg(kind, nx, ny, nz);
+  else if (kind == J3D_KIND_F64X2 || kind == J3D_KIND_F32X2)
+    c = default_cfg2(kind == J3D_KIND_F32X2 ? J3D_F32 : J3D_F64, nx, ny, nz);
+  else
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32, J3D_KIND_F64X2 or J3D_KIND_F32X2");
+  out->rows = c.rows;
+  out->planes = c.planes;
+  out->variant = c.variant;
+  out->persistent = c.persistent;
+  out->order = c.order;
+  out->cols = c.cols;
+  return J3D_OK;
+}
 
 int j3d_tune_count(void) { return (int)tune_table().size(); }
 

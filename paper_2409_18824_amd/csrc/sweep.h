@@ -15,8 +15,10 @@
 //
 // VAR selects how the tile is fed (bits may be combined):
 //   1  the current plane is staged in LDS with its x/y halo ring
-//      (double-buffered, one barrier per plane); otherwise x and y
-//      neighbours are read through the vector L1/L2 caches;
+//      (double-buffered, one barrier per plane); otherwise x-neighbours come
+//      from the adjacent lanes of the wavefront by DPP wave shifts (the two
+//      halo columns from one gather load per plane) and the y-neighbours at
+//      the block's edge rows through the vector caches;
 //   2, 16  each thread owns 2^(bit2 + 2*bit16) consecutive rows (1, 2, 4 or
 //      8): register blocking in y, which multiplies the independent HBM
 //      loads each wavefront has in flight per plane;
@@ -83,6 +85,46 @@ __device__ __forceinline__ void put(T* p, T v) {
     *p = v;
 }
 
+typedef int dpp_i2 __attribute__((ext_vector_type(2)));
+
+// The value of lane l-1 (from_left) or l+1 (from_right) of the wavefront;
+// lane 0 (resp. 63) gets its own value.  DPP wave_shr:1 / wave_shl:1; every
+// lane of the wavefront must execute the call.
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
+                                                               __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
+                                                               __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x138, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x138, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double from_right(double v) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x130, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+
+// The value lane `src` (a constant) of the wavefront holds, in every lane.
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_readlane(a.x, src);
+  r.y = __builtin_amdgcn_readlane(a.y, src);
+  return __builtin_bit_cast(double, r);
+}
+
 // Rows per thread encoded in the variant bits 2 and 16.
 constexpr int rows_per_thread(int var) { return 1 << (((var >> 1) & 1) + 2 * ((var >> 4) & 1)); }
 
@@ -119,10 +161,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 //
 // Each thread owns RY consecutive rows of its column (register blocking in
 // y as well as z): per plane it issues the 2*RY HBM loads of its rows at
-// once, and the y-neighbours inside its block come from registers.  Every
-// lane loads from in-bounds addresses (lanes and rows past the interior are
-// clamped onto the last interior column/row), so loads need no per-lane
-// branches; only stores and sums are masked.
+// once, the y-neighbours inside its block come from registers and, in the
+// cache-fed variants, the x-neighbours from the adjacent lanes.  Every lane
+// loads from in-bounds addresses (lanes and rows past the interior are
+// clamped onto the halo column/row), so loads need no per-lane branches;
+// only stores and sums are masked.
 template <typename T, int BY, int WX, int VAR, unsigned FL>
 __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __restrict__ partials,
                                            Smem<T, BY, WX, VAR>& sm) {
@@ -143,18 +186,31 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
   const int k0 = 1 + tz * g.planes;
   const int k1 = min(k0 + g.planes, g.nz + 1);
   const bool ix = i <= g.nx;
-  const int ic = min(i, g.nx);
+  const int ic = min(i, g.nx + 1);  // lanes past the interior read the halo column
   const int jc = min(jb, g.ny);
 
-  // Row r of the block is row jb + r, clamped; dj[r] is its offset in rows
-  // from row jc (uniform across the wavefront).
+  // Row r of the block is row jb + r, clamped onto the halo row ny+1; dj[r]
+  // is its offset in rows from row jc (uniform across the wavefront).  With
+  // the clamp, the register holding row r+1 is the correct y-neighbour of
+  // row r for every interior row.
   int dj[RY];
   bool act[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    dj[r] = min(jb + r, g.ny) - jc;
+    dj[r] = min(jb + r, g.ny + 1) - jc;
     act[r] = ix && (jb + r <= g.ny);
   }
+  // Cache-fed stencil: x-neighbours come from the adjacent lanes (DPP), the
+  // two halo columns of the wavefront's rows from one gather per plane: lane
+  // q < RY loads the column left of the wavefront in row q, lane 32 + q the
+  // column right of it.
+  const int lw = lane & (WAVE - 1);
+  const int xw = 1 + tx * TX + (lane - lw);  // first column of this wavefront
+  const int gq = lw < 32 ? lw : lw - 32;
+  const bool gat = gq < RY;
+  const int goff = (lw < 32 ? xw - 1 : min(xw + WAVE, g.nx + 1)) - ic +
+                   (min(jb + min(gq, RY - 1), g.ny + 1) - jc) * g.su_y;
+  const int yhi_off = (min(jb + RY, g.ny + 1) - jc) * g.su_y;
 
   const T* __restrict__ pu = static_cast<const T*>(g.u) + (ic + g.su_y * jc + g.su_z * k0);
   const T* __restrict__ pf = static_cast<const T*>(g.f) + (ic + g.sf_y * jc + g.sf_z * k0);
@@ -183,13 +239,21 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
       fc[r] = pf[dj[r] * g.sf_y];
       up[r] = STENCIL ? u_r[g.su_z] : T(0);
       xm[r] = xp[r] = ym[r] = yp[r] = T(0);
-      if (STENCIL && !USE_LDS) {
-        xm[r] = u_r[-1];
-        xp[r] = u_r[1];
-        // y-neighbours: registers inside the block, loads at its edges and
-        // where the next row is the halo.
-        ym[r] = (r == 0) ? u_r[-g.su_y] : uc[r - 1];
-        yp[r] = (r + 1 < RY && jb + r < g.ny) ? uc[r + 1] : u_r[g.su_y];
+    }
+    if (STENCIL && !USE_LDS) {
+      const T halo = gat ? pu[goff] : T(0);
+      const T below = pu[-g.su_y];
+      const T above = pu[yhi_off];
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        xm[r] = from_left(uc[r]);
+        xp[r] = from_right(uc[r]);
+        const T hl = lane_value(halo, r), hr = lane_value(halo, 32 + r);
+        if (lw == 0) xm[r] = hl;
+        if (lw == WAVE - 1) xp[r] = hr;
+        // y-neighbours: registers inside the block, loads at its edges.
+        ym[r] = r == 0 ? below : uc[r - 1];
+        yp[r] = r + 1 < RY ? uc[r + 1] : above;
       }
     }
     if (USE_LDS) {

@@ -36,33 +36,6 @@ namespace sweep_detail {
 // Output columns per tile in x (one wavefront along x).
 constexpr int sweep2_cols(int wx) { return wx == 1 ? WAVE - 4 : 0; }
 
-typedef int dpp_i2 __attribute__((ext_vector_type(2)));
-
-// The value of lane l-1 (from_left) or l+1 (from_right) of the wavefront;
-// lane 0 (resp. 63) gets its own value.  DPP wave_shr:1 / wave_shl:1.
-__device__ __forceinline__ float from_left(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
-                                                               __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float from_right(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v),
-                                                               __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double from_left(double v) {
-  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
-  dpp_i2 r;
-  r.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x138, 0xF, 0xF, false);
-  r.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x138, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, r);
-}
-__device__ __forceinline__ double from_right(double v) {
-  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
-  dpp_i2 r;
-  r.x = __builtin_amdgcn_update_dpp(a.x, a.x, 0x130, 0xF, 0xF, false);
-  r.y = __builtin_amdgcn_update_dpp(a.y, a.y, 0x130, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, r);
-}
-
 template <typename T, int BY, int WX, int VAR>
 struct Smem2 {
   T edge[3][BY][2][WAVE];  // plane slot, wavefront, first/last row of u1

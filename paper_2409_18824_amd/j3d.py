@@ -116,6 +116,7 @@ _SIGS = {
     "j3d_autotune": ([_I32, _P(Grid), _P(Tune), _V], ctypes.c_int),
     "j3d_autotune_single": ([_I32, _I32, _I32, _I32, _P(Tune), _V], ctypes.c_int),
     "j3d_tune_set_single": ([_I32, _I32, _I32, _I32, _P(Tune)], ctypes.c_int),
+    "j3d_tune_query_single": ([_I32, _I32, _I32, _I32, _P(Tune)], ctypes.c_int),
     "j3d_request_bytes": ([_I32, _I32, _I32], _U64),
     "poisson_serve_create": ([_P(ServeOpts), _P(_V)], ctypes.c_int),
     "poisson_serve_submit": ([_V, _P(Request), _P(_U64)], ctypes.c_int),
@@ -430,6 +431,13 @@ def j3d_autotune_single(dtype, nx, ny, nz, stream=None):
     t = Tune()
     _check(_lib.j3d_autotune_single(dtype, nx, ny, nz, ctypes.byref(t), _stream_handle(stream)),
            "j3d_autotune_single")
+    return t.as_tuple()
+
+
+def j3d_tune_query_single(kind, nx, ny, nz):
+    """The tile shape single-grid calls of this kind and shape use now."""
+    t = Tune()
+    _check(_lib.j3d_tune_query_single(kind, nx, ny, nz, ctypes.byref(t)), "j3d_tune_query_single")
     return t.as_tuple()
 
 
