@@ -27,10 +27,14 @@ Other workloads (their own JSON line; not the default):
                      200 sweeps with residuals every 10, one graph launch;
   --workload serve   a Poisson request stream (200/s, n log-uniform in
                      [32, 384], tolerance 1e-6 or 1e-8, 5000-sweep cap) through
-                     the continuous-batching server: solves/s, p50/p99 latency.
+                     the continuous-batching server: solves/s, p50/p99 latency;
+  --workload reduce  the sum and dot_product intrinsics at the paper's sizes
+                     (32768 x 32768 and 2^27 FP64 elements): GB/s streamed;
+  --workload small   64^3, 100 sweeps, residual after every sweep, one solve
+                     call (launch-latency bound): microseconds per sweep.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--workload plain|mixed|batch|serve]
+                       [--workload plain|mixed|batch|serve|reduce|small]
 """
 from __future__ import annotations
 
@@ -122,11 +126,14 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first and use the fastest (default: the library's default "
                          "shape, the one the committed counter profiles were taken with)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve", "reduce", "small"])
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--active-points", type=float, default=2e8,
                     help="serve: admission target for active interior points (0: no limit)")
     ap.add_argument("--rtol", type=float, default=1e-8, help="mixed: target relative residual")
+    ap.add_argument("--chunk-sweeps", type=int, default=100000,
+                    help="mixed: sweeps per solve call between progress lines (whole 50-sweep cycles)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: request arrival rate per second")
     ap.add_argument("--tile", default=None,
                     help="pin the tile shape as rows,planes,variant,persistent,order[,cols] instead of autotuning")
     ap.add_argument("--probe", action="store_true",
@@ -145,7 +152,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload != "plain":
-        out = {"mixed": run_mixed, "batch": run_batch, "serve": run_serve}[args.workload](args)
+        out = {"mixed": run_mixed, "batch": run_batch, "serve": run_serve, "reduce": run_reduce,
+               "small": run_small}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     n, S, E = args.n, args.sweeps, args.resid_every
@@ -289,23 +297,35 @@ def run_mixed(args):
     f = synth.manufactured_f(n, n, n, h)
     df = j3d.FArray.from_numpy(f)
     u = j3d.FArray.empty(n, n, n)
-    for dt in (j3d.F64, j3d.F32):
-        j3d.j3d_autotune_single(dt, n, n, n)
+    if args.autotune:
+        for kind in (j3d.F64, j3d.F32, j3d.KIND_F64X2, j3d.KIND_F32X2):
+            j3d.j3d_autotune_single(kind, n, n, n)
     res = {}
+    chunk = max(50, args.chunk_sweeps // 50 * 50)
     for mode, name in ((j3d.MODE_MIXED, "mixed"), (j3d.MODE_FP64, "fp64")):
         j3d.j3d_fill_uniform(u, 2, synth.STREAM_U0, 0.0, 1.0)
         torch.cuda.synchronize()
         print("[bench] %s solve to %g on %d^3" % (name, args.rtol, n), file=sys.stderr, flush=True)
+        # The solve runs in chunks of whole 50-sweep cycles, each resuming from
+        # the iterate the previous one returned (the same sequence of
+        # operations as one call), so progress can be reported between chunks.
         t0 = time.perf_counter()
-        r = j3d.poisson_solve(u, df, h, mode=mode, rtol=args.rtol, max_sweeps=10 ** 8,
-                              check_every=50, inner_sweeps=50, history_cap=1 << 21)
+        sweeps = 0
+        while True:
+            r = j3d.poisson_solve(u, df, h, mode=mode, rtol=args.rtol, max_sweeps=chunk,
+                                  check_every=50, inner_sweeps=50, history_cap=0)
+            sweeps += r.sweeps
+            if r.converged or r.sweeps < chunk or sweeps >= 10 ** 8:
+                break
+            print("[bench] %s: %d sweeps, relative residual %.3e, %.1f s" % (
+                name, sweeps, r.resid / r.norm_f, time.perf_counter() - t0), file=sys.stderr, flush=True)
         el = time.perf_counter() - t0
         # the oracle's one-pass FP64 residual of the returned solution
         uo = u.to_numpy()
         rr = oracle.residual_l2(uo, f, h)
-        res[name] = {"seconds": round(el, 3), "sweeps": r.sweeps, "converged": r.converged,
+        res[name] = {"seconds": round(el, 3), "sweeps": sweeps, "converged": r.converged,
                      "rel_resid_gpu": r.resid / r.norm_f, "rel_resid_oracle": rr / oracle.norm2(f),
-                     "glups": round(float(n) ** 3 * r.sweeps / el / 1e9, 2)}
+                     "glups": round(float(n) ** 3 * sweeps / el / 1e9, 2)}
         print("[bench] %s: %s" % (name, res[name]), file=sys.stderr, flush=True)
         del uo
     speedup = res["fp64"]["seconds"] / res["mixed"]["seconds"]
@@ -358,6 +378,76 @@ def run_batch(args):
                         "hbm_frac_of_step": round(glups * 24.0 / HBM_PEAK_GBS, 4)})
 
 
+def run_small(args):
+    """64^3 FP64, 100 sweeps with the residual after every sweep, as one
+    poisson_solve call (the launch-latency-bound configuration)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    n = 64
+    u0, f, h = synth.small_plain(n, seed=1)
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    hist = None
+    for _ in range(max(1, args.warmup)):
+        du.copy_from(u0)
+        j3d.poisson_solve(du, df, h, rtol=0.0, max_sweeps=100, check_every=1)
+    times = []
+    for _ in range(args.steps):
+        du.copy_from(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = j3d.poisson_solve(du, df, h, rtol=0.0, max_sweeps=100, check_every=1)
+        times.append(time.perf_counter() - t0)
+        hist = r.history
+    med = float(np.median(times))
+    assert len(hist) == 101 and hist[-1] < hist[0]
+    return _base(args, "GLUP/s (64^3, 100 sweeps, residual after every sweep)", round(n ** 3 * 100 / med / 1e9, 3),
+                 "GLUP/s", round(med * 1e3, 3), "f64", "small-64cubed-100sweeps-resid1",
+                 extra={"us_per_sweep": round(med / 100 * 1e6, 2), "best_ms": round(min(times) * 1e3, 3)})
+
+
+def run_reduce(args):
+    """The paper's reduction intrinsics at its sizes: sum over a 32768 x 32768
+    FP64 array and dot_product of two FP64 vectors of 2^27 (134 million)
+    elements; bytes streamed per second against the HBM peak."""
+    import torch
+
+    from paper_2409_18824_amd import j3d
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    out = {}
+    for name, n in (("sum", 32768 * 32768), ("dot", 1 << 27)):
+        x = torch.rand(n, dtype=torch.float64, device="cuda", generator=g)
+        y = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) if name == "dot" else None
+        res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        call = (lambda: j3d.j3d_sum(x, out=res)) if name == "sum" else (lambda: j3d.j3d_dot(x, y, out=res))
+        for _ in range(max(1, args.warmup)):
+            call()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a, b in ev:
+            a.record()
+            call()
+            b.record()
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in ev)
+        nbytes = 8 * n * (2 if name == "dot" else 1)
+        med = ms[len(ms) // 2]
+        out[name] = {"elements": n, "bytes": nbytes, "median_ms": round(med, 4), "best_ms": round(ms[0], 4),
+                     "gbps": round(nbytes / (med * 1e-3) / 1e9, 1),
+                     "frac_of_hbm_peak": round(nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        print("[bench] %s: %s" % (name, out[name]), file=sys.stderr, flush=True)
+        del x, y
+    tot_bytes = sum(v["bytes"] for v in out.values())
+    tot_ms = sum(v["median_ms"] for v in out.values())
+    return _base(args, "GB/s streamed by the sum / dot_product intrinsics", round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
+                 "GB/s", tot_ms, "f64", "reduce-sum32768sq-dot2p27", extra={"results": out})
+
+
 def run_serve(args):
     """Poisson arrivals at 200/s through the continuous-batching server."""
     import numpy as np
@@ -366,7 +456,7 @@ def run_serve(args):
     import synth
     from paper_2409_18824_amd import j3d
 
-    reqs = synth.serve_requests(args.requests, rate=200.0, seed=5)
+    reqs = synth.serve_requests(args.requests, rate=args.rate, seed=5)
     # warm the kernels with one small solve
     with j3d.Server(hbm_budget_bytes=8 << 30, max_slots=4, cycle_sweeps=50) as s:
         s.submit(32, 1 / 33, 1e-6, 100, seed=1)
@@ -407,8 +497,8 @@ def run_serve(args):
     lups = float(np.sum(ns.astype(np.float64) ** 3 * sweeps))
     out = _base(args, "served solves/s (mixed precision, continuous batching)", round(len(results) / (t1 - t0), 3),
                 "solves/s", round((t1 - t0) * 1e3, 1), "f32+f64",
-                "serve-poisson-200rps-n32to384-tol1e-6or1e-8-cap5000",
-                extra={"requests": len(results), "offered_rate_per_s": 200.0, "hbm_budget_bytes": budget,
+                "serve-poisson-%grps-n32to384-tol1e-6or1e-8-cap5000" % args.rate,
+                extra={"requests": len(results), "offered_rate_per_s": args.rate, "hbm_budget_bytes": budget,
                        "max_active_points": int(args.active_points)})
     out["latency_s"] = {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                         "p50_tol1e-8": round(float(np.percentile(lat[tol8], 50)), 3) if tol8.any() else None,
