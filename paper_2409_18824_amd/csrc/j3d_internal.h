@@ -102,6 +102,13 @@ hipError_t launch_reduce_one(const double* partials, int part0, int n, double* o
                              const double* test_normf, double rtol, long long s, int* done,
                              long long* conv_at, int* nonfinite, hipStream_t st);
 
+// The solve drivers' check: sum of partials[0 .. n) -> sqrt -> hist[*qnext];
+// convergence test against rtol * (*normf) as launch_reduce_one with
+// s = *qnext; then *qnext += 1.  Nothing happens once *done != 0.
+hipError_t launch_reduce_count(const double* partials, int n, double* hist, const double* normf,
+                               double rtol, int* done, long long* conv_at, int* nonfinite,
+                               long long* qnext, hipStream_t st);
+
 // Batched reduce: one workgroup per table entry; entry g (id = table[g].id)
 // sums its own tile slots and writes sqrt to out[id*ostride + q].  Grids
 // flagged done[id] are skipped.  With normf (indexed by id) the convergence

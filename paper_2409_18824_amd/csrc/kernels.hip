@@ -73,6 +73,30 @@ __global__ void __launch_bounds__(RED_THREADS)
   }
 }
 
+// As k_reduce_one for the solve drivers' checks, with the check index kept
+// on the device: check *qnext goes to hist[*qnext], then *qnext advances.
+// Every check of a replayed graph chunk is therefore the same kernel with the
+// same arguments.
+__global__ void __launch_bounds__(RED_THREADS)
+    k_reduce_count(const double* __restrict__ partials, int n, double* hist, const double* normf,
+                   double rtol, int* done, long long* conv_at, int* nonfinite, long long* qnext) {
+  if (*done != 0) return;
+  __shared__ double sred[RED_WAVES];
+  const double tot = reduce_slots(partials, n, sred);
+  if (threadIdx.x == 0) {
+    const long long q = *qnext;
+    const double r = sqrt(tot);
+    hist[q] = r;
+    const bool bad = !isfinite(r);
+    if (bad || r <= rtol * (*normf)) {
+      *done = 1;
+      *conv_at = q;
+      if (bad) *nonfinite = 1;
+    }
+    *qnext = q + 1;
+  }
+}
+
 __global__ void __launch_bounds__(RED_THREADS)
     k_reduce_batch(const double* __restrict__ partials, const GridArgs* __restrict__ table,
                    double* out, int ostride, int q, const double* normf, const double* rtol,
@@ -314,6 +338,14 @@ hipError_t launch_reduce_one(const double* partials, int part0, int n, double* o
                              long long* conv_at, int* nonfinite, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_one, dim3(1), dim3(RED_THREADS), 0, st, partials, part0, n, out,
                      test_normf, rtol, s, done, conv_at, nonfinite);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_count(const double* partials, int n, double* hist, const double* normf,
+                               double rtol, int* done, long long* conv_at, int* nonfinite,
+                               long long* qnext, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_count, dim3(1), dim3(RED_THREADS), 0, st, partials, n, hist, normf, rtol,
+                     done, conv_at, nonfinite, qnext);
   return hipGetLastError();
 }
 

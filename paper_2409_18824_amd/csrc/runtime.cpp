@@ -220,6 +220,13 @@ int ensure_work(Scratch* s, size_t bytes) {
   return J3D_OK;
 }
 
+void free_solve_graph(SolveGraph* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+}
+
 int release_all_scratch() {
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   int cur = 0;
@@ -235,6 +242,8 @@ int release_all_scratch() {
     if (s->ctl_host) (void)hipHostFree(s->ctl_host);
     for (auto& ev : s->ev)
       if (ev) (void)hipEventDestroy(ev);
+    for (SolveGraph& g : s->graphs) free_solve_graph(&g);
+    if (s->capture) (void)hipStreamDestroy(s->capture);
     delete s;
   }
   g_scratch.clear();

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "j3d_internal.h"
 
@@ -67,8 +68,18 @@ struct Control {
   double value2;
   double pad;
   long long conv_at;
+  long long qnext;  // index of the next check (advanced on the device)
   int done;
   int nonfinite;
+};
+
+// An instantiated graph of one chunk of a solve, keyed by everything its
+// kernels' arguments depend on.
+struct SolveGraph {
+  std::string key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long stamp = 0;
 };
 
 struct Scratch {
@@ -84,7 +95,17 @@ struct Scratch {
   // work arrays for poisson_solve
   void* work = nullptr;
   size_t work_bytes = 0;
+  // graphs of solve chunks replayed on `stream` (captured on `capture`)
+  hipStream_t capture = nullptr;
+  std::vector<SolveGraph> graphs;
+  unsigned long long graph_stamp = 0;
 };
+
+// The cached graph for `key`, or a new one captured by enqueue(capture
+// stream) and instantiated; at most a few graphs are kept per scratch.
+template <typename Enqueue>
+int solve_graph(Scratch* s, const std::string& key, Enqueue&& enqueue, hipGraphExec_t* out);
+void free_solve_graph(SolveGraph* g);
 
 int get_scratch(hipStream_t st, Scratch** out);
 int ensure_partials(Scratch* s, size_t n);
@@ -98,5 +119,45 @@ int dev_alloc(void** p, size_t bytes, const char* what);
 void release_batch_cache();
 
 double now_seconds();
+
+template <typename Enqueue>
+int solve_graph(Scratch* s, const std::string& key, Enqueue&& enqueue, hipGraphExec_t* out) {
+  for (SolveGraph& g : s->graphs)
+    if (g.key == key) {
+      g.stamp = ++s->graph_stamp;
+      *out = g.exec;
+      return J3D_OK;
+    }
+  if (s->capture == nullptr) J3D_HIP(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking));
+  J3D_HIP(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue(s->capture);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s->capture, &graph);
+  if (rc != J3D_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != J3D_OK ? rc : hip_fail(e, "hipStreamEndCapture");
+  }
+  SolveGraph g;
+  g.key = key;
+  g.graph = graph;
+  const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(ei, "hipGraphInstantiate");
+  }
+  g.stamp = ++s->graph_stamp;
+  constexpr size_t kMaxGraphs = 4;
+  if (s->graphs.size() >= kMaxGraphs) {
+    size_t old = 0;
+    for (size_t i = 1; i < s->graphs.size(); ++i)
+      if (s->graphs[i].stamp < s->graphs[old].stamp) old = i;
+    J3D_HIP(hipStreamSynchronize(s->stream));
+    free_solve_graph(&s->graphs[old]);
+    s->graphs.erase(s->graphs.begin() + (long)old);
+  }
+  s->graphs.push_back(g);
+  *out = g.exec;
+  return J3D_OK;
+}
 
 }  // namespace j3d

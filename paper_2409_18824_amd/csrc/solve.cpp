@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -121,35 +123,79 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
 
   // which_at[q]: buffer holding the iterate whose residual is check q
   std::vector<unsigned char> which_at((size_t)nchecks, 0);
+  // The passes for sweeps [from, to) starting from buffer b: a two-sweep pass
+  // wherever pairs apply and two sweeps remain before `to` (chunk ends are
+  // multiples of 4 when pairs apply, so chunking never changes the
+  // schedule).  Checks take their index from the device counter, so a chunk
+  // is the same kernel sequence wherever it starts and can be replayed.
+  auto passes = [&](long long from, long long to, int b, hipStream_t q) -> int {
+    for (long long sw = from; sw < to;) {
+      const bool check = (sw % c) == 0;
+      const unsigned fl = F_WRITE | (check ? F_RES : 0u);
+      int nt;
+      if (pairs && sw + 2 <= to) {
+        J3D_HIP(launch_sweep2_one(J3D_F64, fl, cfg2, two[b], s->partials, done, q));
+        nt = nt2;
+        sw += 2;
+      } else {
+        J3D_HIP(launch_pass_one(J3D_F64, fl, cfg, one[b], s->partials, done, q));
+        nt = nt1;
+        sw += 1;
+      }
+      if (check)
+        J3D_HIP(launch_reduce_count(s->partials, nt, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
+                                    &s->ctl->nonfinite, &s->ctl->qnext, q));
+      b = 1 - b;
+    }
+    return J3D_OK;
+  };
+  // Host mirror of the schedule: the buffer of every check, and at the end.
+  auto track = [&](long long from, long long to, int b) -> int {
+    for (long long sw = from; sw < to;) {
+      if (sw % c == 0) which_at[(size_t)(sw / c)] = (unsigned char)b;
+      sw += (pairs && sw + 2 <= to) ? 2 : 1;
+      b = 1 - b;
+    }
+    return b;
+  };
   const long long points = (long long)u.nx() * u.ny() * u.nz();
-  const long long chunk = chunk_sweeps(points, pairs ? 12.0 : 24.0, c);
+  const long long unit = std::lcm(c, pairs ? 4LL : 2LL);  // an even number of passes
+  const long long chunk = chunk_sweeps(points, pairs ? 12.0 : 24.0, unit);
   long long sw = 0;
   int cur = 0;
   int slot = 0;
   bool seen = false;
+  // Whole chunks from one captured graph, replayed (each leaves the iterate
+  // in u again), when there are at least two of them.
+  const long long M = std::min(chunk, S / 2 / unit * unit);
+  if (M > 0) {
+    std::string key = "fp64";
+    auto add = [&key](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+    add(one, sizeof one);
+    add(two, sizeof two);
+    add(&cfg, sizeof cfg);
+    add(&cfg2, sizeof cfg2);
+    const long long meta[4] = {c, M, nt1, nt2};
+    add(meta, sizeof meta);
+    const void* ptrs[3] = {s->partials, s->hist, s->ctl};
+    add(ptrs, sizeof ptrs);
+    add(&o.rtol, sizeof o.rtol);
+    hipGraphExec_t exec = nullptr;
+    J3D_TRY(solve_graph(s, key, [&](hipStream_t q) { return passes(0, M, 0, q); }, &exec));
+    for (long long r = 0; r < S / M && !seen; ++r) {
+      J3D_HIP(hipGraphLaunch(exec, st));
+      (void)track(sw, sw + M, 0);
+      sw += M;
+      J3D_TRY(publish_done(s, slot, st));
+      if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
+      ++slot;
+    }
+  }
   while (sw < S && !seen) {
     const long long end = std::min(S, sw + chunk);
-    while (sw < end) {
-      const bool check = (sw % c) == 0;
-      const long long q = sw / c;  // check index served by this pass's fused residual
-      if (check) which_at[(size_t)q] = (unsigned char)cur;
-      const unsigned fl = F_WRITE | (check ? F_RES : 0u);
-      int nt;
-      if (pairs && sw + 2 <= S) {
-        J3D_HIP(launch_sweep2_one(J3D_F64, fl, cfg2, two[cur], s->partials, done, st));
-        nt = nt2;
-        sw += 2;
-      } else {
-        J3D_HIP(launch_pass_one(J3D_F64, fl, cfg, one[cur], s->partials, done, st));
-        nt = nt1;
-        sw += 1;
-      }
-      if (check) {
-        J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + q, &s->ctl->normf, o.rtol, q, done,
-                                  &s->ctl->conv_at, &s->ctl->nonfinite, st));
-      }
-      cur = 1 - cur;
-    }
+    J3D_TRY(passes(sw, end, cur, st));
+    cur = track(sw, end, cur);
+    sw = end;
     J3D_TRY(publish_done(s, slot, st));
     if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
     ++slot;
@@ -159,9 +205,9 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   {
     if (S % c == 0) which_at[(size_t)(S / c)] = (unsigned char)cur;
     J3D_HIP(launch_pass_one(J3D_F64, F_RES, cfg, resid[cur], s->partials, done, st));
-    if (S % c == 0)
-      J3D_HIP(launch_reduce_one(s->partials, 0, nt1, s->hist + S / c, &s->ctl->normf, o.rtol, S / c,
-                                done, &s->ctl->conv_at, &s->ctl->nonfinite, st));
+    if (S % c == 0)  // check S / c: the counter holds exactly that index here
+      J3D_HIP(launch_reduce_count(s->partials, nt1, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
+                                  &s->ctl->nonfinite, &s->ctl->qnext, st));
     else
       J3D_HIP(launch_reduce_one(s->partials, 0, nt1, &s->ctl->value, nullptr, 0.0, 0, done, nullptr,
                                 nullptr, st));
@@ -255,43 +301,84 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   J3D_TRY(norm_f(f, cd, s, st));
   int* done = &s->ctl->done;
 
-  const long long points = (long long)u.nx() * u.ny() * u.nz();
-  const long long chunk = chunk_sweeps(points, 6.6, m_in);
-  long long sw = 0, q = 0, since = 0;
-  int slot = 0;
-  bool seen = false;
-  for (;;) {
-    J3D_HIP(launch_pass_one(J3D_F64, F_RES | F_R32, cd, defect, s->partials, done, st));
-    J3D_HIP(launch_reduce_one(s->partials, 0, nt, s->hist + q, &s->ctl->normf, o.rtol, q, done,
-                              &s->ctl->conv_at, &s->ctl->nonfinite, st));
-    if (sw >= S) break;
-    const long long m = std::min(m_in, S - sw);
+  // One unit: the defect step with its check (index from the device
+  // counter), then a correction cycle of m sweeps (none for the final
+  // defect step).  Units with the same m are the same kernel sequence.
+  auto unit = [&](long long m, hipStream_t q) -> int {
+    J3D_HIP(launch_pass_one(J3D_F64, F_RES | F_R32, cd, defect, s->partials, done, q));
+    J3D_HIP(launch_reduce_count(s->partials, nt, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
+                                &s->ctl->nonfinite, &s->ctl->qnext, q));
+    if (m == 0) return J3D_OK;
     if (m == 1) {
-      J3D_HIP(launch_pass_one(J3D_F32, F_LAST | F_FIRST, cs, first_last1, nullptr, done, st));
+      J3D_HIP(launch_pass_one(J3D_F32, F_LAST | F_FIRST, cs, first_last1, nullptr, done, q));
     } else if (m == 2) {
-      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST | F_FIRST, cs2, first_last2, nullptr, done, st));
+      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST | F_FIRST, cs2, first_last2, nullptr, done, q));
     } else {
       if (m & 1)
-        J3D_HIP(launch_pass_one(J3D_F32, F_WRITE | F_FIRST, cs, first1, nullptr, done, st));
+        J3D_HIP(launch_pass_one(J3D_F32, F_WRITE | F_FIRST, cs, first1, nullptr, done, q));
       else
-        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE | F_FIRST, cs2, first2, nullptr, done, st));
+        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE | F_FIRST, cs2, first2, nullptr, done, q));
       const long long pairs = (m - 2 + (m & 1)) / 2;  // passes after the first, >= 1
       int cur = 0;                                    // e0 holds the iterate
       for (long long p = 1; p < pairs; ++p) {
-        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE, cs2, mid2[cur], nullptr, done, st));
+        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE, cs2, mid2[cur], nullptr, done, q));
         cur = 1 - cur;
       }
-      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST, cs2, last2[cur], nullptr, done, st));
+      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST, cs2, last2[cur], nullptr, done, q));
     }
+    return J3D_OK;
+  };
+
+  const long long points = (long long)u.nx() * u.ny() * u.nz();
+  const long long chunk = chunk_sweeps(points, 6.6, m_in);
+  const long long full = S / m_in;                            // units with a whole cycle
+  const long long K = std::max<long long>(1, chunk / m_in);   // units per replayed graph
+  long long sw = 0, q = 0;
+  int slot = 0;
+  bool seen = false;
+  auto poll = [&]() -> int {
+    J3D_TRY(publish_done(s, slot, st));
+    if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
+    ++slot;
+    return J3D_OK;
+  };
+  if (full / K >= 2) {
+    std::string key = "mixed";
+    auto add = [&key](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+    const GridArgs args[10] = {defect, first1, first_last1, first2, first_last2, mid2[0], mid2[1],
+                               last2[0], last2[1], defect};
+    add(args, sizeof args);
+    add(&cd, sizeof cd);
+    add(&cs, sizeof cs);
+    add(&cs2, sizeof cs2);
+    const long long meta[3] = {m_in, K, nt};
+    add(meta, sizeof meta);
+    const void* ptrs[3] = {s->partials, s->hist, s->ctl};
+    add(ptrs, sizeof ptrs);
+    add(&o.rtol, sizeof o.rtol);
+    hipGraphExec_t exec = nullptr;
+    J3D_TRY(solve_graph(s, key, [&](hipStream_t qs) {
+      for (long long k = 0; k < K; ++k) J3D_TRY(unit(m_in, qs));
+      return J3D_OK;
+    }, &exec));
+    for (long long r = 0; r < full / K && !seen; ++r) {
+      J3D_HIP(hipGraphLaunch(exec, st));
+      sw += K * m_in;
+      q += K;
+      J3D_TRY(poll());
+    }
+  }
+  long long since = 0;
+  while (!seen) {
+    const long long m = std::min(m_in, S - sw);  // 0: the final defect step
+    J3D_TRY(unit(m, st));
+    if (m == 0) break;
     sw += m;
     ++q;
     since += m;
     if (since >= chunk) {
       since = 0;
-      J3D_TRY(publish_done(s, slot, st));
-      if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
-      ++slot;
-      if (seen) break;
+      J3D_TRY(poll());
     }
   }
   Control ctl;

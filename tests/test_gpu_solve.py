@@ -125,3 +125,39 @@ def test_warm_start_resume():
     j3d.poisson_solve(b, df, h, rtol=0.0, max_sweeps=30, check_every=10)
     j3d.poisson_solve(b, df, h, rtol=0.0, max_sweeps=30, check_every=10)
     assert np.array_equal(a.to_numpy(), b.to_numpy())
+
+
+@pytest.mark.parametrize("S,every", [(1234, 2), (1001, 1), (1200, 3), (999, 4)])
+def test_plain_graph_replay_and_tail(S, every):
+    """Long solves replay a captured chunk graph, then finish directly: same
+    iterate and history as the oracle, and again on a second call (cached
+    graph)."""
+    n = 24
+    say("graph replay", S, every)
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 8, 1, 0, 1)
+    f = synth.uniform_field(n, n, n, 8, 2, -1, 1)
+    uo, ro = oracle.solve_plain(u0, f, h, rtol=0.0, check_every=every, max_sweeps=S)
+    df = j3d.FArray.from_numpy(f)
+    for rep in range(2):
+        du = j3d.FArray.from_numpy(u0)
+        res = j3d.poisson_solve(du, df, h, rtol=0.0, max_sweeps=S, check_every=every)
+        assert res.sweeps == S and len(res.history) == len(ro.history)
+        assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
+        assert np.array_equal(du.to_numpy(), uo), "call %d" % rep
+
+
+def test_mixed_graph_replay_matches_oracle():
+    n = 24
+    say("mixed graph replay")
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 9, 1, 0, 1)
+    f = synth.uniform_field(n, n, n, 9, 2, -1, 1)
+    uo, ro = oracle.solve_mixed(u0, f, h, rtol=0.0, inner=50, max_sweeps=5030)
+    df = j3d.FArray.from_numpy(f)
+    for rep in range(2):
+        du = j3d.FArray.from_numpy(u0)
+        res = j3d.poisson_solve(du, df, h, mode=j3d.MODE_MIXED, rtol=0.0, max_sweeps=5030, inner_sweeps=50)
+        assert res.sweeps == ro.sweeps == 5030 and len(res.history) == len(ro.history)
+        assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
+        assert np.array_equal(du.to_numpy(), uo), "call %d" % rep
