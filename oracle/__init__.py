@@ -7,8 +7,8 @@ and the two share no code.
 Two independent references live here:
 
 * ``j3d_oracle.c`` (built with gcc into ``liboracle.so``): plain triple loops
-  for the sweep, the residual and its norm, and the plain and mixed-precision
-  solves.  The functions below wrap it for NumPy arrays of shape
+  for the sweep, the residual and its norm, the plain and mixed-precision
+  solves, and the paper's 2D Laplace jacobi benchmark.  The functions below wrap it for NumPy arrays of shape
   ``(nz+2, ny+2, ld)`` (Fortran ``u(0:ld-1, 0:ny+1, 0:nz+1)``, x unit stride).
 * ``dense`` : the operator assembled as a dense matrix from its definition,
   used to pin the loop oracle on tiny grids (brute force).
@@ -66,6 +66,10 @@ def lib():
         L.oracle_solve_plain.restype = None
         L.oracle_solve_mixed.argtypes = [P, P, P, P, P, I, I, I, I, I, I, I, D, D, I, I, P, I, P]
         L.oracle_solve_mixed.restype = None
+        L.oracle_jacobi2d.argtypes = [P, P, I, I, I, I]
+        L.oracle_jacobi2d.restype = None
+        L.oracle_laplace2d_resid_l2.argtypes = [P, I, I, I, D]
+        L.oracle_laplace2d_resid_l2.restype = D
         _lib = L
     return _lib
 
@@ -175,3 +179,26 @@ def solve_mixed(u0: np.ndarray, f: np.ndarray, h: float, rtol: float, inner: int
     lib().oracle_solve_mixed(_p(u), _p(f), _p(r32), _p(ea), _p(eb), ld - 2, ny, nz, sy, sz, sy4, sz4,
                              float(h), float(rtol), int(inner), int(max_sweeps), _p(hist), hist_cap, _p(out))
     return u, SolveResult(out, hist)
+
+
+def _geom2(a: np.ndarray):
+    if a.dtype != np.float64 or a.ndim != 2 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous 2-D float64 array")
+    ny2, ld = a.shape
+    return ld, ny2 - 2
+
+
+def jacobi2d(u0: np.ndarray, nsweeps: int, nx: int | None = None) -> np.ndarray:
+    """The paper's 2D Laplace Jacobi benchmark: nsweeps sweeps of u0 (shape
+    (ny+2, ld), x unit stride, halo = boundary values); returns the result."""
+    ld, ny = _geom2(u0)
+    nx = ld - 2 if nx is None else nx
+    a, b = u0.copy(), u0.copy()
+    lib().oracle_jacobi2d(_p(a), _p(b), nx, ny, ld, int(nsweeps))
+    return a if nsweeps % 2 == 0 else b
+
+
+def laplace2d_resid_l2(u: np.ndarray, h: float, nx: int | None = None) -> float:
+    ld, ny = _geom2(u)
+    nx = ld - 2 if nx is None else nx
+    return float(lib().oracle_laplace2d_resid_l2(_p(u), nx, ny, ld, float(h)))

@@ -335,3 +335,50 @@ void oracle_solve_mixed(double* u, const double* f, float* r32, float* e_a,
   out[0] = (double)s; out[1] = rn; out[2] = r0; out[3] = normf;
   out[4] = (double)converged; out[5] = (double)(nh < hist_cap ? nh : hist_cap);
 }
+
+/* ------------------------------------------------------------------ */
+/* The paper's 2D jacobi benchmark                                     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The jacobi benchmark the paper compares compilers on (Sec. "Flang
+ * performance comparison"): Jacobi iteration for Laplace's equation on a 2D
+ * grid u(0:nx+1, 0:ny+1) whose one-cell halo holds the boundary values,
+ *   u'(i,j) = (((u(i-1,j) + u(i+1,j)) + u(i,j-1)) + u(i,j+1)) / 4
+ * over the interior.  nsweeps sweeps alternate a -> b -> a ...; the result is
+ * in a when nsweeps is even, else in b (both must hold the same halo).
+ * Element (i,j) sits at a[i + sy*j].
+ */
+void oracle_jacobi2d(double* a, double* b, idx_t nx, idx_t ny, idx_t sy, idx_t nsweeps) {
+  for (idx_t s = 0; s < nsweeps; ++s) {
+    const double* u = (s % 2 == 0) ? a : b;
+    double* un = (s % 2 == 0) ? b : a;
+#pragma omp parallel for schedule(static)
+    for (idx_t j = 1; j <= ny; ++j)
+      for (idx_t i = 1; i <= nx; ++i) {
+        double t = u[(i - 1) + sy * j] + u[(i + 1) + sy * j];
+        t = t + u[i + sy * (j - 1)];
+        t = t + u[i + sy * (j + 1)];
+        un[i + sy * j] = t / 4.0;
+      }
+  }
+}
+
+/*
+ * ||r||_2 over the interior for Laplace's equation (right-hand side zero):
+ * r(i,j) = (S - 4 u(i,j)) / h^2 with S the four-neighbour sum in the order
+ * above; compensated sum of squares, row by row in order.
+ */
+double oracle_laplace2d_resid_l2(const double* u, idx_t nx, idx_t ny, idx_t sy, double h) {
+  const double h2 = h * h;
+  nsum acc = {0.0, 0.0};
+  for (idx_t j = 1; j <= ny; ++j)
+    for (idx_t i = 1; i <= nx; ++i) {
+      double t = u[(i - 1) + sy * j] + u[(i + 1) + sy * j];
+      t = t + u[i + sy * (j - 1)];
+      t = t + u[i + sy * (j + 1)];
+      const double r = (t - 4.0 * u[i + sy * j]) / h2;
+      nsum_add(&acc, r * r);
+    }
+  return sqrt(acc.s + acc.c);
+}
