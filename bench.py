@@ -31,10 +31,12 @@ Other workloads (their own JSON line; not the default):
   --workload reduce  the sum and dot_product intrinsics at the paper's sizes
                      (32768 x 32768 and 2^27 FP64 elements): GB/s streamed;
   --workload small   64^3, 100 sweeps, residual after every sweep, one solve
-                     call (launch-latency bound): microseconds per sweep.
+                     call (launch-latency bound): microseconds per sweep;
+  --workload jacobi2d  the paper's own jacobi benchmark: Laplace on 1024^2,
+                     100000 iterations (the paper's CPU times quoted as context).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--workload plain|mixed|batch|serve|reduce|small]
+                       [--workload plain|mixed|batch|serve|reduce|small|jacobi2d]
 """
 from __future__ import annotations
 
@@ -126,7 +128,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first and use the fastest (default: the library's default "
                          "shape, the one the committed counter profiles were taken with)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve", "reduce", "small"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve", "reduce", "small", "jacobi2d"])
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--active-points", type=float, default=2e8,
                     help="serve: admission target for active interior points (0: no limit)")
@@ -134,6 +136,7 @@ def main():
     ap.add_argument("--chunk-sweeps", type=int, default=100000,
                     help="mixed: sweeps per solve call between progress lines (whole 50-sweep cycles)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: request arrival rate per second")
+    ap.add_argument("--sweeps2d", type=int, default=100000, help="jacobi2d: iterations")
     ap.add_argument("--tile", default=None,
                     help="pin the tile shape as rows,planes,variant,persistent,order[,cols] instead of autotuning")
     ap.add_argument("--probe", action="store_true",
@@ -153,7 +156,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "plain":
         out = {"mixed": run_mixed, "batch": run_batch, "serve": run_serve, "reduce": run_reduce,
-               "small": run_small}[args.workload](args)
+               "small": run_small, "jacobi2d": run_jacobi2d}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     n, S, E = args.n, args.sweeps, args.resid_every
@@ -407,6 +410,36 @@ def run_small(args):
     return _base(args, "GLUP/s (64^3, 100 sweeps, residual after every sweep)", round(n ** 3 * 100 / med / 1e9, 3),
                  "GLUP/s", round(med * 1e3, 3), "f64", "small-64cubed-100sweeps-resid1",
                  extra={"us_per_sweep": round(med / 100 * 1e6, 2), "best_ms": round(min(times) * 1e3, 3)})
+
+
+def run_jacobi2d(args):
+    """The paper's jacobi benchmark: Laplace's equation on a 1024 x 1024 grid,
+    100000 Jacobi iterations (zero interior, top edge 1, other edges 0)."""
+    import numpy as np
+    import torch
+
+    from paper_2409_18824_amd import j3d
+
+    n, S = 1024, args.sweeps2d
+    u0 = np.zeros((n + 2, n + 2))
+    u0[-1, :] = 1.0
+    ua, ub = j3d.FArray.from_numpy2d(u0), j3d.FArray.from_numpy2d(u0)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi2d_sweeps(ua, ub, 1024, 1.0 / (n + 1))  # warm-up (captures the graph)
+    times = []
+    for _ in range(max(1, args.steps)):
+        ua.copy_from(u0[None]), ub.copy_from(u0[None])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        j3d.jacobi2d_sweeps(ua, ub, S, 1.0 / (n + 1), resid_out=out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print("[bench] jacobi2d %d sweeps: %.3f s" % (S, times[-1]), file=sys.stderr, flush=True)
+    med = float(np.median(times))
+    return _base(args, "GLUP/s (2D Laplace jacobi, 1024^2, %d iterations)" % S, round(n * n * S / med / 1e9, 2),
+                 "GLUP/s", round(med * 1e3, 2), "f64", "jacobi2d-1024sq-%dsweeps" % S,
+                 extra={"seconds": round(med, 4), "resid_l2": out.item(),
+                        "paper_cpu_seconds_context": {"this work's lowering, serial": 249.08, "Flang": 277.67}})
 
 
 def run_reduce(args):

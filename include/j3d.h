@@ -173,6 +173,24 @@ int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags
 int j3d_sum(const double* x, int64_t n, uint32_t flags, double* out, void* stream);
 int j3d_dot(const double* x, const double* y, int64_t n, uint32_t flags, double* out, void* stream);
 
+/*
+ * The paper's jacobi benchmark (Sec. "Flang performance comparison": Jacobi
+ * iteration for Laplace's equation on a 1024 x 1024 grid, 100000
+ * iterations): nsweeps sweeps of
+ *   u'(i,j) = (((u(i-1,j) + u(i+1,j)) + u(i,j-1)) + u(i,j+1)) / 4
+ * over the interior of rank-2 FP64 arrays (j3d_array with lbound[2] ==
+ * ubound[2]; the halo holds the boundary values, the same in both arrays).
+ * Sweeps alternate u_a -> u_b -> u_a ...: the result is in u_a when nsweeps
+ * is even, else in u_b; both arrays are written.  If resid_out is not NULL,
+ * ||r||_2 of the result, r = (S - 4 u) / h^2 over the interior (Laplace's
+ * equation, right-hand side zero), goes to *resid_out (device; host with
+ * J3D_HOST_RESULT).  Every sweep has exactly the arithmetic above (bit for
+ * bit the same as one sweep at a time).  Errors: J3D_EINVAL (bounds, rank,
+ * nsweeps < 0, h with resid_out), J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
+ */
+int jacobi2d_sweeps(const j3d_array* u_a, const j3d_array* u_b, int64_t nsweeps, double h,
+                    uint32_t flags, double* resid_out, void* stream);
+
 /* Solver modes */
 #define J3D_MODE_FP64 0  /* FP64 Jacobi sweeps */
 #define J3D_MODE_MIXED 1 /* FP32 correction sweeps with FP64 defect correction */

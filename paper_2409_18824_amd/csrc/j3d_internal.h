@@ -128,6 +128,17 @@ int sum_blocks(long long n);
 hipError_t launch_sum(const double* x, const double* y, long long n, double* partials, double* out,
                       hipStream_t st);
 
+// The 2D Laplace jacobi benchmark: `sweeps` (1, 2, 4 or 8) Jacobi sweeps of
+// the interior nx x ny of `in` (row stride si) written to `out` (row stride
+// so); in and out hold the same halo.  Skipped when *done != 0.
+hipError_t launch_jacobi2d(int sweeps, const double* in, double* out, int nx, int ny, int si, int so,
+                           const int* done, hipStream_t st);
+// Per-block sums of r^2, r = (S - 4 u) / h^2, over the interior of a 2D
+// array (laplace2d_res_blocks(ny) slots).
+int laplace2d_res_blocks(int ny);
+hipError_t launch_laplace2d_res(const double* u, int nx, int ny, int su, double h, double* partials,
+                                hipStream_t st);
+
 hipError_t launch_fill_uniform(double* a, int ex, int ey, int ez, long long sy, long long sz,
                                unsigned long long key, double lo, double hi, double halo,
                                hipStream_t st);

@@ -80,6 +80,21 @@ int check_field(const j3d_array* a, int dtype, Field* out, const char* name) {
   return J3D_OK;
 }
 
+int check_field2d(const j3d_array* a, int dtype, Field* out, const char* name) {
+  if (a == nullptr) return fail(J3D_EINVAL, "%s: null descriptor", name);
+  if (a->lbound[2] != a->ubound[2])
+    return fail(J3D_EINVAL, "%s: a rank-2 array has lbound[2] == ubound[2]", name);
+  j3d_array b = *a;  // validate axes 0 and 1 with a stand-in third axis of extent 3
+  b.ubound[2] = b.lbound[2] + 2;
+  b.stride[2] = b.stride[1] * (b.ubound[1] - b.lbound[1] + 1);
+  J3D_TRY(check_field(&b, dtype, out, name));
+  if (out) {
+    out->ez = 1;
+    out->sz = 0;
+  }
+  return J3D_OK;
+}
+
 bool fields_overlap(const Field& a, const Field& b) {
   const char* a0 = a.base;
   const char* a1 = a.base + a.span_bytes();

@@ -128,6 +128,7 @@ _SIGS = {
     "j3d_fill_const": ([_P(J3DArray), _D, _V], ctypes.c_int),
     "j3d_bandwidth_probe": ([_V, _V, _I64, _I32, _P(_D), _V], ctypes.c_int),
     "j3d_sum": ([_V, _I64, _U32, _V, _V], ctypes.c_int),
+    "jacobi2d_sweeps": ([_P(J3DArray), _P(J3DArray), _I64, _D, _U32, _V, _V], ctypes.c_int),
     "j3d_dot": ([_V, _V, _I64, _U32, _V, _V], ctypes.c_int),
     "j3d_release_cache": ([], ctypes.c_int),
 }
@@ -242,6 +243,30 @@ class FArray:
         return self
 
     @classmethod
+    def empty2d(cls, nx, ny, dtype=F64, device="cuda", lbound=(0, 0), align_bytes=128, ld_extra=0):
+        """A rank-2 array u(0:nx+1, 0:ny+1) (descriptor axis 2 of extent 1)."""
+        es = 8 if dtype == F64 else 4
+        al = max(1, align_bytes // es)
+        ex, ey = nx + 2, ny + 2
+        ld = (ex + al - 1) // al * al + ld_extra
+        offset = al - 1
+        st = torch.zeros(offset + ld * ey + al, dtype=_TORCH_DT[dtype], device=device)
+        lb = (int(lbound[0]), int(lbound[1]), 0)
+        ub = (lb[0] + ex - 1, lb[1] + ey - 1, 0)
+        return cls(st, offset, lb, ub, (1, ld, ld * ey), dtype)
+
+    @classmethod
+    def from_numpy2d(cls, a: np.ndarray, dtype=None, device="cuda", **kw):
+        ey, ex = a.shape
+        if dtype is None:
+            dtype = F32 if a.dtype == np.float32 else F64
+        out = cls.empty2d(ex - 2, ey - 2, dtype=dtype, device=device, **kw)
+        return out.copy_from(a[None, :, :])
+
+    def to_numpy2d(self) -> np.ndarray:
+        return self.to_numpy()[0]
+
+    @classmethod
     def from_numpy(cls, a: np.ndarray, dtype=None, device="cuda", **kw):
         ez, ey, ex = a.shape
         if dtype is None:
@@ -320,6 +345,25 @@ def _vec(x, what):
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
         raise TypeError("%s: a contiguous float64 CUDA tensor is required" % what)
     return ctypes.c_void_p(x.data_ptr()), x.numel()
+
+
+def jacobi2d_sweeps(u_a: FArray, u_b: FArray, nsweeps: int, h: float = 1.0, resid_out=None, host_result=False,
+                    stream=None):
+    """The paper's 2D Laplace jacobi benchmark: nsweeps sweeps alternating
+    u_a -> u_b -> ...; the result is in u_a when nsweeps is even.  With
+    ``host_result`` returns ||r||_2 of the result; with ``resid_out`` (one
+    device float64) stores it asynchronously."""
+    a, b = u_a.desc(), u_b.desc()
+    st = _stream_handle(stream)
+    if host_result:
+        v = ctypes.c_double()
+        _check(_lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(b), int(nsweeps), float(h), HOST_RESULT,
+                                    ctypes.cast(ctypes.byref(v), ctypes.c_void_p), st), "jacobi2d_sweeps")
+        return v.value
+    ptr = None if resid_out is None else ctypes.c_void_p(resid_out.data_ptr())
+    _check(_lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(b), int(nsweeps), float(h), 0, ptr, st),
+           "jacobi2d_sweeps")
+    return None
 
 
 def j3d_sum(x, out=None, stream=None):

@@ -225,3 +225,24 @@ def test_tune_query_default_set_and_bad_kind():
     assert ei.value.code == j3d.EDTYPE
     with pytest.raises(j3d.J3DError):
         j3d.j3d_tune_query_single(j3d.F64, 0, 5, 3)
+
+
+def test_jacobi2d_validation_before_device_work():
+    lib = j3d._lib
+    a = fake_desc(10, 8, 1)
+    a.lbound[2] = a.ubound[2] = 0  # rank 2
+    b = fake_desc(10, 8, 1, base=0x900000)
+    b.lbound[2] = b.ubound[2] = 0
+    assert lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(b), -1, 0.1, 0, None, None) == j3d.EINVAL
+    c = fake_desc(10, 8, 3, base=0x900000)  # rank 3
+    assert lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(c), 4, 0.1, 0, None, None) == j3d.EINVAL
+    assert "rank-2" in j3d.last_error()
+    d = fake_desc(11, 8, 1, base=0x900000)
+    d.lbound[2] = d.ubound[2] = 0
+    assert lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(d), 4, 0.1, 0, None, None) == j3d.EINVAL
+    e = fake_desc(10, 8, 1, base=0x10000 + 64)  # overlaps a
+    e.lbound[2] = e.ubound[2] = 0
+    assert lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(e), 4, 0.1, 0, None, None) == j3d.EALIAS
+    out = ctypes.c_double()
+    assert lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(b), 4, -1.0, j3d.HOST_RESULT,
+                               ctypes.cast(ctypes.byref(out), ctypes.c_void_p), None) == j3d.EINVAL

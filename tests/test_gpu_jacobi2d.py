@@ -1,0 +1,73 @@
+"""GPU parity of the paper's 2D Laplace jacobi benchmark against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import RESID_RTOL, needs_gpu, rel, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+from paper_2409_18824_amd import j3d  # noqa: E402
+
+
+def grid(nx, ny, seed, hot_top=False):
+    """Interior U[0,1) (seed, stream 1), halo U[-1,1) (stream 9); or the
+    benchmark's set-up: zero interior, top edge 1, other edges 0."""
+    if hot_top:
+        u = np.zeros((ny + 2, nx + 2))
+        u[-1, :] = 1.0
+        return u
+    u = synth.uniform(seed, 1, np.arange((ny + 2) * (nx + 2), dtype=np.uint64), 0, 1).reshape(ny + 2, nx + 2)
+    halo = synth.uniform(seed, 9, np.arange(u.size, dtype=np.uint64), -1, 1).reshape(u.shape)
+    mask = np.ones(u.shape, dtype=bool)
+    mask[1:-1, 1:-1] = False
+    u[mask] = halo[mask]
+    return u
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (37, 23), (48, 16), (49, 17), (130, 70), (200, 33)])
+@pytest.mark.parametrize("nsweeps", [0, 1, 2, 3, 7, 8, 9, 16, 21, 40])
+def test_jacobi2d_matches_oracle(shape, nsweeps):
+    nx, ny = shape
+    say("jacobi2d", shape, nsweeps)
+    u0 = grid(nx, ny, 3)
+    ua = j3d.FArray.from_numpy2d(u0)
+    ub = j3d.FArray.from_numpy2d(u0, ld_extra=5)
+    h = 1.0 / (max(nx, ny) + 1)
+    r = j3d.jacobi2d_sweeps(ua, ub, nsweeps, h, host_result=True)
+    want = oracle.jacobi2d(u0, nsweeps)
+    got = (ua if nsweeps % 2 == 0 else ub).to_numpy2d()[:, : nx + 2]
+    assert np.array_equal(got, want)
+    assert rel(r, oracle.laplace2d_resid_l2(want, h)) <= RESID_RTOL or r == oracle.laplace2d_resid_l2(want, h)
+
+
+def test_jacobi2d_full_size_with_graph_replay():
+    """1024^2 with the benchmark's boundary, 2000 sweeps (graph replays of
+    64 launches of 8 sweeps, then the rest), against the oracle."""
+    n, S = 1024, 2000 + 5
+    say("jacobi2d 1024^2", S)
+    u0 = grid(n, n, 0, hot_top=True)
+    ua, ub = j3d.FArray.from_numpy2d(u0), j3d.FArray.from_numpy2d(u0)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi2d_sweeps(ua, ub, S, 1.0 / (n + 1), resid_out=out)
+    torch.cuda.synchronize()
+    want = oracle.jacobi2d(u0, S)
+    assert np.array_equal(ub.to_numpy2d()[:, : n + 2], want)
+    assert rel(out.item(), oracle.laplace2d_resid_l2(want, 1.0 / (n + 1))) <= RESID_RTOL
+    # a second call replays the cached graph: continuing from the result equals one longer run
+    j3d.jacobi2d_sweeps(ub, ua, 1024, 1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(ub.to_numpy2d()[:, : n + 2], oracle.jacobi2d(want, 1024))
+
+
+def test_jacobi2d_lbounds_and_rank_checks():
+    u0 = grid(20, 9, 5)
+    ua = j3d.FArray.from_numpy2d(u0, lbound=(-4, 7))
+    ub = j3d.FArray.from_numpy2d(u0, lbound=(1, 1), ld_extra=3)
+    j3d.jacobi2d_sweeps(ua, ub, 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(ub.to_numpy2d()[:, :22], oracle.jacobi2d(u0, 5))
+    with pytest.raises(j3d.J3DError):
+        j3d.jacobi2d_sweeps(ua, j3d.FArray.empty(20, 9, 1), 5)  # a rank-3 array
