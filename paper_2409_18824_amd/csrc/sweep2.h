@@ -13,11 +13,11 @@
 // The x-neighbours in both stages come from the adjacent lanes of the same
 // wavefront by DPP wave shifts (no memory access: the lanes at the block's
 // x edges only feed columns that are not output), and the y-neighbours from
-// the thread's own rows, except at a wavefront's first and last row: stage
-// 1 loads those u0 rows through the cache, stage 2 exchanges the u1 edge rows
-// between wavefronts through LDS.  Only these edge rows take a barrier per
-// plane; they rotate over three LDS slots so one barrier per plane
-// suffices.  u1 never reaches HBM: per pair of sweeps the pass streams u0
+// the thread's own rows, except at a wavefront's first and last row: those
+// come from the neighbouring wavefront through LDS (u0 rows in stage 1, u1
+// rows in stage 2), and only the block's outer wavefronts load the u0 rows
+// beyond the block through the cache.  The edge rows rotate over plane slots
+// so one barrier per plane suffices.  u1 never reaches HBM: per pair of sweeps the pass streams u0
 // and f once and writes u2 once.  The outputs of a block are its inner 60 x
 // (BY*RY - 2) columns; the ring around them is recomputed by the
 // neighbouring blocks.
@@ -38,7 +38,8 @@ constexpr int sweep2_cols(int wx) { return wx == 1 ? WAVE - 4 : 0; }
 
 template <typename T, int BY, int WX, int VAR>
 struct Smem2 {
-  T edge[3][BY][2][WAVE];  // plane slot, wavefront, first/last row of u1
+  T edge[3][BY][2][WAVE];   // plane slot, wavefront, first/last row of u1
+  T u0edge[2][BY][2][WAVE]; // plane parity, wavefront, first/last row of u0
   double red[BY];
 };
 
@@ -107,6 +108,14 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
     u1m2[r] = T(0);
     fprev[r] = T(0);
   }
+  // The u0 rows just below and above a wavefront's rows are the neighbouring
+  // wavefronts' edge rows: they pass through LDS (two plane slots), and only
+  // the block's outer wavefronts load the rows beyond the block.
+  if (!ZERO) {
+    sm.u0edge[(k0 - 1) & 1][wy][0][lane] = u0c[0];
+    sm.u0edge[(k0 - 1) & 1][wy][1][lane] = u0c[RY - 1];
+    __syncthreads();
+  }
 
   for (int k = k0 - 1; k <= k1; ++k) {
     // Stage 1: u1 at plane k on every row of the block.
@@ -119,8 +128,14 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
       fk[r] = f[cf[r] + g.sf_z * kf];
       u0p[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * kp];
     }
-    const T nylo = ZERO ? T(0) : u0[cym + zk];
-    const T nyhi = ZERO ? T(0) : u0[cyp + zk];
+    T nylo = T(0), nyhi = T(0);
+    if (!ZERO) {
+      nylo = wy > 0 ? sm.u0edge[k & 1][wy - 1][1][lane] : u0[cym + zk];
+      nyhi = wy < BY - 1 ? sm.u0edge[k & 1][wy + 1][0][lane] : u0[cyp + zk];
+      // plane k+1 for the next step (read after this step's barrier)
+      sm.u0edge[(k + 1) & 1][wy][0][lane] = u0p[0];
+      sm.u0edge[(k + 1) & 1][wy][1][lane] = u0p[RY - 1];
+    }
     T u1[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
