@@ -377,8 +377,7 @@ def run_batch(args):
     return _base(args, "GLUP/s (batched uneven grids)", round(glups, 3), "GLUP/s", round(el / args.steps * 1e3, 3),
                  "f64", "batch-256-grids-32to256-200sweeps-resid10",
                  extra={"grids": len(grids), "points": pts, "tile": tune,
-                        "hbm_gbs_algorithmic": round(glups * 24.0, 1),
-                        "hbm_frac_of_step": round(glups * 24.0 / HBM_PEAK_GBS, 4)})
+                        "single_sweep_equivalent_gbs": round(glups * 24.0, 1)})
 
 
 def run_small(args):
