@@ -118,7 +118,8 @@ def test_sweep2_full_size_512():
     j3d.j3d_fill_uniform(du, 2, synth.STREAM_U0, 0.0, 1.0)
     dv = j3d.FArray.empty(n, n, n)
     df = j3d.FArray.from_numpy(f)
-    j3d.j3d_autotune_single(j3d.KIND_F64X2, n, n, n)
+    # the benchmark's launch configuration: the library's default shape
+    say("tile", j3d.j3d_tune_query_single(j3d.KIND_F64X2, n, n, n))
     r = torch.zeros(1, dtype=torch.float64, device="cuda")
     j3d.jacobi3d_sweep2(du, dv, df, h, resid_out=r)
     torch.cuda.synchronize()
