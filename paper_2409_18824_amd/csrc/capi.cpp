@@ -50,11 +50,14 @@ TileCfg default_cfg2(int dtype, int nx, int ny, int nz) {
   if (tune_cache_lookup_single(dtype == J3D_F32 ? J3D_KIND_F32X2 : J3D_KIND_F64X2, nx, ny, nz, &c) &&
       tile2_cfg_supported(dtype == J3D_F32 ? J3D_F32 : J3D_F64, c))
     return c;
-  c.rows = 4;  // 16 rows per block (4 per thread), nontemporal stores
-  c.planes = 16;
+  // measured at 512^3: FP64 16 rows per block, 16 planes, launch order;
+  // FP32 32 rows per block, 8 planes, XCD-blocked order (4 rows per thread,
+  // nontemporal stores in both)
+  c.rows = dtype == J3D_F32 ? 8 : 4;
+  c.planes = dtype == J3D_F32 ? 8 : 16;
   c.variant = 20;
   c.persistent = 0;
-  c.order = 1;
+  c.order = dtype == J3D_F32 ? 0 : 1;
   c.cols = 1;
   return c;
 }

@@ -215,7 +215,7 @@ def test_tune_query_default_set_and_bad_kind():
     # defaults (no cache entry for this odd shape)
     assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (1, 2, 20, 0, 1, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X2, 97, 5, 3) == (4, 16, 20, 0, 1, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F32X2, 97, 5, 3) == (4, 16, 20, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X2, 97, 5, 3) == (8, 8, 20, 0, 0, 1)
     # a pinned shape is what later calls of that kind and shape use
     j3d.j3d_tune_set_single(j3d.F32, 97, 5, 3, (2, 8, 6, 1, 2, 1))
     assert j3d.j3d_tune_query_single(j3d.F32, 97, 5, 3) == (2, 8, 6, 1, 2, 1)
