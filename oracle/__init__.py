@@ -8,7 +8,8 @@ Two independent references live here:
 
 * ``j3d_oracle.c`` (built with gcc into ``liboracle.so``): plain triple loops
   for the sweep, the residual and its norm, the plain and mixed-precision
-  solves, and the paper's 2D Laplace jacobi benchmark.  The functions below wrap it for NumPy arrays of shape
+  solves, the paper's 2D Laplace jacobi benchmark, and the two multi-field
+  stencils standing in for pw-advection and tra-adv.  The functions below wrap it for NumPy arrays of shape
   ``(nz+2, ny+2, ld)`` (Fortran ``u(0:ld-1, 0:ny+1, 0:nz+1)``, x unit stride).
 * ``dense`` : the operator assembled as a dense matrix from its definition,
   used to pin the loop oracle on tiny grids (brute force).
@@ -70,6 +71,10 @@ def lib():
         L.oracle_jacobi2d.restype = None
         L.oracle_laplace2d_resid_l2.argtypes = [P, I, I, I, D]
         L.oracle_laplace2d_resid_l2.restype = D
+        L.oracle_pw_advection.argtypes = [P, P, P, P, P, P, I, I, I, I, I, D, D, D]
+        L.oracle_pw_advection.restype = None
+        L.oracle_tracer_advection.argtypes = [P, P, P, P, P, P, I, I, I, I, I, I]
+        L.oracle_tracer_advection.restype = None
         _lib = L
     return _lib
 
@@ -202,3 +207,34 @@ def laplace2d_resid_l2(u: np.ndarray, h: float, nx: int | None = None) -> float:
     ld, ny = _geom2(u)
     nx = ld - 2 if nx is None else nx
     return float(lib().oracle_laplace2d_resid_l2(_p(u), nx, ny, ld, float(h)))
+
+
+def _same(*arrs):
+    a0 = arrs[0]
+    for a in arrs:
+        if a.shape != a0.shape:
+            raise ValueError("all fields must have the same shape")
+    return _geom(a0, np.float64)
+
+
+def pw_advection(u: np.ndarray, v: np.ndarray, w: np.ndarray, dx: float, dy: float, dz: float,
+                 nx: int | None = None):
+    """Momentum advection tendencies (su, sv, sw) of the staggered velocity
+    (u, v, w), centred flux form; interior written, halo zero."""
+    ld, ny, nz, sy, sz = _same(u, v, w)
+    nx = ld - 2 if nx is None else nx
+    su, sv, sw = np.zeros_like(u), np.zeros_like(u), np.zeros_like(u)
+    lib().oracle_pw_advection(_p(u), _p(v), _p(w), _p(su), _p(sv), _p(sw), nx, ny, nz, sy, sz,
+                              float(dx), float(dy), float(dz))
+    return su, sv, sw
+
+
+def tracer_advection(t0: np.ndarray, u: np.ndarray, v: np.ndarray, w: np.ndarray, r: np.ndarray,
+                     niter: int, nx: int | None = None) -> np.ndarray:
+    """niter donor-cell advection steps of the tracer t0 (its halo = boundary
+    values); returns the result."""
+    ld, ny, nz, sy, sz = _same(t0, u, v, w, r)
+    nx = ld - 2 if nx is None else nx
+    a, b = t0.copy(), t0.copy()
+    lib().oracle_tracer_advection(_p(a), _p(b), _p(u), _p(v), _p(w), _p(r), nx, ny, nz, sy, sz, int(niter))
+    return a if niter % 2 == 0 else b
