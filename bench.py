@@ -128,7 +128,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first and use the fastest (default: the library's default "
                          "shape, the one the committed counter profiles were taken with)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve", "reduce", "small", "jacobi2d"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "mixed", "batch", "serve", "reduce", "small", "jacobi2d",
+                             "pw-advection", "tra-adv"])
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--active-points", type=float, default=2e8,
                     help="serve: admission target for active interior points (0: no limit)")
@@ -156,7 +157,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "plain":
         out = {"mixed": run_mixed, "batch": run_batch, "serve": run_serve, "reduce": run_reduce,
-               "small": run_small, "jacobi2d": run_jacobi2d}[args.workload](args)
+               "small": run_small, "jacobi2d": run_jacobi2d, "pw-advection": run_pw_advection,
+               "tra-adv": run_tra_adv}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     n, S, E = args.n, args.sweeps, args.resid_every
@@ -478,6 +480,152 @@ def run_reduce(args):
     tot_ms = sum(v["median_ms"] for v in out.values())
     return _base(args, "GB/s streamed by the sum / dot_product intrinsics", round(tot_bytes / (tot_ms * 1e-3) / 1e9, 1),
                  "GB/s", tot_ms, "f64", "reduce-sum32768sq-dot2p27", extra={"results": out})
+
+
+ADVECT_SOURCES = ("advect.h", "kernels_advect.hip", "sweep.h")
+
+
+def advect_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ADVECT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_18824_amd", "csrc", name), "rb") as fp:
+            h.update(fp.read())
+    return h.hexdigest()[:16]
+
+
+def advect_tile() -> str:
+    return os.environ.get("J3D_ADVECT_TILE", "default")
+
+
+def advect_traffic(name: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current advection kernel source with the same tile."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "%s_counters.json" % name)) as fp:
+            d = json.load(fp)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sources_sha256_16") != advect_source_hash() or d.get("tile") != advect_tile():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def _event_times(call, steps):
+    import torch
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        call()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) * 1e-3 for a, b in ev]
+
+
+def _advect_roofline(alg_bytes, launch_s, traffic):
+    gbs = alg_bytes / launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def run_pw_advection(args):
+    """Momentum advection standing in for the paper's pw-advection: three
+    velocity fields in, three tendencies out, on 2048 x 1024 x 1024 FP64."""
+    import numpy as np
+
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    nx, ny, nz = synth.PW_SHAPE
+    recipe, d = synth.pw_recipe()
+    print("[bench] allocating 6 x %dx%dx%d FP64" % (nx, ny, nz), file=sys.stderr, flush=True)
+    ins = []
+    for fr in recipe:
+        a = j3d.FArray.empty(nx, ny, nz)
+        j3d.j3d_fill_uniform(a, fr.seed, fr.stream, fr.lo, fr.hi, fr.halo)
+        ins.append(a)
+    outs = [j3d.FArray.empty(nx, ny, nz) for _ in range(3)]
+    call = lambda: j3d.pw_advection(*ins, *outs, *d)
+    for _ in range(max(1, args.warmup)):
+        call()
+    times = _event_times(call, args.steps)
+    med = float(np.median(times))
+    pts = nx * ny * nz
+    alg = 48 * pts  # read u, v, w and write su, sv, sw once per point
+    out = _base(args, "grid points per second (momentum advection, 3 fields in / 3 out, %dx%dx%d)" % (nx, ny, nz),
+                round(pts / med / 1e9, 2), "Gpoints/s", round(med * 1e3, 3), "f64",
+                "pw-advection-%dx%dx%d" % (nx, ny, nz),
+                extra={"tile": advect_tile(), "algorithmic_bytes_per_launch": alg, "launches_per_step": 1})
+    out["roofline"] = _advect_roofline(alg, med, advect_traffic("pw_advection"))
+    del ins, outs
+    if not args.no_cpu_baseline:
+        import oracle
+
+        kz = 6
+        fields = [synth.uniform_field(nx, ny, kz, fr.seed, fr.stream, fr.lo, fr.hi, fr.halo) for fr in recipe]
+        t0, calls = time.perf_counter(), 0
+        while True:
+            oracle.pw_advection(*fields, *d)
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= 10.0 or calls >= 200:
+                break
+        out["cpu_baseline"] = {"value": round(calls * nx * ny * kz / el / 1e9, 4), "unit": "Gpoints/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": "%d calls on the first %d z-planes (%dx%dx%d), %.1f s" % (
+                                   calls, kz, nx, ny, kz, el)}
+    return out
+
+
+def run_tra_adv(args):
+    """Tracer advection standing in for the paper's tra-adv: six fields on
+    1024 x 512 x 512 FP64, 20 donor-cell steps per call."""
+    import numpy as np
+
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    nx, ny, nz = synth.TRA_SHAPE
+    S = synth.TRA_ITERS
+    rt, rvel, rr = synth.tracer_recipe()
+    recipe = [rt, rt] + rvel + [rr]
+    arrs = []
+    for fr in recipe:
+        a = j3d.FArray.empty(nx, ny, nz)
+        j3d.j3d_fill_uniform(a, fr.seed, fr.stream, fr.lo, fr.hi, fr.halo)
+        arrs.append(a)
+    call = lambda: j3d.tracer_advection(*arrs, S)
+    for _ in range(max(1, args.warmup)):
+        call()
+    times = _event_times(call, args.steps)
+    med = float(np.median(times))
+    pts = nx * ny * nz
+    alg = 48 * pts  # per step: read t, u, v, w, r and write t once per point
+    out = _base(args, "point updates per second (tracer advection, 6 fields, %dx%dx%d, %d steps)" % (nx, ny, nz, S),
+                round(pts * S / med / 1e9, 2), "GLUP/s", round(med * 1e3, 3), "f64",
+                "tra-adv-%dx%dx%d-%dsteps" % (nx, ny, nz, S),
+                extra={"tile": advect_tile(), "algorithmic_bytes_per_launch": alg, "launches_per_step": S})
+    out["roofline"] = _advect_roofline(alg, med / S, advect_traffic("tracer_advection"))
+    del arrs
+    if not args.no_cpu_baseline:
+        import oracle
+
+        kz = 8
+        fields = [synth.uniform_field(nx, ny, kz, fr.seed, fr.stream, fr.lo, fr.hi, fr.halo)
+                  for fr in [rt] + rvel + [rr]]
+        t0, calls = time.perf_counter(), 0
+        while True:
+            oracle.tracer_advection(*fields, S)
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= 10.0 or calls >= 100:
+                break
+        out["cpu_baseline"] = {"value": round(calls * nx * ny * kz * S / el / 1e9, 4), "unit": "GLUP/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": "%d calls of %d steps on the first %d z-planes (%dx%dx%d), %.1f s" % (
+                                   calls, S, kz, nx, ny, kz, el)}
+    return out
 
 
 def run_serve(args):

@@ -87,7 +87,9 @@ extern "C" {
  * Bounds are inclusive and include the one-cell halo.  Strides are in
  * elements: stride[0] must be 1, stride[1] >= extent[0], stride[2] >=
  * stride[1]*extent[1], where extent[d] = ubound[d]-lbound[d]+1 >= 3.  The
- * largest element offset must be below 2^31.
+ * largest element offset must be below 2^31, except for the advection
+ * entry points and the fills, which only need the offsets within one
+ * z-plane below 2^31 (and the whole array below 2^46 elements).
  */
 typedef struct j3d_array {
   void* base;
@@ -190,6 +192,55 @@ int j3d_dot(const double* x, const double* y, int64_t n, uint32_t flags, double*
  */
 int jacobi2d_sweeps(const j3d_array* u_a, const j3d_array* u_b, int64_t nsweeps, double h,
                     uint32_t flags, double* resid_out, void* stream);
+
+/*
+ * Multi-field stencils.  The paper compares compilers on two stencil codes
+ * it does not list, pw-advection (three fields on a 2048 x 1024 x 1024
+ * grid) and tra-adv (six fields on 1024 x 512 x 512, 20 iterations), Sec.
+ * "Flang performance comparison"; these two calls are documented stencils
+ * with those field counts and shapes.
+ *
+ * pw_advection: momentum advection in the centred flux form of Piacsek and
+ * Williams (1970) on a staggered grid.  u(i,j,k) is the x-velocity on the
+ * east face of cell (i,j,k), v on its north face, w on its top face.  The
+ * tendency of each component at its own point is minus the divergence of
+ * its momentum flux; the flux through a face is the advecting velocity
+ * averaged onto the face times the advected component averaged onto it,
+ * each the mean of two neighbours.  With c = 0.25 / spacing and, per
+ * direction, am, bm (ap, bp) the two-point sums of advecting velocity and
+ * advected component at the lower (upper) face,
+ *   D = (am * bm - ap * bp) * c,   tendency = (Dx + Dy) + Dz,
+ * which is exact for the arithmetic written (no fused multiply-add).
+ * u, v, w: FP64 inputs (0:nx+1, 0:ny+1, 0:nz+1) with equal bounds and
+ * strides, halo = boundary values.  su, sv, sw: FP64 outputs with the same
+ * bounds (their own common strides); only the interior is written.
+ * dx, dy, dz > 0 and finite.  Outputs may not overlap each other or the
+ * inputs.  Asynchronous on `stream`.  Errors: J3D_EINVAL (bounds, strides,
+ * spacing), J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
+ */
+int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_array* w,
+                 const j3d_array* su, const j3d_array* sv, const j3d_array* sw,
+                 double dx, double dy, double dz, void* stream);
+
+/*
+ * tracer_advection: niter explicit donor-cell (first-order upwind) steps of
+ * a tracer t carried by volume transports u, v, w through the east, north
+ * and top faces of each cell:
+ *   F = q+ * t(cell below the face) + q- * t(cell above the face),
+ *   q+ = q if q > 0 else 0, q- = q if q < 0 else 0,
+ *   t' = t - r * (((Fe - Fw) + (Fn - Fs)) + (Ft - Fb)),
+ * r = time step / cell volume.  Six FP64 arrays (0:nx+1, 0:ny+1, 0:nz+1)
+ * with equal bounds and strides: t_a holds the initial tracer, its halo the
+ * boundary values, which t_b must hold too; u(0,..), v(..,0,..), w(..,0)
+ * are the transports through the lower domain faces.  Steps alternate
+ * t_a -> t_b -> t_a ...: the result is in t_a when niter is even, else in
+ * t_b; the interiors of both are written (for niter >= 2).  niter >= 0.
+ * t_a and t_b may not overlap each other or u, v, w, r.  Asynchronous on
+ * `stream`.  Errors: J3D_EINVAL, J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
+ */
+int tracer_advection(const j3d_array* t_a, const j3d_array* t_b, const j3d_array* u,
+                     const j3d_array* v, const j3d_array* w, const j3d_array* r,
+                     int64_t niter, void* stream);
 
 /* Solver modes */
 #define J3D_MODE_FP64 0  /* FP64 Jacobi sweeps */

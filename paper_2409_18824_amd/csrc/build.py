@@ -28,9 +28,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off", "-I", INCL
 DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
           "-fno-gpu-flush-denormals-to-zero",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_SOURCES = ["runtime.cpp", "capi.cpp", "solve.cpp", "batch.cpp", "serve.cpp", "jacobi2d.cpp"]
+HOST_SOURCES = ["runtime.cpp", "capi.cpp", "solve.cpp", "batch.cpp", "serve.cpp", "jacobi2d.cpp",
+                "advect.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip",
-                  "kernels_sweep2_f32.hip", "kernels_2d.hip"]
+                  "kernels_sweep2_f32.hip", "kernels_2d.hip", "kernels_advect.hip"]
 
 
 def _run(cmd):

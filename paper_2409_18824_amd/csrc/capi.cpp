@@ -239,7 +239,7 @@ int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags
 int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, double lo, double hi,
                      double halo, void* stream) {
   Field x;
-  J3D_TRY(check_field(a, J3D_F64, &x, "a"));
+  J3D_TRY(check_field_wide(a, J3D_F64, &x, "a"));
   if (x.ey > 65535 || x.ez > 65535) return fail(J3D_EINVAL, "fill: y/z extents above 65535");
   const unsigned long long key = seed ^ (static_cast<unsigned long long>(stream_id) << 40);
   J3D_HIP(launch_fill_uniform(reinterpret_cast<double*>(x.base), x.ex, x.ey, x.ez, x.sy, x.sz, key,
@@ -249,7 +249,7 @@ int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, doub
 
 int j3d_fill_const(const j3d_array* a, double value, void* stream) {
   Field x;
-  J3D_TRY(check_field(a, -1, &x, "a"));
+  J3D_TRY(check_field_wide(a, -1, &x, "a"));
   if (x.ey > 65535 || x.ez > 65535) return fail(J3D_EINVAL, "fill: y/z extents above 65535");
   J3D_HIP(launch_fill_const(x.base, x.dtype, x.ex, x.ey, x.ez, x.sy, x.sz, value,
                             static_cast<hipStream_t>(stream)));

@@ -1,0 +1,267 @@
+// Multi-field 3D stencils on gfx950: the momentum advection standing in for
+// the paper's pw-advection benchmark (three velocity fields in, three
+// tendencies out) and the tracer advection standing in for tra-adv (six
+// fields, iterated); Sec. "Flang performance comparison" gives their field
+// counts and grid sizes.
+//
+// Both are streaming stencils with a few flops per byte: HBM-bound, no dense
+// contraction, no MFMA.  The kernels follow the z-marching design of the
+// Jacobi sweep.  A wavefront owns a tile of 62 x-points (lanes 1..62; lanes 0
+// and 63 hold the x-halo columns, so tiles overlap by two columns) by RY
+// y-rows (one thread holds all RY rows of its column, plus one row above and
+// below) and a chunk of z-planes, and keeps a rolling window of the planes
+// k-1, k, k+1 in registers: every plane of every field is read once per tile.
+// x-neighbours come from the adjacent lanes by DPP wave shifts, y- and
+// z-neighbours from registers.  Four wavefronts of a workgroup take
+// neighbouring rows, so the rows they share hit in the vector cache.
+// Offsets within a plane are 32-bit; plane offsets are 64-bit, so one field
+// may exceed 2^31 elements (the pw-advection grid does).
+//
+// Arithmetic order is fixed and the library is built with contraction off,
+// so the results equal the definitions below bit for bit.
+//
+// Momentum advection (centred flux form of Piacsek and Williams on a
+// staggered grid: u on east faces, v on north faces, w on top faces):
+//   flux difference  D(am, bm, ap, bp, c) = (am * bm - ap * bp) * c,
+//   c = 0.25 / spacing, am / bm the two-point sums of the advecting velocity
+//   and of the advected component at the lower face, ap / bp at the upper;
+//   tendency = (Dx + Dy) + Dz.
+// Tracer advection (donor cell):
+//   F = q+ * t(below) + q- * t(above), q+ = q > 0 ? q : 0, q- = q < 0 ? q : 0,
+//   t' = t - r * (((Fe - Fw) + (Fn - Fs)) + (Ft - Fb)).
+#include "advect.h"
+#include "sweep.h"
+
+namespace j3d {
+namespace {
+
+using sweep_detail::from_left;
+using sweep_detail::from_right;
+using sweep_detail::put;
+using sweep_detail::WAVE;
+using sweep_detail::xcd_remap;
+
+constexpr int kWaves = 4;          // wavefronts per workgroup (stacked in y)
+constexpr int kOut = WAVE - 2;     // outputs per wavefront along x
+
+struct TileMap {
+  int x;      // column of this lane (lane 0 is x0 - 1)
+  int xc;     // column clamped into the array
+  int j0;     // first output row
+  int k0, k1; // planes k0 .. k1-1
+  bool valid;
+};
+
+__device__ __forceinline__ TileMap tile_of(const AdvArgs& a, int ry) {
+  TileMap m;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = b % a.tiles_x;
+  const int rest = b / a.tiles_x;
+  const int yb = rest % a.yblocks;
+  const int kc = rest / a.yblocks;
+  const int ty = yb * kWaves + (int)(threadIdx.x / WAVE);
+  m.valid = ty < a.tiles_y;
+  m.x = tx * kOut + lane;
+  m.xc = min(m.x, a.nx + 1);
+  m.j0 = 1 + ty * ry;
+  m.k0 = 1 + kc * a.planes;
+  m.k1 = min(m.k0 + a.planes, a.nz + 1);
+  return m;
+}
+
+__device__ __forceinline__ double flux_diff(double am, double bm, double ap, double bp, double c) {
+  return (am * bm - ap * bp) * c;
+}
+
+template <int RY, bool NT>
+__global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect(AdvArgs a) {
+  const TileMap m = tile_of(a, RY);
+  if (!m.valid) return;  // the whole wavefront leaves together
+  const int lane = threadIdx.x & (WAVE - 1);
+  int roff[RY + 2];  // in-plane offsets of rows j0-1 .. j0+RY (clamped)
+#pragma unroll
+  for (int r = 0; r < RY + 2; ++r) roff[r] = m.xc + a.siy * min(m.j0 - 1 + r, a.ny + 1);
+  const double* __restrict__ pu = a.in[0];
+  const double* __restrict__ pv = a.in[1];
+  const double* __restrict__ pw = a.in[2];
+  double U[3][RY + 2], V[3][RY + 2], W[3][RY + 2];
+  auto load = [&](int s, int k) {
+    const long long pz = (long long)k * a.siz;
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+      U[s][r] = pu[pz + roff[r]];
+      V[s][r] = pv[pz + roff[r]];
+      W[s][r] = pw[pz + roff[r]];
+    }
+  };
+  load(0, m.k0 - 1);
+  load(1, m.k0);
+  const bool lane_out = lane >= 1 && lane <= kOut && m.x <= a.nx;
+  const double cx = a.cx, cy = a.cy, cz = a.cz;
+  for (int k = m.k0; k < m.k1; ++k) {
+    load(2, k + 1);
+    const long long oz = (long long)k * a.soz;
+#pragma unroll
+    for (int r = 1; r <= RY; ++r) {
+      const double u = U[1][r], v = V[1][r], w = W[1][r];
+      const double uL = from_left(u), uR = from_right(u);
+      const double vL = from_left(v), vR = from_right(v);
+      const double wL = from_left(w), wR = from_right(w);
+      // u at the east face (i+1/2, j, k)
+      const double sxm = uL + u, sxp = u + uR;
+      double tx = flux_diff(sxm, sxm, sxp, sxp, cx);
+      const double vs = V[1][r - 1];
+      double ty = flux_diff(vs + from_right(vs), U[1][r - 1] + u, v + vR, u + U[1][r + 1], cy);
+      const double wb = W[0][r];
+      double tz = flux_diff(wb + from_right(wb), U[0][r] + u, w + wR, u + U[2][r], cz);
+      const double su = (tx + ty) + tz;
+      // v at the north face (i, j+1/2, k)
+      const double un = U[1][r + 1];
+      tx = flux_diff(uL + from_left(un), vL + v, u + un, v + vR, cx);
+      const double syn = vs + v, syp = v + V[1][r + 1];
+      ty = flux_diff(syn, syn, syp, syp, cy);
+      tz = flux_diff(wb + W[0][r + 1], V[0][r] + v, w + W[1][r + 1], v + V[2][r], cz);
+      const double sv = (tx + ty) + tz;
+      // w at the top face (i, j, k+1/2)
+      const double ut = U[2][r];
+      tx = flux_diff(uL + from_left(ut), wL + w, u + ut, w + wR, cx);
+      const double vt = V[2][r - 1];
+      ty = flux_diff(vs + vt, W[1][r - 1] + w, v + V[2][r], w + W[1][r + 1], cy);
+      const double szm = wb + w, szp = w + W[2][r];
+      tz = flux_diff(szm, szm, szp, szp, cz);
+      const double sw = (tx + ty) + tz;
+      const int j = m.j0 + r - 1;
+      if (lane_out && j <= a.ny) {
+        const long long o = oz + m.x + (long long)a.soy * j;
+        put<double, NT>(a.out[0] + o, su);
+        put<double, NT>(a.out[1] + o, sv);
+        put<double, NT>(a.out[2] + o, sw);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+      U[0][r] = U[1][r]; U[1][r] = U[2][r];
+      V[0][r] = V[1][r]; V[1][r] = V[2][r];
+      W[0][r] = W[1][r]; W[1][r] = W[2][r];
+    }
+  }
+}
+
+__device__ __forceinline__ double upwind(double q, double below, double above) {
+  const double qp = q > 0.0 ? q : 0.0;
+  const double qm = q < 0.0 ? q : 0.0;
+  return qp * below + qm * above;
+}
+
+// in[0..3] = u, v, w, r; t = input iterate; out[0] = output iterate.
+template <int RY, bool NT>
+__global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
+  const TileMap m = tile_of(a, RY);
+  if (!m.valid) return;
+  const int lane = threadIdx.x & (WAVE - 1);
+  int roff[RY + 2];
+#pragma unroll
+  for (int r = 0; r < RY + 2; ++r) roff[r] = m.xc + a.siy * min(m.j0 - 1 + r, a.ny + 1);
+  const double* __restrict__ pt = a.t;
+  const double* __restrict__ pu = a.in[0];
+  const double* __restrict__ pv = a.in[1];
+  const double* __restrict__ pw = a.in[2];
+  const double* __restrict__ pr = a.in[3];
+  double T[3][RY + 2], Wb[RY + 2];
+  {
+    const long long z0 = (long long)(m.k0 - 1) * a.siz, z1 = (long long)m.k0 * a.siz;
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+      T[0][r] = pt[z0 + roff[r]];
+      T[1][r] = pt[z1 + roff[r]];
+      Wb[r] = pw[z0 + roff[r]];
+    }
+  }
+  const bool lane_out = lane >= 1 && lane <= kOut && m.x <= a.nx;
+  for (int k = m.k0; k < m.k1; ++k) {
+    const long long pz = (long long)k * a.siz;
+    const long long nz = pz + a.siz;
+    double U[RY + 2], V[RY + 2], W[RY + 2], R[RY + 2];
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+      T[2][r] = pt[nz + roff[r]];
+      if (r >= 1 && r <= RY) {
+        U[r] = pu[pz + roff[r]];
+        W[r] = pw[pz + roff[r]];
+        R[r] = pr[pz + roff[r]];
+      }
+      if (r <= RY) V[r] = pv[pz + roff[r]];
+    }
+#pragma unroll
+    for (int r = 1; r <= RY; ++r) {
+      const double tc = T[1][r];
+      const double tl = from_left(tc), tr = from_right(tc);
+      const double fe = upwind(U[r], tc, tr);
+      const double fw = upwind(from_left(U[r]), tl, tc);
+      const double fn = upwind(V[r], tc, T[1][r + 1]);
+      const double fs = upwind(V[r - 1], T[1][r - 1], tc);
+      const double ft = upwind(W[r], tc, T[2][r]);
+      const double fb = upwind(Wb[r], T[0][r], tc);
+      const double div = ((fe - fw) + (fn - fs)) + (ft - fb);
+      const double tn = tc - R[r] * div;
+      const int j = m.j0 + r - 1;
+      if (lane_out && j <= a.ny) put<double, NT>(a.out[0] + (pz + m.x + (long long)a.siy * j), tn);
+    }
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+      T[0][r] = T[1][r];
+      T[1][r] = T[2][r];
+      if (r >= 1 && r <= RY) Wb[r] = W[r];
+    }
+  }
+}
+
+template <typename Kernel>
+hipError_t go(Kernel kern, AdvArgs a, int ry, hipStream_t st) {
+  a.tiles_x = (a.nx + kOut - 1) / kOut;
+  a.tiles_y = (a.ny + ry - 1) / ry;
+  a.yblocks = (a.tiles_y + kWaves - 1) / kWaves;
+  const int zchunks = (a.nz + a.planes - 1) / a.planes;
+  const long long blocks = (long long)a.tiles_x * a.yblocks * zchunks;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks >= (1LL << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WAVE * kWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool advect_cfg_supported(const AdvectCfg& c) {
+  return (c.ry == 2 || c.ry == 4 || c.ry == 8) && c.planes >= 1 && (c.nt == 0 || c.nt == 1);
+}
+
+hipError_t launch_pw_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st) {
+  if (!advect_cfg_supported(c)) return hipErrorInvalidValue;
+  AdvArgs g = a;
+  g.planes = c.planes;
+  switch (c.ry * 2 + c.nt) {
+    case 4: return go(k_pw_advect<2, false>, g, 2, st);
+    case 5: return go(k_pw_advect<2, true>, g, 2, st);
+    case 8: return go(k_pw_advect<4, false>, g, 4, st);
+    case 9: return go(k_pw_advect<4, true>, g, 4, st);
+    case 16: return go(k_pw_advect<8, false>, g, 8, st);
+    default: return go(k_pw_advect<8, true>, g, 8, st);
+  }
+}
+
+hipError_t launch_tracer_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st) {
+  if (!advect_cfg_supported(c)) return hipErrorInvalidValue;
+  AdvArgs g = a;
+  g.planes = c.planes;
+  switch (c.ry * 2 + c.nt) {
+    case 4: return go(k_tracer_advect<2, false>, g, 2, st);
+    case 5: return go(k_tracer_advect<2, true>, g, 2, st);
+    case 8: return go(k_tracer_advect<4, false>, g, 4, st);
+    case 9: return go(k_tracer_advect<4, true>, g, 4, st);
+    case 16: return go(k_tracer_advect<8, false>, g, 8, st);
+    default: return go(k_tracer_advect<8, true>, g, 8, st);
+  }
+}
+
+}  // namespace j3d

@@ -38,7 +38,9 @@ double now_seconds() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-int check_field(const j3d_array* a, int dtype, Field* out, const char* name) {
+namespace {
+
+int check_field_impl(const j3d_array* a, int dtype, Field* out, const char* name, bool wide) {
   if (a == nullptr) return fail(J3D_EINVAL, "%s: null descriptor", name);
   if (a->base == nullptr) return fail(J3D_EINVAL, "%s: null base address", name);
   if (a->reserved != 0) return fail(J3D_EINVAL, "%s: reserved field must be 0", name);
@@ -61,9 +63,17 @@ int check_field(const j3d_array* a, int dtype, Field* out, const char* name) {
   if (a->stride[2] < a->stride[1] * ext[1])
     return fail(J3D_EINVAL, "%s: stride[2]=%lld < stride[1]*extent[1]=%lld", name,
                 (long long)a->stride[2], (long long)(a->stride[1] * ext[1]));
-  const long long maxoff = (ext[2] - 1) * a->stride[2] + (ext[1] - 1) * a->stride[1] + (ext[0] - 1);
-  if (maxoff >= (1LL << 31) - 1)
-    return fail(J3D_EINVAL, "%s: largest element offset %lld exceeds 2^31", name, maxoff);
+  const long long plane_off = (ext[1] - 1) * a->stride[1] + (ext[0] - 1);
+  if (wide) {
+    if (plane_off >= (1LL << 31) - 1)
+      return fail(J3D_EINVAL, "%s: largest offset within a plane %lld exceeds 2^31", name, plane_off);
+    if (a->stride[2] > ((1LL << 46) - 1) / ext[2])
+      return fail(J3D_EINVAL, "%s: array spans more than 2^46 elements", name);
+  } else {
+    const long long maxoff = (ext[2] - 1) * a->stride[2] + plane_off;
+    if (maxoff >= (1LL << 31) - 1)
+      return fail(J3D_EINVAL, "%s: largest element offset %lld exceeds 2^31", name, maxoff);
+  }
   const int esize = a->dtype == J3D_F64 ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(a->base) % esize != 0)
     return fail(J3D_EINVAL, "%s: base is not aligned to its element size", name);
@@ -78,6 +88,16 @@ int check_field(const j3d_array* a, int dtype, Field* out, const char* name) {
     out->sz = a->stride[2];
   }
   return J3D_OK;
+}
+
+}  // namespace
+
+int check_field(const j3d_array* a, int dtype, Field* out, const char* name) {
+  return check_field_impl(a, dtype, out, name, false);
+}
+
+int check_field_wide(const j3d_array* a, int dtype, Field* out, const char* name) {
+  return check_field_impl(a, dtype, out, name, true);
 }
 
 int check_field2d(const j3d_array* a, int dtype, Field* out, const char* name) {

@@ -42,6 +42,9 @@ struct Field {
 
 // Validate a descriptor; dtype < 0 accepts either element type.
 int check_field(const j3d_array* a, int dtype, Field* out, const char* name);
+// As check_field, for kernels that address planes with 64-bit offsets: only
+// the offsets within one plane must stay below 2^31.
+int check_field_wide(const j3d_array* a, int dtype, Field* out, const char* name);
 // Validate a rank-2 array: axes 0 and 1 as for check_field, axis 2 of
 // extent 1 (lbound[2] == ubound[2]); ez = 1 in the result.
 int check_field2d(const j3d_array* a, int dtype, Field* out, const char* name);

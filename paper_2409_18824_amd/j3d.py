@@ -130,6 +130,8 @@ _SIGS = {
     "j3d_sum": ([_V, _I64, _U32, _V, _V], ctypes.c_int),
     "jacobi2d_sweeps": ([_P(J3DArray), _P(J3DArray), _I64, _D, _U32, _V, _V], ctypes.c_int),
     "j3d_dot": ([_V, _V, _I64, _U32, _V, _V], ctypes.c_int),
+    "pw_advection": ([_P(J3DArray)] * 6 + [_D, _D, _D, _V], ctypes.c_int),
+    "tracer_advection": ([_P(J3DArray)] * 6 + [_I64, _V], ctypes.c_int),
     "j3d_release_cache": ([], ctypes.c_int),
 }
 
@@ -364,6 +366,24 @@ def jacobi2d_sweeps(u_a: FArray, u_b: FArray, nsweeps: int, h: float = 1.0, resi
     _check(_lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(b), int(nsweeps), float(h), 0, ptr, st),
            "jacobi2d_sweeps")
     return None
+
+
+def pw_advection(u: FArray, v: FArray, w: FArray, su: FArray, sv: FArray, sw: FArray,
+                 dx: float, dy: float, dz: float, stream=None):
+    """Momentum advection tendencies (su, sv, sw) of the staggered velocity
+    (u, v, w), centred flux form; asynchronous."""
+    d = [a.desc() for a in (u, v, w, su, sv, sw)]
+    _check(_lib.pw_advection(*[ctypes.byref(x) for x in d], float(dx), float(dy), float(dz),
+                             _stream_handle(stream)), "pw_advection")
+
+
+def tracer_advection(t_a: FArray, t_b: FArray, u: FArray, v: FArray, w: FArray, r: FArray, niter: int,
+                     stream=None):
+    """niter donor-cell steps alternating t_a -> t_b -> ...; the result is in
+    t_a when niter is even.  Asynchronous."""
+    d = [a.desc() for a in (t_a, t_b, u, v, w, r)]
+    _check(_lib.tracer_advection(*[ctypes.byref(x) for x in d], int(niter), _stream_handle(stream)),
+           "tracer_advection")
 
 
 def j3d_sum(x, out=None, stream=None):

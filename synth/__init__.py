@@ -38,6 +38,12 @@ STREAM_F = 2
 STREAM_SIZES = 3
 STREAM_ARRIVALS = 4
 STREAM_TOL = 5
+# multi-field stencils: velocities / transports, tracer, reciprocal volume
+STREAM_ADV_U = 6
+STREAM_ADV_V = 7
+STREAM_ADV_W = 8
+STREAM_TRACER = 9
+STREAM_RVOL = 10
 
 
 def _u64(x):
@@ -77,6 +83,21 @@ def uniform_field(nx: int, ny: int, nz: int, seed: int, stream: int,
         idx = np.arange(k0 * per_plane, k1 * per_plane, dtype=np.uint64)
         a[1 + k0:1 + k1, 1:ny + 1, 1:nx + 1] = uniform(seed, stream, idx, lo, hi).reshape(k1 - k0, ny, nx)
     return a
+
+
+def uniform_box(nx: int, ny: int, nz: int, seed: int, stream: int, lo: float, hi: float, halo: float,
+                i0: int, i1: int, j0: int, j1: int, k0: int, k1: int) -> np.ndarray:
+    """The block [k0:k1, j0:j1, i0:i1] (padded indices, halo = index 0 and
+    n+1) of ``uniform_field(nx, ny, nz, seed, stream, lo, hi, halo)``,
+    computed without the rest of the field."""
+    k = np.arange(k0, k1, dtype=np.int64)[:, None, None]
+    j = np.arange(j0, j1, dtype=np.int64)[None, :, None]
+    i = np.arange(i0, i1, dtype=np.int64)[None, None, :]
+    inside = (i >= 1) & (i <= nx) & (j >= 1) & (j <= ny) & (k >= 1) & (k <= nz)
+    lin = (i - 1) + nx * ((j - 1) + ny * (k - 1))
+    lin = np.where(inside, lin, 0).astype(np.uint64)
+    vals = uniform(seed, stream, lin, lo, hi)
+    return np.where(inside, vals, halo)
 
 
 def sine_factors(n: int, h: float) -> np.ndarray:
@@ -187,3 +208,34 @@ def serve_requests(count: int = 1000, rate: float = 200.0, seed: int = 5,
                                 tols[0] if ut[r] < 0.5 else tols[1],
                                 seed * 65536 + r, max_sweeps))
     return out
+
+
+# Multi-field stencils (stand-ins for pw-advection and tra-adv).
+PW_SHAPE = (2048, 1024, 1024)     # three fields
+TRA_SHAPE = (1024, 512, 512)      # six fields, 20 iterations
+TRA_ITERS = 20
+
+
+@dataclass
+class FieldRecipe:
+    seed: int
+    stream: int
+    lo: float
+    hi: float
+    halo: float
+
+
+def pw_recipe(seed: int = 6):
+    """Velocities u, v, w ~ U[-1, 1), halo 0.25; spacing 1/1024 on every axis."""
+    fields = [FieldRecipe(seed, s, -1.0, 1.0, 0.25) for s in (STREAM_ADV_U, STREAM_ADV_V, STREAM_ADV_W)]
+    return fields, (1.0 / 1024, 1.0 / 1024, 1.0 / 1024)
+
+
+def tracer_recipe(seed: int = 7):
+    """Tracer t ~ U[0, 1) (halo 0.5); transports u, v, w ~ U[-0.1, 0.1) (halo
+    0); r = step / volume ~ U[0.5, 1.5) (halo 1).  r times the outflow of a
+    cell stays below 0.9, so the steps are stable."""
+    t = FieldRecipe(seed, STREAM_TRACER, 0.0, 1.0, 0.5)
+    vel = [FieldRecipe(seed, s, -0.1, 0.1, 0.0) for s in (STREAM_ADV_U, STREAM_ADV_V, STREAM_ADV_W)]
+    r = FieldRecipe(seed, STREAM_RVOL, 0.5, 1.5, 1.0)
+    return t, vel, r

@@ -246,3 +246,72 @@ def test_jacobi2d_validation_before_device_work():
     out = ctypes.c_double()
     assert lib.jacobi2d_sweeps(ctypes.byref(a), ctypes.byref(b), 4, -1.0, j3d.HOST_RESULT,
                                ctypes.cast(ctypes.byref(out), ctypes.c_void_p), None) == j3d.EINVAL
+
+
+def _descs(n, nx=10, ny=8, nz=6, gap=0x1000000):
+    return [fake_desc(nx, ny, nz, base=0x10000 + q * gap) for q in range(n)]
+
+
+def _call_pw(d, dx=0.1, dy=0.1, dz=0.1):
+    return j3d._lib.pw_advection(*[ctypes.byref(x) for x in d], dx, dy, dz, None)
+
+
+def _call_tracer(d, niter=2):
+    return j3d._lib.tracer_advection(*[ctypes.byref(x) for x in d], niter, None)
+
+
+def test_pw_advection_validation_before_device_work():
+    d = _descs(6)
+    d[1] = fake_desc(11, 8, 6, base=d[1].base)  # v extent differs
+    assert _call_pw(d) == j3d.EINVAL
+    d = _descs(6)
+    d[2] = fake_desc(10, 8, 6, base=d[2].base, ld=16)  # w stride differs from u
+    assert _call_pw(d) == j3d.EINVAL and "strides" in j3d.last_error()
+    d = _descs(6)
+    d[4] = fake_desc(10, 8, 6, base=d[4].base, ld=16)  # sv stride differs from su
+    assert _call_pw(d) == j3d.EINVAL
+    d = _descs(6)
+    d[3] = fake_desc(10, 8, 7, base=d[3].base)  # su interior differs
+    assert _call_pw(d) == j3d.EINVAL
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        assert _call_pw(_descs(6), dz=bad) == j3d.EINVAL
+    d = _descs(6)
+    d[5] = fake_desc(10, 8, 6, base=d[0].base + 8)  # sw overlaps u
+    assert _call_pw(d) == j3d.EALIAS
+    d = _descs(6)
+    d[4] = fake_desc(10, 8, 6, base=d[3].base + 64)  # sv overlaps su
+    assert _call_pw(d) == j3d.EALIAS
+    d = _descs(6)
+    d[0].dtype = j3d.F32
+    assert _call_pw(d) == j3d.EDTYPE
+    # a plane whose own offsets exceed 2^31 is rejected
+    big = [fake_desc(10, 8, 6, base=0x10000 + q * (1 << 40), ld=1 << 28) for q in range(6)]
+    assert _call_pw(big) == j3d.EINVAL and "plane" in j3d.last_error()
+
+
+def test_tracer_advection_validation_before_device_work():
+    assert _call_tracer(_descs(6), niter=-1) == j3d.EINVAL
+    d = _descs(6)
+    d[3] = fake_desc(10, 8, 6, base=d[3].base, plane=11 * 12 * 10)  # v plane stride differs
+    assert _call_tracer(d) == j3d.EINVAL
+    d = _descs(6)
+    d[1] = fake_desc(10, 8, 6, base=d[0].base + 8)  # t_b overlaps t_a
+    assert _call_tracer(d) == j3d.EALIAS
+    d = _descs(6)
+    d[0] = fake_desc(10, 8, 6, base=d[5].base)  # t_a overlaps r
+    assert _call_tracer(d) == j3d.EALIAS
+
+
+def test_wide_arrays_only_where_planes_are_addressed_in_64_bit():
+    """An array of more than 2^31 elements (small planes, many of them) passes
+    the advection checks' size rule but not the Jacobi sweep's."""
+    nx, ny, nz = 30, 30, 3000000  # 32*32*3000002 > 2^31 elements
+    u = fake_desc(nx, ny, nz)
+    o = fake_desc(nx, ny, nz, base=0x10000 + (1 << 40))
+    f = fake_desc(nx, ny, nz, base=0x10000 + (2 << 40))
+    assert j3d._lib.jacobi3d_sweep(ctypes.byref(u), ctypes.byref(o), ctypes.byref(f), 0.1, 0, None,
+                                   None) == j3d.EINVAL
+    assert "2^31" in j3d.last_error()
+    d = [fake_desc(nx, ny, nz, base=0x10000 + q * (1 << 40)) for q in range(6)]
+    d[5].dtype = j3d.F32  # fails on the dtype, after the size rule accepted the others
+    assert _call_pw(d) == j3d.EDTYPE
