@@ -482,7 +482,7 @@ def run_reduce(args):
                  "GB/s", tot_ms, "f64", "reduce-sum32768sq-dot2p27", extra={"results": out})
 
 
-ADVECT_SOURCES = ("advect.h", "kernels_advect.hip", "sweep.h")
+ADVECT_SOURCES = ("advect.h", "advect.cpp", "kernels_advect.hip", "sweep.h")
 
 
 def advect_source_hash() -> str:
@@ -523,10 +523,23 @@ def _event_times(call, steps):
     return [a.elapsed_time(b) * 1e-3 for a, b in ev]
 
 
-def _advect_roofline(alg_bytes, launch_s, traffic):
+def _advect_roofline(alg_bytes, launch_s, traffic, launches, args):
     gbs = alg_bytes / launch_s / 1e9
-    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(launch_s * 1e6, 1), "launches": launches}
+    if args.probe:
+        import torch
+
+        from paper_2409_18824_amd import j3d
+
+        nprobe = 1 << 27  # 1 GiB of doubles per buffer
+        src = torch.ones(nprobe, dtype=torch.float64, device="cuda")
+        dst = torch.zeros(nprobe, dtype=torch.float64, device="cuda")
+        roof["copy_ceiling_gbps"] = round(j3d.j3d_bandwidth_probe(src, dst, reps=5), 1)
+        roof["frac_of_copy_ceiling"] = round(gbs / roof["copy_ceiling_gbps"], 4)
+        del src, dst
+    return roof
 
 
 def run_pw_advection(args):
@@ -557,8 +570,8 @@ def run_pw_advection(args):
                 round(pts / med / 1e9, 2), "Gpoints/s", round(med * 1e3, 3), "f64",
                 "pw-advection-%dx%dx%d" % (nx, ny, nz),
                 extra={"tile": advect_tile(), "algorithmic_bytes_per_launch": alg, "launches_per_step": 1})
-    out["roofline"] = _advect_roofline(alg, med, advect_traffic("pw_advection"))
     del ins, outs
+    out["roofline"] = _advect_roofline(alg, med, advect_traffic("pw_advection"), len(times), args)
     if not args.no_cpu_baseline:
         import oracle
 
@@ -606,8 +619,8 @@ def run_tra_adv(args):
                 round(pts * S / med / 1e9, 2), "GLUP/s", round(med * 1e3, 3), "f64",
                 "tra-adv-%dx%dx%d-%dsteps" % (nx, ny, nz, S),
                 extra={"tile": advect_tile(), "algorithmic_bytes_per_launch": alg, "launches_per_step": S})
-    out["roofline"] = _advect_roofline(alg, med / S, advect_traffic("tracer_advection"))
     del arrs
+    out["roofline"] = _advect_roofline(alg, med / S, advect_traffic("tracer_advection"), len(times) * S, args)
     if not args.no_cpu_baseline:
         import oracle
 

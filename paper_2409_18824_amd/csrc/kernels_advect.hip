@@ -6,14 +6,17 @@
 //
 // Both are streaming stencils with a few flops per byte: HBM-bound, no dense
 // contraction, no MFMA.  The kernels follow the z-marching design of the
-// Jacobi sweep.  A wavefront owns a tile of 62 x-points (lanes 1..62; lanes 0
-// and 63 hold the x-halo columns, so tiles overlap by two columns) by RY
-// y-rows (one thread holds all RY rows of its column, plus one row above and
-// below) and a chunk of z-planes, and keeps a rolling window of the planes
-// k-1, k, k+1 in registers: every plane of every field is read once per tile.
-// x-neighbours come from the adjacent lanes by DPP wave shifts, y- and
-// z-neighbours from registers.  Four wavefronts of a workgroup take
-// neighbouring rows, so the rows they share hit in the vector cache.
+// Jacobi sweep.  A wavefront owns a tile of 64 x-points (one 128-byte-aligned
+// 512-byte row segment per field and row, so every load and store covers
+// whole cache lines) by RY y-rows (one thread holds all RY rows of its
+// column, plus one row above and below) and a chunk of z-planes, and keeps a
+// rolling window of the planes k-1, k, k+1 in registers: every plane of every
+// field is read once per tile.  x-neighbours come from the adjacent lanes by
+// DPP wave shifts; the two halo columns left and right of the tile come from
+// one gather load per field and plane (lane q < RY+2 reads the left column
+// of row q, lane 32+q the right one) and reach lanes 0 and 63 by readlane.
+// y- and z-neighbours come from registers.  Four wavefronts of a workgroup
+// take neighbouring rows, so the rows they share hit in the vector cache.
 // Offsets within a plane are 32-bit; plane offsets are 64-bit, so one field
 // may exceed 2^31 elements (the pw-advection grid does).
 //
@@ -37,24 +40,27 @@ namespace {
 
 using sweep_detail::from_left;
 using sweep_detail::from_right;
+using sweep_detail::lane_value;
 using sweep_detail::put;
 using sweep_detail::WAVE;
 using sweep_detail::xcd_remap;
 
-constexpr int kWaves = 4;          // wavefronts per workgroup (stacked in y)
-constexpr int kOut = WAVE - 2;     // outputs per wavefront along x
+constexpr int kWaves = 4;  // wavefronts per workgroup (stacked in y)
 
 struct TileMap {
-  int x;      // column of this lane (lane 0 is x0 - 1)
+  int lane;
+  int x;      // column of this lane
   int xc;     // column clamped into the array
   int j0;     // first output row
   int k0, k1; // planes k0 .. k1-1
+  int goff;   // in-plane offset of this lane's halo-column element
+  bool gat;   // this lane takes part in the halo gather
   bool valid;
 };
 
 __device__ __forceinline__ TileMap tile_of(const AdvArgs& a, int ry) {
   TileMap m;
-  const int lane = threadIdx.x & (WAVE - 1);
+  m.lane = threadIdx.x & (WAVE - 1);
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = b % a.tiles_x;
   const int rest = b / a.tiles_x;
@@ -62,12 +68,32 @@ __device__ __forceinline__ TileMap tile_of(const AdvArgs& a, int ry) {
   const int kc = rest / a.yblocks;
   const int ty = yb * kWaves + (int)(threadIdx.x / WAVE);
   m.valid = ty < a.tiles_y;
-  m.x = tx * kOut + lane;
+  const int x0 = 1 + tx * WAVE;
+  m.x = x0 + m.lane;
   m.xc = min(m.x, a.nx + 1);
   m.j0 = 1 + ty * ry;
   m.k0 = 1 + kc * a.planes;
   m.k1 = min(m.k0 + a.planes, a.nz + 1);
+  // lane q < ry+2: column x0-1 of row j0-1+q; lane 32+q: column x0+64
+  // (clamped onto the halo column) of the same row
+  const int q = m.lane < 32 ? m.lane : m.lane - 32;
+  m.gat = q < ry + 2;
+  const int gx = m.lane < 32 ? x0 - 1 : min(x0 + WAVE, a.nx + 1);
+  m.goff = gx + a.siy * min(m.j0 - 1 + min(q, ry + 1), a.ny + 1);
   return m;
+}
+
+// Left / right x-neighbour of value v of row r, whose halo columns are in
+// the gathered vector g (lane r: left, lane 32+r: right).
+__device__ __forceinline__ double nb_left(double v, double g, int r, int lane) {
+  const double h = lane_value(g, r);
+  const double s = from_left(v);
+  return lane == 0 ? h : s;
+}
+__device__ __forceinline__ double nb_right(double v, double g, int r, int lane) {
+  const double h = lane_value(g, 32 + r);
+  const double s = from_right(v);
+  return lane == WAVE - 1 ? h : s;
 }
 
 __device__ __forceinline__ double flux_diff(double am, double bm, double ap, double bp, double c) {
@@ -78,14 +104,15 @@ template <int RY, bool NT>
 __global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect(AdvArgs a) {
   const TileMap m = tile_of(a, RY);
   if (!m.valid) return;  // the whole wavefront leaves together
-  const int lane = threadIdx.x & (WAVE - 1);
+  const int lane = m.lane;
   int roff[RY + 2];  // in-plane offsets of rows j0-1 .. j0+RY (clamped)
 #pragma unroll
   for (int r = 0; r < RY + 2; ++r) roff[r] = m.xc + a.siy * min(m.j0 - 1 + r, a.ny + 1);
   const double* __restrict__ pu = a.in[0];
   const double* __restrict__ pv = a.in[1];
   const double* __restrict__ pw = a.in[2];
-  double U[3][RY + 2], V[3][RY + 2], W[3][RY + 2];
+  // planes k-1, k, k+1 of each field, and their gathered halo columns
+  double U[3][RY + 2], V[3][RY + 2], W[3][RY + 2], GU[3], GV[3], GW[3];
   auto load = [&](int s, int k) {
     const long long pz = (long long)k * a.siz;
 #pragma unroll
@@ -94,10 +121,13 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect(AdvArgs a) {
       V[s][r] = pv[pz + roff[r]];
       W[s][r] = pw[pz + roff[r]];
     }
+    GU[s] = m.gat ? pu[pz + m.goff] : 0.0;
+    GV[s] = m.gat ? pv[pz + m.goff] : 0.0;
+    GW[s] = m.gat ? pw[pz + m.goff] : 0.0;
   };
   load(0, m.k0 - 1);
   load(1, m.k0);
-  const bool lane_out = lane >= 1 && lane <= kOut && m.x <= a.nx;
+  const bool lane_out = m.x <= a.nx;
   const double cx = a.cx, cy = a.cy, cz = a.cz;
   for (int k = m.k0; k < m.k1; ++k) {
     load(2, k + 1);
@@ -105,27 +135,27 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect(AdvArgs a) {
 #pragma unroll
     for (int r = 1; r <= RY; ++r) {
       const double u = U[1][r], v = V[1][r], w = W[1][r];
-      const double uL = from_left(u), uR = from_right(u);
-      const double vL = from_left(v), vR = from_right(v);
-      const double wL = from_left(w), wR = from_right(w);
+      const double uL = nb_left(u, GU[1], r, lane), uR = nb_right(u, GU[1], r, lane);
+      const double vL = nb_left(v, GV[1], r, lane), vR = nb_right(v, GV[1], r, lane);
+      const double wL = nb_left(w, GW[1], r, lane), wR = nb_right(w, GW[1], r, lane);
       // u at the east face (i+1/2, j, k)
       const double sxm = uL + u, sxp = u + uR;
       double tx = flux_diff(sxm, sxm, sxp, sxp, cx);
       const double vs = V[1][r - 1];
-      double ty = flux_diff(vs + from_right(vs), U[1][r - 1] + u, v + vR, u + U[1][r + 1], cy);
+      double ty = flux_diff(vs + nb_right(vs, GV[1], r - 1, lane), U[1][r - 1] + u, v + vR, u + U[1][r + 1], cy);
       const double wb = W[0][r];
-      double tz = flux_diff(wb + from_right(wb), U[0][r] + u, w + wR, u + U[2][r], cz);
+      double tz = flux_diff(wb + nb_right(wb, GW[0], r, lane), U[0][r] + u, w + wR, u + U[2][r], cz);
       const double su = (tx + ty) + tz;
       // v at the north face (i, j+1/2, k)
       const double un = U[1][r + 1];
-      tx = flux_diff(uL + from_left(un), vL + v, u + un, v + vR, cx);
+      tx = flux_diff(uL + nb_left(un, GU[1], r + 1, lane), vL + v, u + un, v + vR, cx);
       const double syn = vs + v, syp = v + V[1][r + 1];
       ty = flux_diff(syn, syn, syp, syp, cy);
       tz = flux_diff(wb + W[0][r + 1], V[0][r] + v, w + W[1][r + 1], v + V[2][r], cz);
       const double sv = (tx + ty) + tz;
       // w at the top face (i, j, k+1/2)
       const double ut = U[2][r];
-      tx = flux_diff(uL + from_left(ut), wL + w, u + ut, w + wR, cx);
+      tx = flux_diff(uL + nb_left(ut, GU[2], r, lane), wL + w, u + ut, w + wR, cx);
       const double vt = V[2][r - 1];
       ty = flux_diff(vs + vt, W[1][r - 1] + w, v + V[2][r], w + W[1][r + 1], cy);
       const double szm = wb + w, szp = w + W[2][r];
@@ -145,6 +175,9 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect(AdvArgs a) {
       V[0][r] = V[1][r]; V[1][r] = V[2][r];
       W[0][r] = W[1][r]; W[1][r] = W[2][r];
     }
+    GU[0] = GU[1]; GU[1] = GU[2];
+    GV[0] = GV[1]; GV[1] = GV[2];
+    GW[0] = GW[1]; GW[1] = GW[2];
   }
 }
 
@@ -159,7 +192,7 @@ template <int RY, bool NT>
 __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
   const TileMap m = tile_of(a, RY);
   if (!m.valid) return;
-  const int lane = threadIdx.x & (WAVE - 1);
+  const int lane = m.lane;
   int roff[RY + 2];
 #pragma unroll
   for (int r = 0; r < RY + 2; ++r) roff[r] = m.xc + a.siy * min(m.j0 - 1 + r, a.ny + 1);
@@ -169,6 +202,7 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
   const double* __restrict__ pw = a.in[2];
   const double* __restrict__ pr = a.in[3];
   double T[3][RY + 2], Wb[RY + 2];
+  double GT1, GT2;  // halo columns of planes k and k+1 of t
   {
     const long long z0 = (long long)(m.k0 - 1) * a.siz, z1 = (long long)m.k0 * a.siz;
 #pragma unroll
@@ -177,8 +211,9 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
       T[1][r] = pt[z1 + roff[r]];
       Wb[r] = pw[z0 + roff[r]];
     }
+    GT1 = m.gat ? pt[z1 + m.goff] : 0.0;
   }
-  const bool lane_out = lane >= 1 && lane <= kOut && m.x <= a.nx;
+  const bool lane_out = m.x <= a.nx;
   for (int k = m.k0; k < m.k1; ++k) {
     const long long pz = (long long)k * a.siz;
     const long long nz = pz + a.siz;
@@ -193,12 +228,14 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
       }
       if (r <= RY) V[r] = pv[pz + roff[r]];
     }
+    GT2 = m.gat ? pt[nz + m.goff] : 0.0;
+    const double GU = m.gat ? pu[pz + m.goff] : 0.0;
 #pragma unroll
     for (int r = 1; r <= RY; ++r) {
       const double tc = T[1][r];
-      const double tl = from_left(tc), tr = from_right(tc);
+      const double tl = nb_left(tc, GT1, r, lane), tr = nb_right(tc, GT1, r, lane);
       const double fe = upwind(U[r], tc, tr);
-      const double fw = upwind(from_left(U[r]), tl, tc);
+      const double fw = upwind(nb_left(U[r], GU, r, lane), tl, tc);
       const double fn = upwind(V[r], tc, T[1][r + 1]);
       const double fs = upwind(V[r - 1], T[1][r - 1], tc);
       const double ft = upwind(W[r], tc, T[2][r]);
@@ -214,12 +251,13 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
       T[1][r] = T[2][r];
       if (r >= 1 && r <= RY) Wb[r] = W[r];
     }
+    GT1 = GT2;
   }
 }
 
 template <typename Kernel>
 hipError_t go(Kernel kern, AdvArgs a, int ry, hipStream_t st) {
-  a.tiles_x = (a.nx + kOut - 1) / kOut;
+  a.tiles_x = (a.nx + WAVE - 1) / WAVE;
   a.tiles_y = (a.ny + ry - 1) / ry;
   a.yblocks = (a.tiles_y + kWaves - 1) / kWaves;
   const int zchunks = (a.nz + a.planes - 1) / a.planes;

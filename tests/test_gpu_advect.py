@@ -18,8 +18,8 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 
 # rows per thread, z-planes per wavefront, nontemporal stores
 TILES = ["2,7,0", "2,128,1", "4,5,1", "4,128,0", "8,3,0", "8,64,1"]
-# x tiles are 62 wide, y tiles 4 x rows-per-thread, z chunks `planes` deep
-SHAPES = [(1, 1, 1), (62, 4, 3), (63, 17, 9), (130, 37, 19), (125, 9, 131)]
+# x tiles are 64 wide, y tiles 4 x rows-per-thread, z chunks `planes` deep
+SHAPES = [(1, 1, 1), (64, 4, 3), (65, 8, 2), (63, 17, 9), (130, 37, 19), (125, 9, 131)]
 
 
 def rand_padded(nx, ny, nz, seed, stream, lo=-1.0, hi=1.0):
@@ -114,7 +114,7 @@ def test_pw_advection_full_size_sampled():
     outs = [j3d.FArray.empty(nx, ny, nz) for _ in range(3)]
     j3d.pw_advection(*ins, *outs, *d)  # the library's default tile shape
     torch.cuda.synchronize()
-    seams = ((1, 2, 62, 63, 124, 2046, 2047, 2048), (1, 4, 5, 16, 17, 1023, 1024), (1, 128, 129, 1024))
+    seams = ((1, 2, 63, 64, 65, 128, 129, 2047, 2048), (1, 4, 5, 16, 17, 1023, 1024), (1, 128, 129, 1024))
     pts = sample_points((nx, ny, nz), 1500, seams, 31)
     got = [gather(o, pts) for o in outs]
     # the inputs on the device are the generator's (checked on a few boxes)
@@ -150,7 +150,7 @@ def test_tracer_advection_full_size_sampled():
     j3d.tracer_advection(*arrs, niter)
     torch.cuda.synchronize()
     res = arrs[0] if niter % 2 == 0 else arrs[1]
-    seams = ((1, 62, 63, 1024), (1, 16, 17, 512), (1, 128, 129, 512))
+    seams = ((1, 64, 65, 1024), (1, 16, 17, 512), (1, 128, 129, 512))
     pts = sample_points((nx, ny, nz), 40, seams, 32)
     got = gather(res, pts)
     R = niter + 1  # the result at a point depends on cells within niter steps
