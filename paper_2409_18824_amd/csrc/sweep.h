@@ -26,7 +26,7 @@
 //
 // Arithmetic order is fixed and the library is built with contraction off:
 //   S  = ((((u[i-1] + u[i+1]) + u[j-1]) + u[j+1]) + u[k-1]) + u[k+1]
-//   u' = (S + h2 * f) / 6                  (true IEEE division)
+//   u' = (S + h2 * f) / 6                  (the IEEE quotient, see div6)
 //   r  = f - (6 * u - S) / h2              (FP64)
 // A tile's sum of r^2 is reduced by a fixed butterfly within the wavefront
 // and in wave order across wavefronts into one fixed slot per tile.
@@ -123,6 +123,29 @@ __device__ __forceinline__ double lane_value(double v, int src) {
   r.x = __builtin_amdgcn_readlane(a.x, src);
   r.y = __builtin_amdgcn_readlane(a.y, src);
   return __builtin_bit_cast(double, r);
+}
+
+// x / 6 rounded to nearest, without a division instruction, by the method
+// of Brisebarre, Muller and Raina for a divisor known in advance (IEEE
+// Trans. Computers 53(8), 2004): with zh = RN(1/6) and zl = RN(1/6 - zh),
+// q = RN(x * zh + RN(x * zl)) in one fused multiply-add.  It equals the IEEE
+// quotient x / 6 for every x whose quotient is normal: x = m 2^e with an
+// integer m makes x / 6 = (m / 3) 2^(e-1) a multiple of a third of its own
+// ulp, so it lies at least ulp / 6 from every rounding boundary, while the
+// fused value differs from x / 6 by less than 2^-20 ulp.  Below that range
+// (|x| < 2^-1000 in FP64, 2^-100 in FP32, where the quotient may be
+// subnormal and a tie possible) the lane divides.  Infinities, NaNs and
+// signed zeros come out as the division gives them.  The library is
+// otherwise built without contraction; this fma is explicit.
+__device__ __forceinline__ double div6(double x) {
+  const double q = __builtin_fma(x, 0x1.5555555555555p-3, x * 0x1.5555555555555p-57);
+  if (__builtin_fabs(x) < 0x1p-1000) return x / 6.0;
+  return q;
+}
+__device__ __forceinline__ float div6(float x) {
+  const float q = __builtin_fmaf(x, 0x1.555556p-3f, x * -0x1.555556p-28f);
+  if (__builtin_fabsf(x) < 0x1p-100f) return x / 6.0f;
+  return q;
 }
 
 // Rows per thread encoded in the variant bits 2 and 16.
@@ -301,7 +324,7 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
           if ((FL & F_R32) && act[r]) put<float, NT>(pr + dj[r] * g.sr_y, static_cast<float>(res));
         }
         if (FL & (F_WRITE | F_LAST)) {
-          const T v = (s + h2 * fc[r]) / T(6);
+          const T v = div6(s + h2 * fc[r]);
           if ((FL & F_WRITE) && act[r]) put<T, NT>(po + dj[r] * g.so_y, v);
           if ((FL & F_LAST) && act[r]) {
             double* q = p64 + dj[r] * g.s64_y;

@@ -147,7 +147,7 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
       s = s + nyp;
       s = s + u0m[r];
       s = s + u0p[r];
-      u1[r] = pt_in ? (s + h2 * fk[r]) / T(6) : u0c[r];
+      u1[r] = pt_in ? div6(s + h2 * fk[r]) : u0c[r];
       if (FL & F_RES) {
         const double res = static_cast<double>(fk[r]) -
                            (6.0 * static_cast<double>(u0c[r]) - static_cast<double>(s)) / g.h2;
@@ -174,7 +174,7 @@ __device__ __forceinline__ void sweep2_tile(const GridArgs& g, int t, double* __
           s1 = s1 + yp;
           s1 = s1 + u1m2[r];
           s1 = s1 + u1[r];
-          const T u2 = (s1 + h2 * fprev[r]) / T(6);
+          const T u2 = div6(s1 + h2 * fprev[r]);
           if (col_in[r]) {
             if (FL & F_LAST) {
               double* q = u64 + co[r] + g.s64_z * (k - 1);
