@@ -494,7 +494,8 @@ def advect_source_hash() -> str:
 
 
 def advect_tile() -> str:
-    return os.environ.get("J3D_ADVECT_TILE", "default")
+    return "%s/%s/%s" % (os.environ.get("J3D_ADVECT_TILE", "default"), os.environ.get("J3D_TRACER2_TILE", "default"),
+                         os.environ.get("J3D_TRACER_STEPS_PER_PASS", "default"))
 
 
 def advect_traffic(name: str):
@@ -614,13 +615,20 @@ def run_tra_adv(args):
     times = _event_times(call, args.steps)
     med = float(np.median(times))
     pts = nx * ny * nz
-    alg = 48 * pts  # per step: read t, u, v, w, r and write t once per point
+    # the library's schedule: two steps per launch (one pass over memory),
+    # unless J3D_TRACER_STEPS_PER_PASS=1; S = 20 needs no single-step launch
+    per_launch = 1 if os.environ.get("J3D_TRACER_STEPS_PER_PASS") == "1" else 2
+    launches = S // per_launch
+    alg = 48 * pts  # per launch: read t, u, v, w, r and write t once per point
     out = _base(args, "point updates per second (tracer advection, 6 fields, %dx%dx%d, %d steps)" % (nx, ny, nz, S),
                 round(pts * S / med / 1e9, 2), "GLUP/s", round(med * 1e3, 3), "f64",
                 "tra-adv-%dx%dx%d-%dsteps" % (nx, ny, nz, S),
-                extra={"tile": advect_tile(), "algorithmic_bytes_per_launch": alg, "launches_per_step": S})
+                extra={"tile": advect_tile(), "steps_per_launch": per_launch, "algorithmic_bytes_per_launch": alg,
+                       "launches_per_step": launches,
+                       "single_step_equivalent_gbs": round(48 * pts * S / med / 1e9, 1)})
     del arrs
-    out["roofline"] = _advect_roofline(alg, med / S, advect_traffic("tracer_advection"), len(times) * S, args)
+    out["roofline"] = _advect_roofline(alg, med / launches, advect_traffic("tracer_advection"),
+                                       len(times) * launches, args)
     if not args.no_cpu_baseline:
         import oracle
 

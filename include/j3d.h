@@ -235,6 +235,8 @@ int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_array* w,
  * are the transports through the lower domain faces.  Steps alternate
  * t_a -> t_b -> t_a ...: the result is in t_a when niter is even, else in
  * t_b; the interiors of both are written (for niter >= 2).  niter >= 0.
+ * Steps run two per pass over memory where the parity allows (each point of
+ * either step has exactly the arithmetic above).
  * t_a and t_b may not overlap each other or u, v, w, r.  Asynchronous on
  * `stream`.  Errors: J3D_EINVAL, J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
  */

@@ -25,6 +25,23 @@ AdvectCfg advect_cfg(bool tracer) {
   return c;
 }
 
+// Two-step tracer pass: 4 rows per thread, 64 planes, nontemporal stores.
+// J3D_TRACER2_TILE="ry,planes,nt" overrides it; J3D_TRACER_STEPS_PER_PASS=1
+// runs every step as its own pass.
+AdvectCfg tracer2_cfg() {
+  AdvectCfg c{4, 64, 1};
+  if (const char* e = std::getenv("J3D_TRACER2_TILE")) {
+    AdvectCfg t{0, 0, 0};
+    if (std::sscanf(e, "%d,%d,%d", &t.ry, &t.planes, &t.nt) == 3 && tracer2_cfg_supported(t)) c = t;
+  }
+  return c;
+}
+
+bool tracer_two_steps_per_pass() {
+  const char* e = std::getenv("J3D_TRACER_STEPS_PER_PASS");
+  return !(e != nullptr && std::atoi(e) == 1);
+}
+
 int check_spacing(double d, const char* name) {
   if (!(std::isfinite(d) && d > 0.0)) return fail(J3D_EINVAL, "%s must be finite and > 0", name);
   return J3D_OK;
@@ -95,15 +112,30 @@ extern "C" int tracer_advection(const j3d_array* t_a, const j3d_array* t_b, cons
   a.nz = f[0].nz();
   a.siy = a.soy = (int)f[0].sy;
   a.siz = a.soz = f[0].sz;
-  const AdvectCfg c = advect_cfg(true);
+  const AdvectCfg c1 = advect_cfg(true);
+  const AdvectCfg c2 = tracer2_cfg();
   hipStream_t st = static_cast<hipStream_t>(stream);
   double* ta = reinterpret_cast<double*>(f[0].base);
   double* tb = reinterpret_cast<double*>(f[1].base);
-  for (int64_t s = 0; s < niter; ++s) {
-    const bool from_a = (s % 2) == 0;
+  // n2 launches of two steps, then n1 of one; every launch swaps the arrays,
+  // so the number of launches keeps the parity of niter (one two-step launch
+  // is split in two when it would not) and the result is in t_a exactly when
+  // niter is even.
+  int64_t n2 = tracer_two_steps_per_pass() ? niter / 2 : 0;
+  int64_t n1 = niter - 2 * n2;
+  if (((n2 + n1) & 1) != (niter & 1)) {
+    n2 -= 1;
+    n1 += 2;
+  }
+  bool from_a = true;
+  for (int64_t q = 0; q < n2 + n1; ++q) {
     a.t = from_a ? ta : tb;
     a.out[0] = from_a ? tb : ta;
-    J3D_HIP(launch_tracer_advect(a, c, st));
+    if (q < n2)
+      J3D_HIP(launch_tracer2_advect(a, c2, st));
+    else
+      J3D_HIP(launch_tracer_advect(a, c1, st));
+    from_a = !from_a;
   }
   return J3D_OK;
 }

@@ -255,6 +255,151 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
   }
 }
 
+// Two tracer steps in one pass: t2 = S(S(t0)), u, v, w, r read once for
+// both.  Lane l of a wavefront is column x0 - 2 + l (tiles 60 wide, x0 =
+// 1 + 60 tx, overlapping by four columns): the intermediate t1 is valid on
+// lanes 1..62, t2 on lanes 2..61, which are stored.  A thread's RY output
+// rows need t1 on one row more on each side and t0 on two; t1 at a halo cell
+// (outside the interior in any axis) is t0 there, the fixed boundary value.
+// Marching through z, step k computes t1 at plane k and t2 at plane k-1.
+// Each point of t1 and t2 has exactly the arithmetic of one step.
+constexpr int kOut2 = WAVE - 4;  // outputs per wavefront along x
+
+template <int RY, bool NT>
+__global__ void __launch_bounds__(WAVE * kWaves) k_tracer2_advect(AdvArgs a) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = b % a.tiles_x;
+  const int rest = b / a.tiles_x;
+  const int yb = rest % a.yblocks;
+  const int kc = rest / a.yblocks;
+  const int ty = yb * kWaves + (int)(threadIdx.x / WAVE);
+  if (ty >= a.tiles_y) return;  // the whole wavefront leaves together
+  const int x = tx * kOut2 - 1 + lane;  // x0 - 2 + lane
+  const int xc = min(max(x, 0), a.nx + 1);
+  const bool x_in = x >= 1 && x <= a.nx;
+  const bool lane_out = lane >= 2 && lane <= kOut2 + 1 && x_in;
+  const int j0 = 1 + ty * RY;  // first output row
+  const int k0 = 1 + kc * a.planes;
+  const int k1 = min(k0 + a.planes, a.nz + 1);
+  // row i of the t0 window is j0 - 2 + i (i = 0 .. RY+3); stage-1 row i is
+  // j0 - 1 + i (i = 0 .. RY+1), whose v(j-1), v(j) are v rows i, i+1
+  int roff[RY + 4];
+  bool row_in[RY + 2];
+#pragma unroll
+  for (int i = 0; i < RY + 4; ++i) roff[i] = xc + a.siy * min(max(j0 - 2 + i, 0), a.ny + 1);
+#pragma unroll
+  for (int i = 0; i < RY + 2; ++i) row_in[i] = j0 - 1 + i >= 1 && j0 - 1 + i <= a.ny;
+  const double* __restrict__ pt = a.t;
+  const double* __restrict__ pu = a.in[0];
+  const double* __restrict__ pv = a.in[1];
+  const double* __restrict__ pw = a.in[2];
+  const double* __restrict__ pr = a.in[3];
+  double T0[3][RY + 4];            // t0 at planes k-1, k, k+1
+  double T1[3][RY + 2];            // t1 at planes k-2, k-1, k
+  double W[3][RY + 2];             // w at planes k-2, k-1, k
+  double U[2][RY + 2], R[2][RY + 2], V[2][RY + 3];  // planes k-1, k
+  auto zoff = [&](int k) { return (long long)min(max(k, 0), a.nz + 1) * a.siz; };
+  {
+    const long long za = zoff(k0 - 2), zb = zoff(k0 - 1);
+#pragma unroll
+    for (int i = 0; i < RY + 4; ++i) {
+      T0[0][i] = pt[za + roff[i]];
+      T0[1][i] = pt[zb + roff[i]];
+    }
+    // w at plane k0-2 goes to the newest slot: the first shift moves it to
+    // plane k-1 of step k0-1
+#pragma unroll
+    for (int i = 0; i < RY + 2; ++i) {
+      W[2][i] = pw[za + roff[i + 1]];
+      W[1][i] = 0.0;
+      T1[1][i] = 0.0;
+      T1[2][i] = 0.0;
+      U[1][i] = R[1][i] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RY + 3; ++i) V[1][i] = 0.0;
+  }
+  for (int k = k0 - 1; k <= k1; ++k) {
+    // shift the windows: plane k becomes the newest
+#pragma unroll
+    for (int i = 0; i < RY + 2; ++i) {
+      T1[0][i] = T1[1][i];
+      T1[1][i] = T1[2][i];
+      W[0][i] = W[1][i];
+      W[1][i] = W[2][i];
+      U[0][i] = U[1][i];
+      R[0][i] = R[1][i];
+    }
+#pragma unroll
+    for (int i = 0; i < RY + 3; ++i) V[0][i] = V[1][i];
+    const long long zk = zoff(k), zn = zoff(k + 1);
+#pragma unroll
+    for (int i = 0; i < RY + 4; ++i) T0[2][i] = pt[zn + roff[i]];
+#pragma unroll
+    for (int i = 0; i < RY + 2; ++i) {
+      U[1][i] = pu[zk + roff[i + 1]];
+      W[2][i] = pw[zk + roff[i + 1]];
+      R[1][i] = pr[zk + roff[i + 1]];
+    }
+#pragma unroll
+    for (int i = 0; i < RY + 3; ++i) V[1][i] = pv[zk + roff[i]];
+    // stage 1: t1 at plane k, stage-1 rows 0 .. RY+1
+    const bool k_in = k >= 1 && k <= a.nz;
+#pragma unroll
+    for (int i = 0; i < RY + 2; ++i) {
+      const double tc = T0[1][i + 1];
+      const double tl = from_left(tc), tr = from_right(tc);
+      const double fe = upwind(U[1][i], tc, tr);
+      const double fw = upwind(from_left(U[1][i]), tl, tc);
+      const double fn = upwind(V[1][i + 1], tc, T0[1][i + 2]);
+      const double fs = upwind(V[1][i], T0[1][i], tc);
+      const double ft = upwind(W[2][i], tc, T0[2][i + 1]);
+      const double fb = upwind(W[1][i], T0[0][i + 1], tc);
+      const double div = ((fe - fw) + (fn - fs)) + (ft - fb);
+      const double t1 = tc - R[1][i] * div;
+      T1[2][i] = (x_in && row_in[i] && k_in) ? t1 : tc;
+    }
+    // stage 2: t2 at plane k-1, output rows (stage-1 rows 1 .. RY)
+    if (k - 1 >= k0) {
+      const long long zo = (long long)(k - 1) * a.soz;
+#pragma unroll
+      for (int i = 1; i <= RY; ++i) {
+        const double tc = T1[1][i];
+        const double tl = from_left(tc), tr = from_right(tc);
+        const double fe = upwind(U[0][i], tc, tr);
+        const double fw = upwind(from_left(U[0][i]), tl, tc);
+        const double fn = upwind(V[0][i + 1], tc, T1[1][i + 1]);
+        const double fs = upwind(V[0][i], T1[1][i - 1], tc);
+        const double ft = upwind(W[1][i], tc, T1[2][i]);
+        const double fb = upwind(W[0][i], T1[0][i], tc);
+        const double div = ((fe - fw) + (fn - fs)) + (ft - fb);
+        const double t2 = tc - R[0][i] * div;
+        const int j = j0 - 1 + i;
+        if (lane_out && j <= a.ny) put<double, NT>(a.out[0] + (zo + x + (long long)a.soy * j), t2);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RY + 4; ++i) {
+      T0[0][i] = T0[1][i];
+      T0[1][i] = T0[2][i];
+    }
+  }
+}
+
+template <typename Kernel>
+hipError_t go2(Kernel kern, AdvArgs a, int ry, hipStream_t st) {
+  a.tiles_x = (a.nx + kOut2 - 1) / kOut2;
+  a.tiles_y = (a.ny + ry - 1) / ry;
+  a.yblocks = (a.tiles_y + kWaves - 1) / kWaves;
+  const int zchunks = (a.nz + a.planes - 1) / a.planes;
+  const long long blocks = (long long)a.tiles_x * a.yblocks * zchunks;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks >= (1LL << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WAVE * kWaves), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename Kernel>
 hipError_t go(Kernel kern, AdvArgs a, int ry, hipStream_t st) {
   a.tiles_x = (a.nx + WAVE - 1) / WAVE;
@@ -299,6 +444,22 @@ hipError_t launch_tracer_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_
     case 9: return go(k_tracer_advect<4, true>, g, 4, st);
     case 16: return go(k_tracer_advect<8, false>, g, 8, st);
     default: return go(k_tracer_advect<8, true>, g, 8, st);
+  }
+}
+
+bool tracer2_cfg_supported(const AdvectCfg& c) {
+  return (c.ry == 2 || c.ry == 4) && c.planes >= 1 && (c.nt == 0 || c.nt == 1);
+}
+
+hipError_t launch_tracer2_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st) {
+  if (!tracer2_cfg_supported(c)) return hipErrorInvalidValue;
+  AdvArgs g = a;
+  g.planes = c.planes;
+  switch (c.ry * 2 + c.nt) {
+    case 4: return go2(k_tracer2_advect<2, false>, g, 2, st);
+    case 5: return go2(k_tracer2_advect<2, true>, g, 2, st);
+    case 8: return go2(k_tracer2_advect<4, false>, g, 4, st);
+    default: return go2(k_tracer2_advect<4, true>, g, 4, st);
   }
 }
 

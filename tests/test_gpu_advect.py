@@ -64,19 +64,26 @@ def test_pw_advection_uniform_flow_is_zero():
         assert np.all(o.to_numpy()[1:-1, 1:-1, 1:-1] == 0.0)
 
 
-@pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("tile", TILES)
-def test_tracer_advection_parity(tile, shape, monkeypatch):
+# two-step tracer passes: rows per thread 2 or 4 (x tiles 60 wide)
+TILES2 = ["2,7,0", "4,64,1", "2,64,1", "4,5,0"]
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(60, 8, 4), (61, 9, 70), (121, 3, 2)])
+@pytest.mark.parametrize("tile,tile2,steps", [(t, TILES2[n % 4], 1 + n % 2) for n, t in enumerate(TILES)]
+                         + [(TILES[1], t2, 2) for t2 in TILES2])
+def test_tracer_advection_parity(tile, tile2, steps, shape, monkeypatch):
     monkeypatch.setenv("J3D_ADVECT_TILE", tile)
+    monkeypatch.setenv("J3D_TRACER2_TILE", tile2)
+    monkeypatch.setenv("J3D_TRACER_STEPS_PER_PASS", str(steps))
     nx, ny, nz = shape
-    say("tracer_advection", tile, shape)
+    say("tracer_advection", tile, tile2, steps, shape)
     t = rand_padded(nx, ny, nz, 22, synth.STREAM_TRACER, 0.0, 1.0)
     u, v, w = (rand_padded(nx, ny, nz, 22, s, -0.1, 0.1) for s in (6, 7, 8))
     u[::3, ::2, ::5] = 0.0  # zero transports take neither branch
     v[1::4, ::3, ::2] = -0.0
     r = rand_padded(nx, ny, nz, 22, synth.STREAM_RVOL, 0.5, 1.5)
     fields = [j3d.FArray.from_numpy(a) for a in (u, v, w, r)]
-    for niter in (0, 1, 2, 3):
+    for niter in (0, 1, 2, 3, 4, 5):
         want = oracle.tracer_advection(t, u, v, w, r, niter)
         da, db = j3d.FArray.from_numpy(t), j3d.FArray.from_numpy(t)
         j3d.tracer_advection(da, db, *fields, niter)
@@ -150,8 +157,8 @@ def test_tracer_advection_full_size_sampled():
     j3d.tracer_advection(*arrs, niter)
     torch.cuda.synchronize()
     res = arrs[0] if niter % 2 == 0 else arrs[1]
-    seams = ((1, 64, 65, 1024), (1, 16, 17, 512), (1, 128, 129, 512))
-    pts = sample_points((nx, ny, nz), 40, seams, 32)
+    seams = ((1, 60, 61, 64, 65, 1020, 1021, 1024), (1, 16, 17, 512), (1, 64, 65, 512))
+    pts = sample_points((nx, ny, nz), 20, seams, 32)
     got = gather(res, pts)
     R = niter + 1  # the result at a point depends on cells within niter steps
     bad = 0
