@@ -75,7 +75,8 @@ def test_sweep_fp64_parity(shape, tune):
 
 TUNES2 = [(1, 32, 20, 0, 1, 1), (4, 16, 4, 0, 2, 1), (2, 16, 20, 0, 1, 1), (8, 8, 6, 1, 0, 1), (4, 8, 0, 0, 0), (8, 32, 4, 0, 1), (4, 16, 4, 0, 2), (4, 1, 0, 1, 1), (8, 3, 0, 1, 2),
           (2, 128, 2, 0, 0), (1, 16, 20, 0, 1), (4, 8, 16, 1, 2), (8, 16, 6, 0, 0), (2, 32, 20, 0, 2)]
-SHAPES2 = [(1, 1, 1), (3, 4, 5), (60, 6, 9), (61, 7, 10), (62, 6, 9), (121, 30, 17), (17, 45, 64), (200, 14, 3)]
+SHAPES2 = [(1, 1, 1), (3, 4, 5), (60, 6, 9), (61, 7, 10), (62, 6, 9), (121, 30, 17), (17, 45, 64), (200, 14, 3),
+           (64, 5, 7), (65, 9, 4), (129, 33, 18)]
 
 
 @pytest.mark.parametrize("shape", SHAPES2)
@@ -154,7 +155,7 @@ TUNES2_F32 = [(4, 32, 20, 0, 1, 1), (1, 16, 20, 0, 2, 1), (2, 8, 6, 1, 0, 1), (4
               (8, 64, 6, 0, 2, 1), (1, 8, 20, 1, 1, 1)]
 
 
-@pytest.mark.parametrize("shape", [(70, 13, 21), (1, 1, 1), (130, 40, 9), (62, 14, 33)])
+@pytest.mark.parametrize("shape", [(70, 13, 21), (1, 1, 1), (130, 40, 9), (62, 14, 33), (64, 7, 5), (129, 10, 6)])
 @pytest.mark.parametrize("tune", TUNES2_F32)
 def test_sweep2_fp32_equals_two_fp32_sweeps(shape, tune):
     nx, ny, nz = shape
