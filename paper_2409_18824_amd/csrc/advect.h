@@ -34,7 +34,7 @@ bool advect_cfg_supported(const AdvectCfg& c);
 hipError_t launch_pw_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st);
 hipError_t launch_tracer_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st);
 // Two tracer steps per launch (t = in iterate, out[0] = iterate two steps
-// later); rows per thread 2 or 4.
+// later); rows per thread 2, 4 or 6.
 bool tracer2_cfg_supported(const AdvectCfg& c);
 hipError_t launch_tracer2_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st);
 

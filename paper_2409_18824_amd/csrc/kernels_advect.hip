@@ -258,129 +258,149 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer_advect(AdvArgs a) {
 // Two tracer steps in one pass: t2 = S(S(t0)), u, v, w, r read once for
 // both.  Lane l of a wavefront is column x0 - 2 + l (tiles 60 wide, x0 =
 // 1 + 60 tx, overlapping by four columns): the intermediate t1 is valid on
-// lanes 1..62, t2 on lanes 2..61, which are stored.  A thread's RY output
-// rows need t1 on one row more on each side and t0 on two; t1 at a halo cell
-// (outside the interior in any axis) is t0 there, the fixed boundary value.
-// Marching through z, step k computes t1 at plane k and t2 at plane k-1.
-// Each point of t1 and t2 has exactly the arithmetic of one step.
+// lanes 1..62, t2 on lanes 2..61, which are stored.  A workgroup of four
+// wavefronts, each owning RY consecutive rows, covers 4 RY rows; the first
+// and last of them form a ring around the 4 RY - 2 output rows (the
+// neighbouring workgroups output them).  Marching through z, step k
+// computes t1 at plane k on every row of the workgroup and t2 at plane k-1
+// on the output rows.  A wavefront loads its own rows of every field, one
+// row of t0 beyond each end of them and one row of v below; the t1 rows just
+// outside its own come from the neighbouring wavefronts through LDS (three
+// plane slots, one barrier per plane).  t1 at a halo cell (outside the
+// interior in any axis) is t0 there, the fixed boundary value.  Each point
+// of t1 and t2 has exactly the arithmetic of one step.
 constexpr int kOut2 = WAVE - 4;  // outputs per wavefront along x
 
 template <int RY, bool NT>
 __global__ void __launch_bounds__(WAVE * kWaves) k_tracer2_advect(AdvArgs a) {
+  constexpr int TR = kWaves * RY;  // workgroup rows
+  constexpr int H = TR - 2;        // output rows
+  __shared__ double edge[3][kWaves][2][WAVE];  // t1: plane slot, wavefront, first/last row
   const int lane = threadIdx.x & (WAVE - 1);
+  const int wy = threadIdx.x / WAVE;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = b % a.tiles_x;
   const int rest = b / a.tiles_x;
-  const int yb = rest % a.yblocks;
-  const int kc = rest / a.yblocks;
-  const int ty = yb * kWaves + (int)(threadIdx.x / WAVE);
-  if (ty >= a.tiles_y) return;  // the whole wavefront leaves together
+  const int ty = rest % a.tiles_y;  // workgroup-uniform
+  const int kc = rest / a.tiles_y;
   const int x = tx * kOut2 - 1 + lane;  // x0 - 2 + lane
   const int xc = min(max(x, 0), a.nx + 1);
   const bool x_in = x >= 1 && x <= a.nx;
   const bool lane_out = lane >= 2 && lane <= kOut2 + 1 && x_in;
-  const int j0 = 1 + ty * RY;  // first output row
+  const int y0 = ty * H + wy * RY;  // row of this wavefront's first own row
   const int k0 = 1 + kc * a.planes;
   const int k1 = min(k0 + a.planes, a.nz + 1);
-  // row i of the t0 window is j0 - 2 + i (i = 0 .. RY+3); stage-1 row i is
-  // j0 - 1 + i (i = 0 .. RY+1), whose v(j-1), v(j) are v rows i, i+1
-  int roff[RY + 4];
-  bool row_in[RY + 2];
+  // t0 window rows i = 0 .. RY+1 are rows y0 - 1 + i (own rows at i = 1..RY);
+  // v rows i = 0 .. RY are rows y0 - 1 + i
+  int roff[RY + 2];
+  bool row_in[RY], row_out[RY];
 #pragma unroll
-  for (int i = 0; i < RY + 4; ++i) roff[i] = xc + a.siy * min(max(j0 - 2 + i, 0), a.ny + 1);
+  for (int i = 0; i < RY + 2; ++i) roff[i] = xc + a.siy * min(max(y0 - 1 + i, 0), a.ny + 1);
 #pragma unroll
-  for (int i = 0; i < RY + 2; ++i) row_in[i] = j0 - 1 + i >= 1 && j0 - 1 + i <= a.ny;
+  for (int r = 0; r < RY; ++r) {
+    const int y = y0 + r;
+    const int br = wy * RY + r;
+    row_in[r] = y >= 1 && y <= a.ny;
+    row_out[r] = lane_out && br >= 1 && br <= H && y <= a.ny;
+  }
   const double* __restrict__ pt = a.t;
   const double* __restrict__ pu = a.in[0];
   const double* __restrict__ pv = a.in[1];
   const double* __restrict__ pw = a.in[2];
   const double* __restrict__ pr = a.in[3];
-  double T0[3][RY + 4];            // t0 at planes k-1, k, k+1
-  double T1[3][RY + 2];            // t1 at planes k-2, k-1, k
-  double W[3][RY + 2];             // w at planes k-2, k-1, k
-  double U[2][RY + 2], R[2][RY + 2], V[2][RY + 3];  // planes k-1, k
+  double T0[3][RY + 2];            // t0 at planes k-1, k, k+1
+  double T1[3][RY];                // t1 at planes k-2, k-1, k (own rows)
+  double W[3][RY];                 // w at planes k-2, k-1, k
+  double U[2][RY], R[2][RY], V[2][RY + 1];  // planes k-1, k
   auto zoff = [&](int k) { return (long long)min(max(k, 0), a.nz + 1) * a.siz; };
   {
     const long long za = zoff(k0 - 2), zb = zoff(k0 - 1);
 #pragma unroll
-    for (int i = 0; i < RY + 4; ++i) {
+    for (int i = 0; i < RY + 2; ++i) {
       T0[0][i] = pt[za + roff[i]];
       T0[1][i] = pt[zb + roff[i]];
     }
     // w at plane k0-2 goes to the newest slot: the first shift moves it to
     // plane k-1 of step k0-1
 #pragma unroll
-    for (int i = 0; i < RY + 2; ++i) {
-      W[2][i] = pw[za + roff[i + 1]];
-      W[1][i] = 0.0;
-      T1[1][i] = 0.0;
-      T1[2][i] = 0.0;
-      U[1][i] = R[1][i] = 0.0;
+    for (int r = 0; r < RY; ++r) {
+      W[2][r] = pw[za + roff[r + 1]];
+      W[1][r] = 0.0;
+      T1[1][r] = 0.0;
+      T1[2][r] = 0.0;
+      U[1][r] = R[1][r] = 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < RY + 3; ++i) V[1][i] = 0.0;
+    for (int i = 0; i < RY + 1; ++i) V[1][i] = 0.0;
   }
   for (int k = k0 - 1; k <= k1; ++k) {
     // shift the windows: plane k becomes the newest
 #pragma unroll
-    for (int i = 0; i < RY + 2; ++i) {
-      T1[0][i] = T1[1][i];
-      T1[1][i] = T1[2][i];
-      W[0][i] = W[1][i];
-      W[1][i] = W[2][i];
-      U[0][i] = U[1][i];
-      R[0][i] = R[1][i];
+    for (int r = 0; r < RY; ++r) {
+      T1[0][r] = T1[1][r];
+      T1[1][r] = T1[2][r];
+      W[0][r] = W[1][r];
+      W[1][r] = W[2][r];
+      U[0][r] = U[1][r];
+      R[0][r] = R[1][r];
     }
 #pragma unroll
-    for (int i = 0; i < RY + 3; ++i) V[0][i] = V[1][i];
+    for (int i = 0; i < RY + 1; ++i) V[0][i] = V[1][i];
     const long long zk = zoff(k), zn = zoff(k + 1);
 #pragma unroll
-    for (int i = 0; i < RY + 4; ++i) T0[2][i] = pt[zn + roff[i]];
+    for (int i = 0; i < RY + 2; ++i) T0[2][i] = pt[zn + roff[i]];
 #pragma unroll
-    for (int i = 0; i < RY + 2; ++i) {
-      U[1][i] = pu[zk + roff[i + 1]];
-      W[2][i] = pw[zk + roff[i + 1]];
-      R[1][i] = pr[zk + roff[i + 1]];
+    for (int r = 0; r < RY; ++r) {
+      U[1][r] = pu[zk + roff[r + 1]];
+      W[2][r] = pw[zk + roff[r + 1]];
+      R[1][r] = pr[zk + roff[r + 1]];
     }
 #pragma unroll
-    for (int i = 0; i < RY + 3; ++i) V[1][i] = pv[zk + roff[i]];
-    // stage 1: t1 at plane k, stage-1 rows 0 .. RY+1
+    for (int i = 0; i < RY + 1; ++i) V[1][i] = pv[zk + roff[i]];
+    // stage 1: t1 at plane k on the own rows
     const bool k_in = k >= 1 && k <= a.nz;
 #pragma unroll
-    for (int i = 0; i < RY + 2; ++i) {
-      const double tc = T0[1][i + 1];
+    for (int r = 0; r < RY; ++r) {
+      const double tc = T0[1][r + 1];
       const double tl = from_left(tc), tr = from_right(tc);
-      const double fe = upwind(U[1][i], tc, tr);
-      const double fw = upwind(from_left(U[1][i]), tl, tc);
-      const double fn = upwind(V[1][i + 1], tc, T0[1][i + 2]);
-      const double fs = upwind(V[1][i], T0[1][i], tc);
-      const double ft = upwind(W[2][i], tc, T0[2][i + 1]);
-      const double fb = upwind(W[1][i], T0[0][i + 1], tc);
+      const double fe = upwind(U[1][r], tc, tr);
+      const double fw = upwind(from_left(U[1][r]), tl, tc);
+      const double fn = upwind(V[1][r + 1], tc, T0[1][r + 2]);
+      const double fs = upwind(V[1][r], T0[1][r], tc);
+      const double ft = upwind(W[2][r], tc, T0[2][r + 1]);
+      const double fb = upwind(W[1][r], T0[0][r + 1], tc);
       const double div = ((fe - fw) + (fn - fs)) + (ft - fb);
-      const double t1 = tc - R[1][i] * div;
-      T1[2][i] = (x_in && row_in[i] && k_in) ? t1 : tc;
+      const double t1 = tc - R[1][r] * div;
+      T1[2][r] = (x_in && row_in[r] && k_in) ? t1 : tc;
     }
-    // stage 2: t2 at plane k-1, output rows (stage-1 rows 1 .. RY)
+    edge[k % 3][wy][0][lane] = T1[2][0];
+    edge[k % 3][wy][1][lane] = T1[2][RY - 1];
+    __syncthreads();
+    // stage 2: t2 at plane k-1 on the output rows
     if (k - 1 >= k0) {
+      const int sl = (k + 2) % 3;  // slot of plane k-1
+      const double below = wy > 0 ? edge[sl][wy - 1][1][lane] : 0.0;
+      const double above = wy < kWaves - 1 ? edge[sl][wy + 1][0][lane] : 0.0;
       const long long zo = (long long)(k - 1) * a.soz;
 #pragma unroll
-      for (int i = 1; i <= RY; ++i) {
-        const double tc = T1[1][i];
+      for (int r = 0; r < RY; ++r) {
+        const double tc = T1[1][r];
         const double tl = from_left(tc), tr = from_right(tc);
-        const double fe = upwind(U[0][i], tc, tr);
-        const double fw = upwind(from_left(U[0][i]), tl, tc);
-        const double fn = upwind(V[0][i + 1], tc, T1[1][i + 1]);
-        const double fs = upwind(V[0][i], T1[1][i - 1], tc);
-        const double ft = upwind(W[1][i], tc, T1[2][i]);
-        const double fb = upwind(W[0][i], T1[0][i], tc);
+        const double ts = r == 0 ? below : T1[1][r - 1];
+        const double tn = r == RY - 1 ? above : T1[1][r + 1];
+        const double fe = upwind(U[0][r], tc, tr);
+        const double fw = upwind(from_left(U[0][r]), tl, tc);
+        const double fn = upwind(V[0][r + 1], tc, tn);
+        const double fs = upwind(V[0][r], ts, tc);
+        const double ft = upwind(W[1][r], tc, T1[2][r]);
+        const double fb = upwind(W[0][r], T1[0][r], tc);
         const double div = ((fe - fw) + (fn - fs)) + (ft - fb);
-        const double t2 = tc - R[0][i] * div;
-        const int j = j0 - 1 + i;
-        if (lane_out && j <= a.ny) put<double, NT>(a.out[0] + (zo + x + (long long)a.soy * j), t2);
+        const double t2 = tc - R[0][r] * div;
+        if (row_out[r]) put<double, NT>(a.out[0] + (zo + x + (long long)a.soy * (y0 + r)), t2);
       }
     }
 #pragma unroll
-    for (int i = 0; i < RY + 4; ++i) {
+    for (int i = 0; i < RY + 2; ++i) {
       T0[0][i] = T0[1][i];
       T0[1][i] = T0[2][i];
     }
@@ -389,11 +409,12 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_tracer2_advect(AdvArgs a) {
 
 template <typename Kernel>
 hipError_t go2(Kernel kern, AdvArgs a, int ry, hipStream_t st) {
+  const int h = kWaves * ry - 2;  // output rows per workgroup
   a.tiles_x = (a.nx + kOut2 - 1) / kOut2;
-  a.tiles_y = (a.ny + ry - 1) / ry;
-  a.yblocks = (a.tiles_y + kWaves - 1) / kWaves;
+  a.tiles_y = (a.ny + h - 1) / h;
+  a.yblocks = a.tiles_y;
   const int zchunks = (a.nz + a.planes - 1) / a.planes;
-  const long long blocks = (long long)a.tiles_x * a.yblocks * zchunks;
+  const long long blocks = (long long)a.tiles_x * a.tiles_y * zchunks;
   if (blocks <= 0) return hipSuccess;
   if (blocks >= (1LL << 31)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(WAVE * kWaves), 0, st, a);
@@ -448,7 +469,7 @@ hipError_t launch_tracer_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_
 }
 
 bool tracer2_cfg_supported(const AdvectCfg& c) {
-  return (c.ry == 2 || c.ry == 4) && c.planes >= 1 && (c.nt == 0 || c.nt == 1);
+  return (c.ry == 2 || c.ry == 4 || c.ry == 6) && c.planes >= 1 && (c.nt == 0 || c.nt == 1);
 }
 
 hipError_t launch_tracer2_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st) {
@@ -459,7 +480,9 @@ hipError_t launch_tracer2_advect(const AdvArgs& a, const AdvectCfg& c, hipStream
     case 4: return go2(k_tracer2_advect<2, false>, g, 2, st);
     case 5: return go2(k_tracer2_advect<2, true>, g, 2, st);
     case 8: return go2(k_tracer2_advect<4, false>, g, 4, st);
-    default: return go2(k_tracer2_advect<4, true>, g, 4, st);
+    case 9: return go2(k_tracer2_advect<4, true>, g, 4, st);
+    case 12: return go2(k_tracer2_advect<6, false>, g, 6, st);
+    default: return go2(k_tracer2_advect<6, true>, g, 6, st);
   }
 }
 

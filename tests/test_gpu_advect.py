@@ -64,12 +64,14 @@ def test_pw_advection_uniform_flow_is_zero():
         assert np.all(o.to_numpy()[1:-1, 1:-1, 1:-1] == 0.0)
 
 
-# two-step tracer passes: rows per thread 2 or 4 (x tiles 60 wide)
-TILES2 = ["2,7,0", "4,64,1", "2,64,1", "4,5,0"]
+# two-step tracer passes: rows per thread 2, 4 or 6 (x tiles 60 wide,
+# workgroups of 4 x rows-per-thread rows, the outer two a ring)
+TILES2 = ["2,7,0", "4,64,1", "6,64,1", "4,5,0", "6,3,0", "2,64,1"]
 
 
-@pytest.mark.parametrize("shape", SHAPES + [(60, 8, 4), (61, 9, 70), (121, 3, 2)])
-@pytest.mark.parametrize("tile,tile2,steps", [(t, TILES2[n % 4], 1 + n % 2) for n, t in enumerate(TILES)]
+@pytest.mark.parametrize("shape", SHAPES + [(60, 8, 4), (61, 9, 70), (121, 3, 2), (64, 22, 5), (65, 23, 4),
+                                            (60, 45, 3), (17, 14, 9)])
+@pytest.mark.parametrize("tile,tile2,steps", [(t, TILES2[n % len(TILES2)], 1 + n % 2) for n, t in enumerate(TILES)]
                          + [(TILES[1], t2, 2) for t2 in TILES2])
 def test_tracer_advection_parity(tile, tile2, steps, shape, monkeypatch):
     monkeypatch.setenv("J3D_ADVECT_TILE", tile)
@@ -174,3 +176,35 @@ def test_tracer_advection_full_size_sampled():
     assert bad == 0
     del arrs, res
     torch.cuda.empty_cache()
+
+
+def test_non_finite_inputs_follow_the_oracle(monkeypatch):
+    """NaN and infinity propagate (or not) exactly as the definitions give:
+    an upwind flux with a NaN transport takes neither branch and is zero, a
+    NaN tracer or velocity value spreads to the stencil's points."""
+    nx, ny, nz = 70, 9, 6
+    u, v, w = (rand_padded(nx, ny, nz, 23, s) for s in (6, 7, 8))
+    u[3, 4, 5] = np.nan
+    v[2, 2, 60] = np.inf
+    w[4, 7, 1] = -np.inf
+    want = oracle.pw_advection(u, v, w, 0.5, 0.25, 0.125)
+    ins = [j3d.FArray.from_numpy(a) for a in (u, v, w)]
+    outs = [j3d.FArray.empty(nx, ny, nz) for _ in range(3)]
+    j3d.pw_advection(*ins, *outs, 0.5, 0.25, 0.125)
+    torch.cuda.synchronize()
+    for o, wt in zip(outs, want):
+        g = o.to_numpy()[1:-1, 1:-1, 1:-1]
+        assert np.array_equal(g, wt[1:-1, 1:-1, 1:-1], equal_nan=True)
+        assert not np.isfinite(g).all()
+    t = rand_padded(nx, ny, nz, 24, synth.STREAM_TRACER, 0.0, 1.0)
+    t[3, 3, 30] = np.nan
+    q = [0.1 * a for a in (u, v, w)]
+    q[0][2, 5, 10] = np.nan  # a NaN transport gives a zero flux
+    r = rand_padded(nx, ny, nz, 24, synth.STREAM_RVOL, 0.5, 1.5)
+    want = oracle.tracer_advection(t, *q, r, 4)
+    for steps in ("1", "2"):
+        monkeypatch.setenv("J3D_TRACER_STEPS_PER_PASS", steps)
+        da, db = j3d.FArray.from_numpy(t), j3d.FArray.from_numpy(t)
+        j3d.tracer_advection(da, db, *[j3d.FArray.from_numpy(a) for a in q + [r]], 4)
+        torch.cuda.synchronize()
+        assert np.array_equal(da.to_numpy(), want, equal_nan=True), steps
