@@ -146,6 +146,17 @@ int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
                     double h, uint32_t flags, double* resid_out, void* stream);
 
 /*
+ * Three Jacobi sweeps in one pass over memory: u_out = J(J(J(u_in; f, h))),
+ * as jacobi3d_sweep2 with a third sweep (bit-identical to three
+ * jacobi3d_sweep calls).  The two intermediate iterates stay on chip, so the
+ * pass streams u_in and f once and writes u_out once for three sweeps' worth
+ * of updates.  resid_out and flags as in jacobi3d_sweep (the residual of
+ * u_in; FP64 only).
+ */
+int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
+                    double h, uint32_t flags, double* resid_out, void* stream);
+
+/*
  * ||f - A u||_2 over the interior, in FP64 (u and f FP64).  `out` is a
  * device address (or host, with J3D_HOST_RESULT in flags).
  */
@@ -367,11 +378,18 @@ int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* st
  * output columns); variant bits 2, 4, 16 as above, no LDS bit. */
 #define J3D_KIND_F64X2 2
 #define J3D_KIND_F32X2 3
+/* The three-sweep passes of jacobi3d_sweep3 (the FP32 one also runs the
+ * correction sweeps of the mixed solve): one wavefront along x, not
+ * persistent, rows 2, 4 or 8 wavefronts of 2 or 4 rows per thread (variants
+ * 6 and 20) with rows x rows-per-thread between 8 and 32; a block has that
+ * many rows minus 4 output rows and 58 output columns. */
+#define J3D_KIND_F64X3 4
+#define J3D_KIND_F32X3 5
 
 /* Autotune the single-grid pass of this kind and interior shape on
  * library-allocated scratch arrays; the choice is used by jacobi3d_sweep,
- * jacobi3d_sweep2, residual_l2 and poisson_solve for this shape from then
- * on.  Blocks. */
+ * jacobi3d_sweep2, jacobi3d_sweep3, residual_l2 and poisson_solve for this
+ * shape from then on.  Blocks. */
 int j3d_autotune_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
                         void* stream);
 

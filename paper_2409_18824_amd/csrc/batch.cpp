@@ -478,6 +478,18 @@ int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, L
   return rc;
 }
 
+std::vector<TileCfg> sweep3_candidates(int dtype) {
+  std::vector<TileCfg> v;
+  for (int rows : {2, 4, 8})
+    for (int var : {6, 20})
+      for (int planes : {16, 32, 64})
+        for (int order : {0, 1, 2}) {
+          TileCfg c{rows, planes, var, 0, order, 1};
+          if (tile3_cfg_supported(dtype, c)) v.push_back(c);
+        }
+  return v;
+}
+
 std::vector<TileCfg> sweep2_candidates(int dtype) {
   std::vector<TileCfg> v;
   for (int rows : {1, 2, 4, 8})
@@ -702,13 +714,15 @@ extern "C" int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* bes
 
 extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, j3d_tune* best,
                                    void* stream) {
-  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2 && dtype != J3D_KIND_F32X2)
-    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32, J3D_KIND_F64X2 or J3D_KIND_F32X2");
+  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2 && dtype != J3D_KIND_F32X2 &&
+      dtype != J3D_KIND_F64X3 && dtype != J3D_KIND_F32X3)
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or a J3D_KIND_* pass kind");
   if (nx < 1 || ny < 1 || nz < 1) return fail(J3D_EINVAL, "extents must be >= 1");
   if (best == nullptr) return fail(J3D_EINVAL, "best: null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool pair = dtype == J3D_KIND_F64X2 || dtype == J3D_KIND_F32X2;
-  const int et = (dtype == J3D_F32 || dtype == J3D_KIND_F32X2) ? J3D_F32 : J3D_F64;
+  const bool triple = dtype == J3D_KIND_F64X3 || dtype == J3D_KIND_F32X3;
+  const int et = (dtype == J3D_F32 || dtype == J3D_KIND_F32X2 || dtype == J3D_KIND_F32X3) ? J3D_F32 : J3D_F64;
   const int es = et == J3D_F32 ? 4 : 8;
   const int align = 128 / es;
   Field a;
@@ -743,8 +757,15 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
     J3D_HIP(launch_sweep2_one(et, F_WRITE, c, g, nullptr, nullptr, st));
     return J3D_OK;
   };
+  auto launch3 = [&](const TileCfg& c) -> int {
+    GridArgs g = make_args3(&u, &o, &f, nullptr, 0.01, c, 0);
+    J3D_HIP(launch_sweep3_one(et, F_WRITE, c, g, nullptr, nullptr, st));
+    return J3D_OK;
+  };
   TileCfg c{};
-  int rc = pair ? time_list(st, &c, sweep2_candidates(et), launch2) : time_candidates(st, &c, launch);
+  int rc = triple ? time_list(st, &c, sweep3_candidates(et), launch3)
+           : pair ? time_list(st, &c, sweep2_candidates(et), launch2)
+                  : time_candidates(st, &c, launch);
   (void)hipStreamSynchronize(st);
   (void)hipFree(mem);
   if (rc != J3D_OK) return rc;
@@ -761,10 +782,13 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
 extern "C" int j3d_tune_set_single(int32_t dtype, int32_t nx, int32_t ny, int32_t nz, const j3d_tune* t) {
   if (t == nullptr) return fail(J3D_EINVAL, "tune: null pointer");
   TileCfg c{t->rows, t->planes, t->variant, t->persistent, t->order, t->cols};
-  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2 && dtype != J3D_KIND_F32X2)
-    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32, J3D_KIND_F64X2 or J3D_KIND_F32X2");
+  if (dtype != J3D_F64 && dtype != J3D_F32 && dtype != J3D_KIND_F64X2 && dtype != J3D_KIND_F32X2 &&
+      dtype != J3D_KIND_F64X3 && dtype != J3D_KIND_F32X3)
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or a J3D_KIND_* pass kind");
   const bool ok = dtype == J3D_KIND_F64X2   ? tile2_cfg_supported(J3D_F64, c)
                   : dtype == J3D_KIND_F32X2 ? tile2_cfg_supported(J3D_F32, c)
+                  : dtype == J3D_KIND_F64X3 ? tile3_cfg_supported(J3D_F64, c)
+                  : dtype == J3D_KIND_F32X3 ? tile3_cfg_supported(J3D_F32, c)
                                             : tile_cfg_supported(c);
   if (!ok) return fail(J3D_EINVAL, "unsupported tile shape");
   tune_store(single_key(dtype, nx, ny, nz), c);

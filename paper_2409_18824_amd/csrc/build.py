@@ -31,7 +31,8 @@ DEVICE = ["--offload-arch=" + ARCH, "-fhip-fp32-correctly-rounded-divide-sqrt",
 HOST_SOURCES = ["runtime.cpp", "capi.cpp", "solve.cpp", "batch.cpp", "serve.cpp", "jacobi2d.cpp",
                 "advect.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip",
-                  "kernels_sweep2_f32.hip", "kernels_2d.hip", "kernels_advect.hip"]
+                  "kernels_sweep2_f32.hip", "kernels_sweep3.hip", "kernels_sweep3_f32.hip", "kernels_2d.hip",
+                  "kernels_advect.hip"]
 
 
 def _run(cmd):

@@ -48,6 +48,21 @@ TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   return c;
 }
 
+TileCfg default_cfg3(int dtype, int nx, int ny, int nz) {
+  TileCfg c;
+  const int kind = dtype == J3D_F32 ? J3D_KIND_F32X3 : J3D_KIND_F64X3;
+  if (tune_cache_lookup_single(kind, nx, ny, nz, &c) && tile3_cfg_supported(dtype, c)) return c;
+  // measured at 512^3: FP64 4 wavefronts, FP32 8, each 4 rows per thread;
+  // 32 planes, launch order, nontemporal stores
+  c.rows = dtype == J3D_F32 ? 8 : 4;
+  c.planes = 32;
+  c.variant = 20;
+  c.persistent = 0;
+  c.order = 1;
+  c.cols = 1;
+  return c;
+}
+
 TileCfg default_cfg2(int dtype, int nx, int ny, int nz) {
   TileCfg c;
   if (tune_cache_lookup_single(dtype == J3D_F32 ? J3D_KIND_F32X2 : J3D_KIND_F64X2, nx, ny, nz, &c) &&
@@ -113,8 +128,10 @@ int j3d_tune_query_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_
     c = default_cfg(kind, nx, ny, nz);
   else if (kind == J3D_KIND_F64X2 || kind == J3D_KIND_F32X2)
     c = default_cfg2(kind == J3D_KIND_F32X2 ? J3D_F32 : J3D_F64, nx, ny, nz);
+  else if (kind == J3D_KIND_F64X3 || kind == J3D_KIND_F32X3)
+    c = default_cfg3(kind == J3D_KIND_F32X3 ? J3D_F32 : J3D_F64, nx, ny, nz);
   else
-    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32, J3D_KIND_F64X2 or J3D_KIND_F32X2");
+    return fail(J3D_EDTYPE, "kind must be J3D_F64, J3D_F32 or a J3D_KIND_* pass kind");
   out->rows = c.rows;
   out->planes = c.planes;
   out->variant = c.variant;
@@ -203,6 +220,44 @@ int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
   const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
   J3D_HIP(launch_sweep2_one(J3D_F64, F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
+  const bool host = (flags & J3D_HOST_RESULT) != 0;
+  double* dst = host ? &s->ctl->value : resid_out;
+  J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));
+  if (host) {
+    J3D_HIP(hipMemcpyAsync(&s->ctl_host->value, &s->ctl->value, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    *resid_out = s->ctl_host->value;
+  }
+  return J3D_OK;
+}
+
+int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+                    uint32_t flags, double* resid_out, void* stream) {
+  Field a, b, c;
+  J3D_TRY(check_field(u_in, -1, &a, "u_in"));
+  J3D_TRY(check_field(u_out, a.dtype, &b, "u_out"));
+  J3D_TRY(check_field(f, a.dtype, &c, "f"));
+  J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
+  J3D_TRY(check_same_interior(a, c, "u_in", "f"));
+  J3D_TRY(check_h(h));
+  if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
+  if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
+  if (resid_out != nullptr && a.dtype != J3D_F64)
+    return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const TileCfg cfg = default_cfg3(a.dtype, a.nx(), a.ny(), a.nz());
+  GridArgs g = make_args3(&a, &b, &c, nullptr, h, cfg, 0);
+  if (resid_out == nullptr) {
+    J3D_HIP(launch_sweep3_one(a.dtype, F_WRITE, cfg, g, nullptr, nullptr, st));
+    return J3D_OK;
+  }
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  J3D_TRY(ensure_partials(s, nt));
+  J3D_HIP(launch_sweep3_one(J3D_F64, F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
   const bool host = (flags & J3D_HOST_RESULT) != 0;
   double* dst = host ? &s->ctl->value : resid_out;
   J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));

@@ -76,6 +76,15 @@ hipError_t launch_sweep2_batch(int dtype, unsigned flags, const TileCfg& c, cons
                                int ngrids, int ntiles, double* partials, const int* done,
                                hipStream_t st);
 
+// Three sweeps in one pass: g.o = J(J(J(g.u))), tile shapes of rows 2, 4 or
+// 8 wavefronts of 2 or 4 rows per thread (variants 6 and 20), cols 1, not
+// persistent; 58 x (rows x rows-per-thread - 4) outputs per block.  Flags as
+// for the two-sweep pass.
+bool tile3_cfg_supported(int dtype, const TileCfg& c);
+void tile3_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
+hipError_t launch_sweep3_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                             double* partials, const int* done, hipStream_t st);
+
 // Number of resident workgroups used for persistent launches.
 int persistent_grid(const TileCfg& c);
 

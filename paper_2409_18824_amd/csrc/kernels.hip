@@ -12,6 +12,7 @@
 #include <math.h>
 
 #include "sweep2.h"
+#include "sweep3.h"
 
 namespace j3d {
 namespace {
@@ -293,6 +294,27 @@ static hipError_t dispatch2(int dtype, unsigned flags, const sweep_detail::Launc
   if (!tile2_cfg_supported(dtype, *L.c)) return hipErrorInvalidValue;
   if (dtype == J3D_F64) return sweep_detail::dispatch_sweep2_f64(flags, L);
   return sweep_detail::dispatch_sweep2_f32(flags, L);
+}
+
+bool tile3_cfg_supported(int dtype, const TileCfg& c) {
+  if (dtype != J3D_F64 && dtype != J3D_F32) return false;
+  return sweep_detail::shape3_instantiated(c.rows, c.variant) && c.cols == 1 && c.persistent == 0 &&
+         c.order >= 0 && c.order <= 2 && c.planes >= 1 && c.planes <= 4096;
+}
+
+void tile3_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz) {
+  const int w = sweep_detail::kSweep3Cols;
+  const int h = max(1, c.rows * sweep_detail::rows_per_thread(c.variant) - 4);
+  *tx = (nx + w - 1) / w;
+  *ty = (ny + h - 1) / h;
+  *tz = (nz + max(1, c.planes) - 1) / max(1, c.planes);
+}
+
+hipError_t launch_sweep3_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                             double* partials, const int* done, hipStream_t st) {
+  if (!tile3_cfg_supported(dtype, c)) return hipErrorInvalidValue;
+  if (dtype == J3D_F64) return sweep_detail::dispatch_sweep3_f64(flags, c, g, partials, done, st);
+  return sweep_detail::dispatch_sweep3_f32(flags, c, g, partials, done, st);
 }
 
 hipError_t launch_sweep2_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,

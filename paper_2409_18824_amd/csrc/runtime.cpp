@@ -175,6 +175,14 @@ GridArgs make_args2(const Field* u, const Field* o, const Field* f, const Field*
   return g;
 }
 
+GridArgs make_args3(const Field* u, const Field* o, const Field* f, const Field* u64, double h,
+                    const TileCfg& c, int tile0) {
+  GridArgs g = make_args(u, o, f, u64, nullptr, h, c, tile0);
+  tile3_counts(g.nx, g.ny, g.nz, c, &g.tiles_x, &g.tiles_y, &g.tiles_z);
+  g.chunk = (g.tiles_x * g.tiles_y + 7) / 8;
+  return g;
+}
+
 int dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
   hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);

@@ -61,10 +61,15 @@ GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* 
 GridArgs make_args2(const Field* u, const Field* o, const Field* f, const Field* u64, double h,
                     const TileCfg& c, int tile0);
 
+// Launch arguments of the three-sweep pass (its own tile counts).
+GridArgs make_args3(const Field* u, const Field* o, const Field* f, const Field* u64, double h,
+                    const TileCfg& c, int tile0);
+
 // Default tile shape for a grid of this size and element type (the
 // autotuner's cached choice when there is one).
 TileCfg default_cfg(int dtype, int nx, int ny, int nz);
 TileCfg default_cfg2(int dtype, int nx, int ny, int nz);  // two-sweep pass
+TileCfg default_cfg3(int dtype, int nx, int ny, int nz);  // three-sweep pass
 
 // Per-(device, stream) scratch: tile partials, control words, pinned host
 // words.  Grows on demand; lives until j3d_release_cache().

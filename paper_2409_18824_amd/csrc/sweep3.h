@@ -1,0 +1,278 @@
+// Three Jacobi sweeps in one pass over HBM (temporal blocking in z), in FP64
+// or FP32.
+//
+// u3 = J(J(J(u0))).  A workgroup of BY 64-lane wavefronts, each thread owning
+// RY consecutive rows, covers a block of 64 x (BY*RY) columns: thread (l, w),
+// row r is column (x0 - 3 + l, y0 - 2 + w*RY + r), x0 = 1 + 58 tx.  Marching
+// through z, at step k the block
+//   1. computes u1 at plane k on lanes 1..62 of every row (u1 = u0 on the
+//      Dirichlet halo), from u0 planes k-1, k, k+1 in registers;
+//   2. computes u2 at plane k-1 on lanes 2..61 of rows 1 .. BY*RY-2;
+//   3. computes u3 at plane k-2 on lanes 3..60 of rows 2 .. BY*RY-3, the
+//      outputs (58 x (BY*RY - 4) columns per block; the ring around them is
+//      recomputed by the neighbouring blocks).
+// x-neighbours come from the adjacent lanes by DPP wave shifts, y-neighbours
+// from the thread's own rows, and at a wavefront's first and last row from
+// the neighbouring wavefront through LDS: u0 rows (two plane slots), u1 rows
+// (three) and u2 rows (two); only the block's outer wavefronts load the u0
+// rows beyond the block.  One barrier per plane.  u1 and u2 never reach HBM:
+// per three sweeps the pass streams u0 and f once and writes u3 once.
+//
+// Each point of u1, u2 and u3 is computed with exactly the arithmetic of a
+// single sweep (same neighbour order, no contraction), so the result equals
+// three separate sweeps bit for bit.  The fused residual, when requested, is
+// that of u0 (the input), accumulated by the output columns only.
+#pragma once
+
+#include "sweep.h"
+
+namespace j3d {
+namespace sweep_detail {
+
+// Output columns per tile in x.
+constexpr int kSweep3Cols = WAVE - 6;
+
+template <typename T, int BY>
+struct Smem3 {
+  T e0[2][BY][2][WAVE];  // u0: plane parity, wavefront, first/last row
+  T e1[3][BY][2][WAVE];  // u1: plane slot
+  T e2[2][BY][2][WAVE];  // u2: plane parity
+  double red[BY];
+};
+
+// Flags as for the two-sweep pass: F_WRITE (store u3 to g.o), F_RES (FP64:
+// residual of u0), F_FIRST (u0 is identically zero and not read), F_LAST
+// (add (double) u3 to g.u64 instead of storing it).
+template <typename T, int BY, int VAR, unsigned FL>
+__device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __restrict__ partials,
+                                            Smem3<T, BY>& sm) {
+  constexpr int RY = rows_per_thread(VAR);
+  constexpr int TR = BY * RY;  // block rows
+  constexpr int W = kSweep3Cols;
+  constexpr int H = TR - 4;    // output rows per tile
+  constexpr bool NT = (VAR & 4) != 0;
+  constexpr bool ZERO = (FL & F_FIRST) != 0;
+  static_assert(TR >= 5, "a block needs at least one output row");
+  static_assert(!(FL & F_RES) || sizeof(T) == 8, "the fused residual is an FP64 pass");
+  const int lane = threadIdx.x;
+  const int wy = threadIdx.y;
+  const int tx = t % g.tiles_x;
+  const int t2 = t / g.tiles_x;
+  const int ty = t2 % g.tiles_y;
+  const int tz = t2 / g.tiles_y;
+  const int xi = tx * W - 2 + lane;  // column x (-2 .. beyond nx+1 at the x ends)
+  const int k0 = 1 + tz * g.planes;
+  const int k1 = min(k0 + g.planes, g.nz + 1);
+  const bool lane_out = lane >= 3 && lane <= W + 2;
+  const bool x_in = xi >= 1 && xi <= g.nx;
+  const int xc = min(max(xi, 0), g.nx + 1);
+  const T* __restrict__ u0 = static_cast<const T*>(g.u);
+  const T* __restrict__ f = static_cast<const T*>(g.f);
+  T* __restrict__ out = static_cast<T*>(g.o);
+  double* __restrict__ u64 = g.u64;
+  const T h2 = h2_of<T>(g);
+  const int ztop = g.nz + 1;
+
+  int cu[RY], cf[RY], co[RY];
+  bool inner2[RY], inner3[RY], col_in[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int br = wy * RY + r;       // block row
+    const int yj = ty * H + br - 1;   // column y (block row 2 is the first output row)
+    const int yc = min(max(yj, 0), g.ny + 1);
+    cu[r] = xc + g.su_y * yc;
+    cf[r] = xc + g.sf_y * yc;
+    co[r] = (FL & F_LAST) ? xc + g.s64_y * yc : xc + g.so_y * yc;
+    inner2[r] = br >= 1 && br <= TR - 2;
+    inner3[r] = lane_out && br >= 2 && br <= TR - 3;
+    col_in[r] = x_in && yj >= 1 && yj <= g.ny;
+  }
+  // u0 rows just below and above this wavefront's rows (clamped)
+  const int ylo = max(min(max(ty * H - 1 + wy * RY, 0), g.ny + 1) - 1, 0);
+  const int yhi = min(max(ty * H - 1 + wy * RY + RY, 0), g.ny + 1);
+  const int cym = xc + g.su_y * ylo, cyp = xc + g.su_y * yhi;
+
+  double acc = 0.0;
+  T u0m[RY], u0c[RY], u1m2[RY], u1m1[RY], u2m2[RY], u2m1[RY], fm1[RY], fm2[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    u0m[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 3, 0)];
+    u0c[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 2, 0)];
+    u1m2[r] = u1m1[r] = u2m2[r] = u2m1[r] = fm1[r] = fm2[r] = T(0);
+  }
+  if (!ZERO) {
+    sm.e0[(k0 - 2) & 1][wy][0][lane] = u0c[0];
+    sm.e0[(k0 - 2) & 1][wy][1][lane] = u0c[RY - 1];
+  }
+  __syncthreads();
+
+  for (int k = k0 - 2; k <= k1 + 1; ++k) {
+    const int kc = max(k, 0);
+    const int kp = min(max(k + 1, 0), ztop);
+    const int kf = min(max(k, 1), g.nz);
+    const int zk = g.su_z * min(kc, ztop);
+    T u0p[RY], fk[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      fk[r] = f[cf[r] + g.sf_z * kf];
+      u0p[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * kp];
+    }
+    T nylo = T(0), nyhi = T(0);
+    if (!ZERO) {
+      nylo = wy > 0 ? sm.e0[k & 1][wy - 1][1][lane] : u0[cym + zk];
+      nyhi = wy < BY - 1 ? sm.e0[k & 1][wy + 1][0][lane] : u0[cyp + zk];
+      // plane k+1 for the next step (read after this step's barrier)
+      sm.e0[(k + 1) & 1][wy][0][lane] = u0p[0];
+      sm.e0[(k + 1) & 1][wy][1][lane] = u0p[RY - 1];
+    }
+    // stage 1: u1 at plane k on every row of the block
+    T u1[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const T nym = r == 0 ? nylo : u0c[r - 1];
+      const T nyp = r == RY - 1 ? nyhi : u0c[r + 1];
+      const bool pt_in = col_in[r] && k >= 1 && k <= g.nz;
+      T s = ZERO ? T(0) : from_left(u0c[r]) + from_right(u0c[r]);
+      s = s + nym;
+      s = s + nyp;
+      s = s + u0m[r];
+      s = s + u0p[r];
+      u1[r] = pt_in ? div6(s + h2 * fk[r]) : u0c[r];
+      if (FL & F_RES) {
+        const double res = static_cast<double>(fk[r]) -
+                           (6.0 * static_cast<double>(u0c[r]) - static_cast<double>(s)) / g.h2;
+        acc += (inner3[r] && pt_in && k >= k0 && k < k1) ? res * res : 0.0;
+      }
+    }
+    // slot of plane k (k starts at k0 - 2 >= -1: keep the index non-negative)
+    sm.e1[(k + 3) % 3][wy][0][lane] = u1[0];
+    sm.e1[(k + 3) % 3][wy][1][lane] = u1[RY - 1];
+    __syncthreads();
+    // stage 2: u2 at plane k-1 (from u1 at k-2, k-1, k)
+    T u2[RY];
+    {
+      const int sl = (k + 2) % 3;  // slot of plane k-1
+      const T below = wy > 0 ? sm.e1[sl][wy - 1][1][lane] : T(0);
+      const T above = wy < BY - 1 ? sm.e1[sl][wy + 1][0][lane] : T(0);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const T xm = from_left(u1m1[r]), xp = from_right(u1m1[r]);
+        const T ym = r == 0 ? below : u1m1[r - 1];
+        const T yp = r == RY - 1 ? above : u1m1[r + 1];
+        T s = xm + xp;
+        s = s + ym;
+        s = s + yp;
+        s = s + u1m2[r];
+        s = s + u1[r];
+        const bool pt_in = col_in[r] && k - 1 >= 1 && k - 1 <= g.nz;
+        u2[r] = (pt_in && inner2[r]) ? div6(s + h2 * fm1[r]) : u1m1[r];
+      }
+    }
+    // stage 3: u3 at plane k-2 (from u2 at k-3, k-2, k-1); the u2 edge rows
+    // of plane k-2 were written in the previous step
+    if (k - 2 >= k0) {
+      const int sl = (k - 2) & 1;
+      const T below = wy > 0 ? sm.e2[sl][wy - 1][1][lane] : T(0);
+      const T above = wy < BY - 1 ? sm.e2[sl][wy + 1][0][lane] : T(0);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const T xm = from_left(u2m1[r]), xp = from_right(u2m1[r]);
+        if (inner3[r]) {
+          const T ym = r == 0 ? below : u2m1[r - 1];
+          const T yp = r == RY - 1 ? above : u2m1[r + 1];
+          T s = xm + xp;
+          s = s + ym;
+          s = s + yp;
+          s = s + u2m2[r];
+          s = s + u2[r];
+          const T u3 = div6(s + h2 * fm2[r]);
+          if (col_in[r]) {
+            if (FL & F_LAST) {
+              double* q = u64 + co[r] + g.s64_z * (k - 2);
+              q[0] = q[0] + static_cast<double>(u3);
+            } else {
+              put<T, NT>(out + co[r] + g.so_z * (k - 2), u3);
+            }
+          }
+        }
+      }
+    }
+    sm.e2[(k - 1) & 1][wy][0][lane] = u2[0];
+    sm.e2[(k - 1) & 1][wy][1][lane] = u2[RY - 1];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      u0m[r] = u0c[r];
+      u0c[r] = u0p[r];
+      u1m2[r] = u1m1[r];
+      u1m1[r] = u1[r];
+      u2m2[r] = u2m1[r];
+      u2m1[r] = u2[r];
+      fm2[r] = fm1[r];
+      fm1[r] = fk[r];
+    }
+  }
+
+  if (FL & F_RES) {
+    const double tot = block_sum<BY>(acc, sm.red);
+    if (wy == 0 && lane == 0) partials[g.tile0 + t] = tot;
+  }
+  __syncthreads();
+}
+
+template <typename T, int BY, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * BY)
+    k_sweep3_one(GridArgs g, double* __restrict__ partials, const int* __restrict__ done) {
+  if (done != nullptr && *done != 0) return;
+  __shared__ Smem3<T, BY> sm;
+  const int ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
+  if (g.order == 0) {
+    for (int t = xcd_remap(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
+      sweep3_tile<T, BY, VAR, FL>(g, t, partials, sm);
+  } else {
+    const int nv = virtual_tiles(ntiles, g.order, g.chunk);
+    for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
+      const int t = g.order == 2 ? xcd_chunked(vb, g.chunk) : vb;
+      if (t < ntiles) sweep3_tile<T, BY, VAR, FL>(g, t, partials, sm);
+    }
+  }
+}
+
+// Instantiated three-sweep shapes: one wavefront along x, blocks of 8 to 32
+// rows, 2 or 4 rows per thread, nontemporal stores.
+constexpr bool shape3_instantiated(int by, int var) {
+  const int tr = by * rows_per_thread(var);
+  return (var == 6 || var == 20) && tr >= 8 && tr <= 32 && by <= 16;
+}
+
+template <typename T, int BY, int VAR, unsigned FL>
+hipError_t go3(const GridArgs& g, double* partials, const int* done, hipStream_t st) {
+  if constexpr (!shape3_instantiated(BY, VAR)) {
+    return hipErrorInvalidValue;
+  } else {
+    const int grid = virtual_tiles(g.tiles_x * g.tiles_y * g.tiles_z, g.order, g.chunk);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep3_one<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, st, g, partials, done);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, unsigned FL>
+hipError_t by_shape3(const TileCfg& c, const GridArgs& g, double* partials, const int* done, hipStream_t st) {
+  switch (c.rows * 100 + c.variant) {
+    case 206: return go3<T, 2, 6, FL>(g, partials, done, st);
+    case 220: return go3<T, 2, 20, FL>(g, partials, done, st);
+    case 406: return go3<T, 4, 6, FL>(g, partials, done, st);
+    case 420: return go3<T, 4, 20, FL>(g, partials, done, st);
+    case 806: return go3<T, 8, 6, FL>(g, partials, done, st);
+    case 820: return go3<T, 8, 20, FL>(g, partials, done, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t dispatch_sweep3_f64(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
+                               const int* done, hipStream_t st);
+hipError_t dispatch_sweep3_f32(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
+                               const int* done, hipStream_t st);
+
+}  // namespace sweep_detail
+}  // namespace j3d

@@ -34,6 +34,8 @@ HOST_RESULT = 1
 MODE_FP64, MODE_MIXED = 0, 1
 KIND_F64X2 = 2  # tuning kind of the two-sweep FP64 pass
 KIND_F32X2 = 3  # tuning kind of the two-sweep FP32 pass (also the mixed solve's correction sweeps)
+KIND_F64X3 = 4  # tuning kind of the three-sweep FP64 pass
+KIND_F32X3 = 5  # tuning kind of the three-sweep FP32 pass
 
 _ERRNAMES = {0: "OK", -1: "EINVAL", -2: "EDTYPE", -3: "EALIAS", -4: "ENOMEM", -5: "EBUDGET",
              -6: "EHIP", -7: "ENONFINITE", -8: "EAGAIN", -9: "ESTATE"}
@@ -108,6 +110,7 @@ _SIGS = {
     "j3d_check_array": ([_P(J3DArray), _I32], ctypes.c_int),
     "jacobi3d_sweep": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "jacobi3d_sweep2": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
+    "jacobi3d_sweep3": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "residual_l2": ([_P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "poisson_solve": ([_P(J3DArray), _P(J3DArray), _D, _P(SolveOpts), _P(SolveResult), _V], ctypes.c_int),
     "j3d_tune_count": ([], ctypes.c_int),
@@ -326,6 +329,23 @@ def jacobi3d_sweep2(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=
     ptr = None if resid_out is None else ctypes.c_void_p(resid_out.data_ptr())
     _check(_lib.jacobi3d_sweep2(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h), flags, ptr, st),
            "jacobi3d_sweep2")
+    return None
+
+
+def jacobi3d_sweep3(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=None, host_result=False,
+                    stream=None, flags: int = 0):
+    """Three sweeps in one pass: u_out = J(J(J(u_in))).  Residual (of u_in) as in jacobi3d_sweep."""
+    a, b, c = u_in.desc(), u_out.desc(), f.desc()
+    st = _stream_handle(stream)
+    if host_result:
+        out = ctypes.c_double()
+        _check(_lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h),
+                                    flags | HOST_RESULT, ctypes.cast(ctypes.byref(out), ctypes.c_void_p), st),
+               "jacobi3d_sweep3")
+        return out.value
+    ptr = None if resid_out is None else ctypes.c_void_p(resid_out.data_ptr())
+    _check(_lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h), flags, ptr, st),
+           "jacobi3d_sweep3")
     return None
 
 

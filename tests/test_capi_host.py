@@ -317,3 +317,25 @@ def test_wide_arrays_only_where_planes_are_addressed_in_64_bit():
     d = [fake_desc(nx, ny, nz, base=0x10000 + q * (1 << 40)) for q in range(6)]
     d[5].dtype = j3d.F32  # fails on the dtype, after the size rule accepted the others
     assert _call_pw(d) == j3d.EDTYPE
+
+
+def test_three_sweep_kind_defaults_and_validation():
+    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 97, 5, 3) == (4, 32, 20, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 97, 5, 3) == (8, 32, 20, 0, 1, 1)
+    for bad in [(1, 16, 20, 0, 1, 1), (4, 16, 16, 0, 1, 1), (4, 16, 20, 1, 1, 1), (4, 16, 20, 0, 1, 2),
+                (16, 16, 20, 0, 1, 1)]:
+        with pytest.raises(j3d.J3DError) as ei:
+            j3d.j3d_tune_set_single(j3d.KIND_F64X3, 64, 64, 64, bad)
+        assert ei.value.code == j3d.EINVAL
+    lib = j3d._lib
+    a, b, c = fake_desc(10, 8, 6), fake_desc(10, 8, 6, base=0x900000), fake_desc(10, 8, 6, base=0x1900000)
+    assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), -0.1, 0, None, None) == j3d.EINVAL
+    assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(a), ctypes.byref(c), 0.1, 0, None, None) == j3d.EALIAS
+    d = fake_desc(11, 8, 6, base=0x900000)
+    assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(d), ctypes.byref(c), 0.1, 0, None, None) == j3d.EINVAL
+    a32 = fake_desc(10, 8, 6, dtype=j3d.F32)
+    b32 = fake_desc(10, 8, 6, dtype=j3d.F32, base=0x900000)
+    c32 = fake_desc(10, 8, 6, dtype=j3d.F32, base=0x1900000)
+    r = ctypes.c_double()
+    assert lib.jacobi3d_sweep3(ctypes.byref(a32), ctypes.byref(b32), ctypes.byref(c32), 0.1, j3d.HOST_RESULT,
+                               ctypes.cast(ctypes.byref(r), ctypes.c_void_p), None) == j3d.EDTYPE

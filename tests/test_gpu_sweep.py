@@ -100,6 +100,70 @@ def test_sweep2_equals_two_sweeps(shape, tune):
     assert np.array_equal(du.to_numpy(), u)  # input untouched
 
 
+TUNES3 = [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (4, 7, 6, 0, 1, 1), (8, 64, 20, 0, 0, 1),
+          (2, 3, 20, 0, 2, 1)]
+SHAPES3 = [(1, 1, 1), (3, 4, 5), (58, 6, 9), (59, 12, 10), (57, 13, 8), (117, 30, 17), (17, 45, 64), (200, 28, 3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES3)
+@pytest.mark.parametrize("tune", TUNES3)
+def test_sweep3_equals_three_sweeps(shape, tune):
+    nx, ny, nz = shape
+    say("sweep3", shape, tune)
+    u, f, h = make_inputs(nx, ny, nz, seed=7)
+    j3d.j3d_tune_set_single(j3d.KIND_F64X3, nx, ny, nz, tune)
+    du = j3d.FArray.from_numpy(u)
+    dv = j3d.FArray.from_numpy(u)
+    dv.view()[1:-1, 1:-1, 1:-1] = -7.0
+    df = j3d.FArray.from_numpy(f, ld_extra=3)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    want = oracle.sweep(oracle.sweep(oracle.sweep(u, f, h), f, h), f, h)
+    got = dv.to_numpy()
+    assert np.array_equal(got, want), "max diff %g" % np.max(np.abs(got - want))
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+    assert np.array_equal(du.to_numpy(), u)  # input untouched
+
+
+@pytest.mark.parametrize("shape", [(70, 13, 21), (1, 1, 1), (130, 40, 9), (58, 14, 33)])
+@pytest.mark.parametrize("tune", [(8, 32, 20, 0, 1, 1), (4, 16, 6, 0, 0, 1), (2, 8, 20, 0, 2, 1)])
+def test_sweep3_fp32_equals_three_fp32_sweeps(shape, tune):
+    nx, ny, nz = shape
+    say("sweep3 fp32", shape, tune)
+    e = synth.uniform_field(nx, ny, nz, 8, 1, -1, 1).astype(np.float32)
+    r32 = synth.uniform_field(nx, ny, nz, 8, 2, -1, 1).astype(np.float32)
+    h = 1.0 / (max(shape) + 1)
+    h2 = np.float32(h * h)
+    j3d.j3d_tune_set_single(j3d.KIND_F32X3, nx, ny, nz, tune)
+    de = j3d.FArray.from_numpy(e, dtype=j3d.F32)
+    do = j3d.FArray.from_numpy(e, dtype=j3d.F32)
+    dr = j3d.FArray.from_numpy(r32, dtype=j3d.F32)
+    j3d.jacobi3d_sweep3(de, do, dr, h)
+    torch.cuda.synchronize()
+    want = oracle.sweep_f32(oracle.sweep_f32(oracle.sweep_f32(e, r32, h2), r32, h2), r32, h2)
+    assert np.array_equal(do.to_numpy(), want)
+
+
+def test_sweep3_full_size_512():
+    n = 512
+    say("512^3 sweep3")
+    h = 1.0 / (n + 1)
+    f = synth.manufactured_f(n, n, n, h)
+    du = j3d.FArray.empty(n, n, n)
+    j3d.j3d_fill_uniform(du, 2, synth.STREAM_U0, 0.0, 1.0)
+    dv = j3d.FArray.empty(n, n, n)
+    df = j3d.FArray.from_numpy(f)
+    say("tile", j3d.j3d_tune_query_single(j3d.KIND_F64X3, n, n, n))
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    u = du.to_numpy()
+    want = oracle.sweep(oracle.sweep(oracle.sweep(u, f, h), f, h), f, h)
+    assert np.array_equal(dv.to_numpy()[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1])
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+
+
 def test_sweep2_shapes_with_wide_tiles_rejected():
     for kind in (j3d.KIND_F64X2, j3d.KIND_F32X2):
         for t in [(4, 32, 20, 0, 1, 2), (2, 16, 20, 0, 1, 4), (4, 32, 1, 0, 1, 1), (1, 8, 0, 0, 1, 1)]:
