@@ -3,19 +3,23 @@
 Default workload: 512^3 interior + halo, FP64, two ping-pong arrays plus f,
 u0 ~ U[0,1) (seed 2), f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z), h = 1/513;
 one step = 500 sweeps with the L2 residual fused into every 10th sweep
-(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  The sweeps run as
-250 two-sweep passes (jacobi3d_sweep2: the intermediate iterate stays on
-chip; --passes 1 runs 500 single sweeps instead).  Throughput is grid-point
-updates per second (GLUP/s) over the timed steps.
+(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  Each group of
+10 sweeps runs as two two-sweep passes, the first carrying the fused
+residual, and two three-sweep passes (jacobi3d_sweep3: the intermediate
+iterates stay on chip); --passes 2 runs 250 two-sweep passes instead,
+--passes 1 500 single sweeps.  Throughput is grid-point updates per second (GLUP/s) over the timed
+steps.
 
 The JSON line also carries
-  roofline:     the dominant kernel (the pass without a fused residual, 225
-                of the 250 launches of a step), its average duration from HIP
-                events on the stream it runs on, and its algorithmic bandwidth
-                against the MI355X HBM peak.  Algorithmic bytes per launch:
-                24 per interior point (read u, read f, write the result) for
-                either pass; a two-sweep pass does two updates per point for
-                them (12 bytes per update), a single sweep one (24);
+  roofline:     the dominant kernel (the multi-sweep pass without a fused
+                residual: the 100 three-sweep passes of a step, 54% of its
+                time), its average duration from HIP events on the stream it
+                runs on, and its algorithmic bandwidth against the MI355X HBM
+                peak.  Algorithmic bytes per launch: 24 per interior point
+                (read u, read f, write the result) for every pass; a
+                three-sweep pass does three updates per point for them (8
+                bytes per update), a two-sweep pass two (12), a single sweep
+                one (24);
   cpu_baseline: the CPU oracle timed on a bounded sample of the same
                 workload (a few of the 500 sweeps, on all host threads).
 
@@ -56,8 +60,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP_F64 = 24.0
 
 
-KERNEL_SOURCES = ("sweep.h", "sweep2.h", "kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip",
-                  "j3d_internal.h")
+KERNEL_SOURCES = ("sweep.h", "sweep2.h", "sweep3.h", "kernels.hip", "kernels_f64.hip", "kernels_f32.hip",
+                  "kernels_sweep2.hip", "kernels_sweep3.hip", "j3d_internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -73,7 +77,7 @@ def measured_traffic(kernel_hash: str, passes: int, tile):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on the current kernel source with this tile
     shape."""
-    path = os.path.join(ROOT, "profiles", "sweep%s_fp64_512_counters.json" % ("2" if passes == 2 else ""))
+    path = os.path.join(ROOT, "profiles", "sweep%s_fp64_512_counters.json" % {1: "", 2: "2", 3: "3"}[passes])
     try:
         with open(path) as fp:
             d = json.load(fp)
@@ -122,8 +126,10 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--resid-every", type=int, default=10)
-    ap.add_argument("--passes", type=int, default=2, choices=[1, 2],
-                    help="sweeps per pass over memory (2: temporally blocked pass)")
+    ap.add_argument("--passes", type=int, default=3, choices=[1, 2, 3],
+                    help="sweeps per pass over memory (2, 3: temporally blocked passes; with 3 each residual "
+                         "group starts with two-sweep passes for E mod 3, the first carrying the residual, "
+                         "10 = 2+2+3+3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first and use the fastest (default: the library's default "
@@ -173,20 +179,40 @@ def main():
     P = args.passes
     if P == 2 and (E % 2 != 0 or S % 2 != 0):
         raise SystemExit("two-sweep passes need even --sweeps and --resid-every")
-    kind = j3d.KIND_F64X2 if P == 2 else j3d.F64
+    if P == 3 and (S % E != 0 or E < 2):
+        raise SystemExit("three-sweep schedules need --sweeps a multiple of --resid-every >= 2")
+    kind = {1: j3d.F64, 2: j3d.KIND_F64X2, 3: j3d.KIND_F64X3}[P]
     if args.tile:
         j3d.j3d_tune_set_single(kind, n, n, n, tuple(int(x) for x in args.tile.split(",")))
     elif args.autotune:
         j3d.j3d_autotune_single(kind, n, n, n)
-        if P == 2:
+        if P >= 2:
             j3d.j3d_autotune_single(j3d.F64, n, n, n)  # the standalone residual pass
+        if P == 3 and E % 3 != 0:
+            j3d.j3d_autotune_single(j3d.KIND_F64X2, n, n, n)  # the two-sweep passes of each group
     tune = j3d.j3d_tune_query_single(kind, n, n, n)  # the shape the timed passes use
     print("[bench] tile shape (rows, planes, variant, persistent, order, cols) = %s" % (tune,), file=sys.stderr, flush=True)
 
     nres = S // E + 1
     resid = torch.zeros(nres, dtype=torch.float64, device="cuda")
-    sweep = j3d.jacobi3d_sweep2 if P == 2 else j3d.jacobi3d_sweep
-    n_plain = sum(1 for s in range(0, S, P) if s % E != 0)
+    sweeps_of = {1: j3d.jacobi3d_sweep, 2: j3d.jacobi3d_sweep2, 3: j3d.jacobi3d_sweep3}
+    # passes in sweep order: (first sweep, sweeps in the pass); a pass that
+    # starts a residual group carries the fused residual of its input
+    if P == 3:
+        # the remainder of E mod 3 runs first, in two-sweep passes whose first
+        # carries the group's fused residual (10 = 2+2+3+3; a single sweep
+        # leaves eight times as many per-tile partials to reduce)
+        n3, rem = divmod(E, 3)
+        group = [2, 2] + [3] * (n3 - 1) if (rem == 1 and n3 >= 1) else ([rem] if rem else []) + [3] * n3
+        plan = []
+        for g0 in range(0, S, E):
+            s = g0
+            for m in group:
+                plan.append((s, m))
+                s += m
+    else:
+        plan = [(s, P) for s in range(0, S, P)]
+    n_plain = sum(1 for s, m in plan if s % E != 0 and m == P)
     events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(n_plain)] for _ in range(args.steps)]
 
@@ -196,16 +222,17 @@ def main():
         cur, nxt = state["cur"], state["nxt"]
         timed = ev is not None
         q = 0
-        for s in range(0, S, P):
+        for s, m in plan:
+            sweep = sweeps_of[m]
             if s % E == 0:
                 sweep(cur, nxt, df, h, resid_out=resid[s // E:s // E + 1])
-            else:
-                if timed:
-                    ev[q][0].record()
+            elif timed and m == P:
+                ev[q][0].record()
                 sweep(cur, nxt, df, h)
-                if timed:
-                    ev[q][1].record()
-                    q += 1
+                ev[q][1].record()
+                q += 1
+            else:
+                sweep(cur, nxt, df, h)
             cur, nxt = nxt, cur
         if S % E == 0:
             j3d.residual_l2(cur, df, h, out=resid[S // E:S // E + 1])
@@ -241,8 +268,9 @@ def main():
     bytes_launch = BYTES_PER_LUP_F64 * n ** 3  # read u, read f, write the result
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
-    kname = ("k_sweep2_one<F_WRITE> (two FP64 sweeps per pass)" if P == 2
-             else "k_pass_one<double, F_WRITE> (FP64 sweep)")
+    kname = {1: "k_pass_one<double, F_WRITE> (FP64 sweep)",
+             2: "k_sweep2_one<F_WRITE> (two FP64 sweeps per pass)",
+             3: "k_sweep3_one<F_WRITE> (three FP64 sweeps per pass)"}[P]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, P, tune),
             "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2),
@@ -270,7 +298,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "jacobi3d-7pt-fp64-%dcubed-%dsweeps-resid%d" % (n, S, E),
                    "grid": [n, n, n], "halo": 1, "layout": "fortran-column-major",
-                   "sweeps_per_step": S, "resid_every": E, "sweeps_per_pass": P, "tile": tune,
+                   "sweeps_per_step": S, "resid_every": E, "sweeps_per_pass": P,
+                   "passes_per_residual_group": [m for s, m in plan if s < E], "tile": tune,
                    "single_sweep_equivalent_gbs": round(glups * BYTES_PER_LUP_F64, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,

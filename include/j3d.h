@@ -296,6 +296,11 @@ typedef struct j3d_solve_result {
  * from e = 0 with h^2 = (float)(h*h).  The last cycle ends with a defect
  * step, so u includes every correction and `resid` is its residual.
  *
+ * Sweeps run two or three per pass over memory (as jacobi3d_sweep2 and
+ * jacobi3d_sweep3), three when the arrays of a pass exceed 512 MB, i.e.
+ * overflow the last-level cache; J3D_SOLVE_SWEEPS_PER_PASS=1, 2 or 3 fixes
+ * the pass length.  Every schedule gives the same iterate bit for bit.
+ *
  * Not converging is not an error (converged = 0).  A NaN/Inf residual stops
  * the solve with status and return value J3D_ENONFINITE.  The call blocks
  * until the solve has finished.  Work arrays (one FP64 array in FP64 mode,

@@ -9,6 +9,7 @@
 // structures") with the exit test evaluated where the data lives.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -27,6 +28,22 @@ long long chunk_sweeps(long long points, double bytes_per_point, long long multi
   n = std::min<long long>(n, 1 << 16);
   n = ((n + multiple - 1) / multiple) * multiple;
   return n;
+}
+
+// Three-sweep passes pay off once the arrays a pass touches overflow the
+// 256 MB last-level cache: measured on cubes, they save 20-27% per sweep at
+// 384^3 and 512^3, but at 256^3 the cache holds most of the arrays and the
+// three-sweep tile's wider halo cancels the saving (two-sweep passes are
+// as fast or faster there).
+bool three_sweep_passes_pay(double pass_bytes) { return pass_bytes > 512e6; }
+
+// J3D_SOLVE_SWEEPS_PER_PASS=1, 2 or 3 fixes the pass length of both modes
+// (the schedules above, with that step); unset or other values choose it
+// from the grid size.
+int forced_step() {
+  const char* e = std::getenv("J3D_SOLVE_SWEEPS_PER_PASS");
+  const int v = e != nullptr ? std::atoi(e) : 0;
+  return (v >= 1 && v <= 3) ? v : 0;
 }
 
 int publish_done(Scratch* s, int slot, hipStream_t st) {
@@ -92,10 +109,29 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   J3D_TRY(get_scratch(st, &s));
   const TileCfg cfg = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());
   const TileCfg cfg2 = default_cfg2(J3D_F64, u.nx(), u.ny(), u.nz());
+  const TileCfg cfg3 = default_cfg3(J3D_F64, u.nx(), u.ny(), u.nz());
   const long long S = o.max_sweeps;
   const long long c = o.check_every;
-  // Two-sweep passes when every check falls on an even sweep count.
-  const bool pairs = (c % 2) == 0;
+  const long long points = (long long)u.nx() * u.ny() * u.nz();
+  // Passes of `step` sweeps: three on grids whose arrays overflow the
+  // cache, else two when every check falls on an even sweep count, else
+  // one.  A check group of c sweeps opens with one pass of c mod step
+  // sweeps (none when step divides c), which carries the check's residual,
+  // and continues in passes of step sweeps; with three-sweep passes and
+  // c mod 3 = 1 it opens with two two-sweep passes instead, since the
+  // residual of a single sweep leaves many more per-tile partials to
+  // reduce.  A pass ends at the next check and at the end of the range it
+  // belongs to.
+  const long long step = forced_step() != 0 ? forced_step()
+                         : three_sweep_passes_pay(24.0 * (double)points) ? 3 : ((c % 2) == 0 ? 2 : 1);
+  const long long lead = c % step;
+  const bool two_pairs = step == 3 && lead == 1 && c >= 4;
+  auto pass_len = [&](long long sw, long long to) -> int {
+    const long long p = sw % c;
+    const long long len = two_pairs ? ((p == 0 || p == 2) ? 2 : 3) : ((p == 0 && lead != 0) ? lead : step);
+    return (int)std::min(std::min(len, c - p), to - sw);
+  };
+  const long long group_passes = (lead != 0 ? 1 : 0) + c / step;
 
   // The second ping-pong array has u's layout and starts as a copy of u
   // (which gives it the same halo).
@@ -105,15 +141,17 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   J3D_HIP(hipMemcpyAsync(w.base, u.base, u.span_bytes(), hipMemcpyDeviceToDevice, st));
 
   const Field* buf[2] = {&u, &w};
-  GridArgs one[2], two[2], resid[2];
+  GridArgs one[2], two[2], three[2], resid[2];
   for (int b = 0; b < 2; ++b) {
     one[b] = make_args(buf[b], buf[1 - b], &f, nullptr, nullptr, h, cfg, 0);
     two[b] = make_args2(buf[b], buf[1 - b], &f, nullptr, h, cfg2, 0);
+    three[b] = make_args3(buf[b], buf[1 - b], &f, nullptr, h, cfg3, 0);
     resid[b] = make_args(buf[b], nullptr, &f, nullptr, nullptr, h, cfg, 0);
   }
   const int nt1 = one[0].tiles_x * one[0].tiles_y * one[0].tiles_z;
   const int nt2 = two[0].tiles_x * two[0].tiles_y * two[0].tiles_z;
-  J3D_TRY(ensure_partials(s, std::max(nt1, nt2)));
+  const int nt3 = three[0].tiles_x * three[0].tiles_y * three[0].tiles_z;
+  J3D_TRY(ensure_partials(s, std::max(nt1, std::max(nt2, nt3))));
   const long long nchecks = S / c + 1;
   J3D_TRY(ensure_hist(s, (size_t)nchecks));
 
@@ -123,25 +161,27 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
 
   // which_at[q]: buffer holding the iterate whose residual is check q
   std::vector<unsigned char> which_at((size_t)nchecks, 0);
-  // The passes for sweeps [from, to) starting from buffer b: a two-sweep pass
-  // wherever pairs apply and two sweeps remain before `to` (chunk ends are
-  // multiples of 4 when pairs apply, so chunking never changes the
-  // schedule).  Checks take their index from the device counter, so a chunk
-  // is the same kernel sequence wherever it starts and can be replayed.
+  // The passes for sweeps [from, to) starting from buffer b (chunk ends are
+  // multiples of c, so chunking never changes the schedule).  Checks take
+  // their index from the device counter, so a chunk is the same kernel
+  // sequence wherever it starts and can be replayed.
   auto passes = [&](long long from, long long to, int b, hipStream_t q) -> int {
     for (long long sw = from; sw < to;) {
       const bool check = (sw % c) == 0;
       const unsigned fl = F_WRITE | (check ? F_RES : 0u);
+      const int len = pass_len(sw, to);
       int nt;
-      if (pairs && sw + 2 <= to) {
+      if (len == 3) {
+        J3D_HIP(launch_sweep3_one(J3D_F64, fl, cfg3, three[b], s->partials, done, q));
+        nt = nt3;
+      } else if (len == 2) {
         J3D_HIP(launch_sweep2_one(J3D_F64, fl, cfg2, two[b], s->partials, done, q));
         nt = nt2;
-        sw += 2;
       } else {
         J3D_HIP(launch_pass_one(J3D_F64, fl, cfg, one[b], s->partials, done, q));
         nt = nt1;
-        sw += 1;
       }
+      sw += len;
       if (check)
         J3D_HIP(launch_reduce_count(s->partials, nt, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
                                     &s->ctl->nonfinite, &s->ctl->qnext, q));
@@ -153,14 +193,13 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   auto track = [&](long long from, long long to, int b) -> int {
     for (long long sw = from; sw < to;) {
       if (sw % c == 0) which_at[(size_t)(sw / c)] = (unsigned char)b;
-      sw += (pairs && sw + 2 <= to) ? 2 : 1;
+      sw += pass_len(sw, to);
       b = 1 - b;
     }
     return b;
   };
-  const long long points = (long long)u.nx() * u.ny() * u.nz();
-  const long long unit = std::lcm(c, pairs ? 4LL : 2LL);  // an even number of passes
-  const long long chunk = chunk_sweeps(points, pairs ? 12.0 : 24.0, unit);
+  const long long unit = group_passes % 2 == 0 ? c : 2 * c;  // an even number of passes
+  const long long chunk = chunk_sweeps(points, 24.0 * group_passes / c, unit);
   long long sw = 0;
   int cur = 0;
   int slot = 0;
@@ -173,9 +212,11 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
     auto add = [&key](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
     add(one, sizeof one);
     add(two, sizeof two);
+    add(three, sizeof three);
     add(&cfg, sizeof cfg);
     add(&cfg2, sizeof cfg2);
-    const long long meta[4] = {c, M, nt1, nt2};
+    add(&cfg3, sizeof cfg3);
+    const long long meta[6] = {c, M, nt1, nt2, nt3, step};
     add(meta, sizeof meta);
     const void* ptrs[3] = {s->partials, s->hist, s->ctl};
     add(ptrs, sizeof ptrs);
@@ -279,19 +320,27 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   J3D_HIP(hipMemsetAsync(mem, 0, 3 * b1, st));  // zero halos of the correction
 
   // A cycle of m correction sweeps e_1 = J(0), e_{p+1} = J(e_p), u += e_m
-  // runs as two-sweep passes: the first pass starts from zero without
-  // reading it (one sweep when m is odd, two when even), the middle passes
+  // runs as passes of `step` sweeps (three on grids whose arrays overflow
+  // the cache, else two): the first pass starts from zero without reading
+  // it (m mod step sweeps, step when step divides m), the middle passes
   // ping-pong between e0 and e1, and the last pass adds its result to u.
+  const long long points = (long long)u.nx() * u.ny() * u.nz();
+  const int step = forced_step() != 0 ? forced_step() : three_sweep_passes_pay(12.0 * (double)points) ? 3 : 2;
   const TileCfg cs2 = default_cfg2(J3D_F32, u.nx(), u.ny(), u.nz());
+  const TileCfg cs3 = default_cfg3(J3D_F32, u.nx(), u.ny(), u.nz());
   const GridArgs defect = make_args(&u, nullptr, &f, nullptr, &r32, h, cd, 0);
-  const GridArgs first1 = make_args(nullptr, &e0, &r32, nullptr, nullptr, h, cs, 0);
-  const GridArgs first_last1 = make_args(nullptr, nullptr, &r32, &u, nullptr, h, cs, 0);
-  const GridArgs first2 = make_args2(nullptr, &e0, &r32, nullptr, h, cs2, 0);
-  const GridArgs first_last2 = make_args2(nullptr, nullptr, &r32, &u, h, cs2, 0);
-  const GridArgs mid2[2] = {make_args2(&e0, &e1, &r32, nullptr, h, cs2, 0),
-                            make_args2(&e1, &e0, &r32, nullptr, h, cs2, 0)};
-  const GridArgs last2[2] = {make_args2(&e0, nullptr, &r32, &u, h, cs2, 0),
-                             make_args2(&e1, nullptr, &r32, &u, h, cs2, 0)};
+  auto pass_args = [&](int len, const Field* in, const Field* out, const Field* add_to) -> GridArgs {
+    if (len == 3) return make_args3(in, out, &r32, add_to, h, cs3, 0);
+    if (len == 2) return make_args2(in, out, &r32, add_to, h, cs2, 0);
+    return make_args(in, out, &r32, add_to, nullptr, h, cs, 0);
+  };
+  GridArgs first[4] = {}, first_last[4] = {};  // indexed by the pass length
+  for (int len = 1; len <= 3; ++len) {
+    first[len] = pass_args(len, nullptr, &e0, nullptr);
+    first_last[len] = pass_args(len, nullptr, nullptr, &u);
+  }
+  const GridArgs mid[2] = {pass_args(step, &e0, &e1, nullptr), pass_args(step, &e1, &e0, nullptr)};
+  const GridArgs last[2] = {pass_args(step, &e0, nullptr, &u), pass_args(step, &e1, nullptr, &u)};
   const int nt = defect.tiles_x * defect.tiles_y * defect.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
   const long long ncyc = (S + m_in - 1) / m_in + 1;  // defect steps at most
@@ -301,6 +350,11 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   J3D_TRY(norm_f(f, cd, s, st));
   int* done = &s->ctl->done;
 
+  auto correction_pass = [&](int len, unsigned fl, const GridArgs& g, hipStream_t q) -> hipError_t {
+    if (len == 3) return launch_sweep3_one(J3D_F32, fl, cs3, g, nullptr, done, q);
+    if (len == 2) return launch_sweep2_one(J3D_F32, fl, cs2, g, nullptr, done, q);
+    return launch_pass_one(J3D_F32, fl, cs, g, nullptr, done, q);
+  };
   // One unit: the defect step with its check (index from the device
   // counter), then a correction cycle of m sweeps (none for the final
   // defect step).  Units with the same m are the same kernel sequence.
@@ -309,27 +363,22 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
     J3D_HIP(launch_reduce_count(s->partials, nt, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
                                 &s->ctl->nonfinite, &s->ctl->qnext, q));
     if (m == 0) return J3D_OK;
-    if (m == 1) {
-      J3D_HIP(launch_pass_one(J3D_F32, F_LAST | F_FIRST, cs, first_last1, nullptr, done, q));
-    } else if (m == 2) {
-      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST | F_FIRST, cs2, first_last2, nullptr, done, q));
+    if (m <= step) {
+      J3D_HIP(correction_pass((int)m, F_LAST | F_FIRST, first_last[m], q));
     } else {
-      if (m & 1)
-        J3D_HIP(launch_pass_one(J3D_F32, F_WRITE | F_FIRST, cs, first1, nullptr, done, q));
-      else
-        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE | F_FIRST, cs2, first2, nullptr, done, q));
-      const long long pairs = (m - 2 + (m & 1)) / 2;  // passes after the first, >= 1
-      int cur = 0;                                    // e0 holds the iterate
-      for (long long p = 1; p < pairs; ++p) {
-        J3D_HIP(launch_sweep2_one(J3D_F32, F_WRITE, cs2, mid2[cur], nullptr, done, q));
+      const long long lead = m % step == 0 ? step : m % step;
+      J3D_HIP(correction_pass((int)lead, F_WRITE | F_FIRST, first[lead], q));
+      const long long rest = (m - lead) / step;  // passes after the first, >= 1
+      int cur = 0;                               // e0 holds the iterate
+      for (long long p = 1; p < rest; ++p) {
+        J3D_HIP(correction_pass(step, F_WRITE, mid[cur], q));
         cur = 1 - cur;
       }
-      J3D_HIP(launch_sweep2_one(J3D_F32, F_LAST, cs2, last2[cur], nullptr, done, q));
+      J3D_HIP(correction_pass(step, F_LAST, last[cur], q));
     }
     return J3D_OK;
   };
 
-  const long long points = (long long)u.nx() * u.ny() * u.nz();
   const long long chunk = chunk_sweeps(points, 6.6, m_in);
   const long long full = S / m_in;                            // units with a whole cycle
   const long long K = std::max<long long>(1, chunk / m_in);   // units per replayed graph
@@ -345,13 +394,16 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   if (full / K >= 2) {
     std::string key = "mixed";
     auto add = [&key](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
-    const GridArgs args[10] = {defect, first1, first_last1, first2, first_last2, mid2[0], mid2[1],
-                               last2[0], last2[1], defect};
-    add(args, sizeof args);
+    add(&defect, sizeof defect);
+    add(first, sizeof first);
+    add(first_last, sizeof first_last);
+    add(mid, sizeof mid);
+    add(last, sizeof last);
     add(&cd, sizeof cd);
     add(&cs, sizeof cs);
     add(&cs2, sizeof cs2);
-    const long long meta[3] = {m_in, K, nt};
+    add(&cs3, sizeof cs3);
+    const long long meta[4] = {m_in, K, nt, step};
     add(meta, sizeof meta);
     const void* ptrs[3] = {s->partials, s->hist, s->ctl};
     add(ptrs, sizeof ptrs);

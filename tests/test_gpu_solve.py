@@ -9,6 +9,10 @@ from gpu_util import RESID_RTOL, needs_gpu, rel, say
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
+# pass lengths forced on the small test grids ("" lets the solver choose:
+# two-sweep and single passes there, three-sweep passes on large grids)
+STEPS = ["", "1", "3"]
+
 from paper_2409_18824_amd import j3d  # noqa: E402
 
 
@@ -30,8 +34,10 @@ def test_small_plain_100_sweeps_residual_every_sweep():
 
 
 @pytest.mark.parametrize("max_sweeps,check_every", [(0, 1), (7, 3), (10, 5), (1, 1), (10, 2), (9, 4), (1, 2),
-                                                   (3, 2), (0, 2)])
-def test_plain_cadence_edges(max_sweeps, check_every):
+                                                   (3, 2), (0, 2), (23, 10), (8, 3), (5, 9), (17, 8)])
+@pytest.mark.parametrize("step", STEPS)
+def test_plain_cadence_edges(max_sweeps, check_every, step, monkeypatch):
+    monkeypatch.setenv("J3D_SOLVE_SWEEPS_PER_PASS", step)
     n = (9, 11, 6)
     say("cadence", max_sweeps, check_every)
     u0 = synth.uniform_field(*n, 4, 1, 0, 1)
@@ -65,9 +71,12 @@ def test_plain_early_exit_matches_oracle():
 @pytest.mark.parametrize("n,inner,rtol,cap", [(24, 50, 1e-8, 100000), (13, 7, 1e-10, 100000),
                                               (16, 50, 1e-14, 120), (10, 1, 1e-3, 1000), (11, 2, 1e-9, 100000),
                                               (12, 3, 1e-9, 100000), (9, 4, 1e-9, 100000), (14, 6, 1e-12, 53),
-                                              (70, 50, 1e-7, 100000)])
-def test_mixed_matches_oracle(n, inner, rtol, cap):
-    say("mixed", n, inner, rtol, cap)
+                                              (70, 50, 1e-7, 100000), (15, 5, 1e-9, 100000),
+                                              (17, 9, 1e-10, 100000), (19, 10, 1e-9, 100000)])
+@pytest.mark.parametrize("step", STEPS)
+def test_mixed_matches_oracle(n, inner, rtol, cap, step, monkeypatch):
+    monkeypatch.setenv("J3D_SOLVE_SWEEPS_PER_PASS", step)
+    say("mixed", n, inner, rtol, cap, step)
     h = 1.0 / (n + 1)
     u0 = synth.uniform_field(n, n, n, 2, 1, 0, 1)
     f = synth.manufactured_f(n, n, n, h)
@@ -127,13 +136,15 @@ def test_warm_start_resume():
     assert np.array_equal(a.to_numpy(), b.to_numpy())
 
 
-@pytest.mark.parametrize("S,every", [(1234, 2), (1001, 1), (1200, 3), (999, 4)])
-def test_plain_graph_replay_and_tail(S, every):
+@pytest.mark.parametrize("S,every", [(1234, 2), (1001, 1), (1200, 3), (999, 4), (1100, 7), (997, 6), (1000, 10)])
+@pytest.mark.parametrize("step", STEPS)
+def test_plain_graph_replay_and_tail(S, every, step, monkeypatch):
     """Long solves replay a captured chunk graph, then finish directly: same
     iterate and history as the oracle, and again on a second call (cached
     graph)."""
+    monkeypatch.setenv("J3D_SOLVE_SWEEPS_PER_PASS", step)
     n = 24
-    say("graph replay", S, every)
+    say("graph replay", S, every, step)
     h = 1.0 / (n + 1)
     u0 = synth.uniform_field(n, n, n, 8, 1, 0, 1)
     f = synth.uniform_field(n, n, n, 8, 2, -1, 1)
@@ -147,9 +158,11 @@ def test_plain_graph_replay_and_tail(S, every):
         assert np.array_equal(du.to_numpy(), uo), "call %d" % rep
 
 
-def test_mixed_graph_replay_matches_oracle():
+@pytest.mark.parametrize("step", STEPS)
+def test_mixed_graph_replay_matches_oracle(step, monkeypatch):
+    monkeypatch.setenv("J3D_SOLVE_SWEEPS_PER_PASS", step)
     n = 24
-    say("mixed graph replay")
+    say("mixed graph replay", step)
     h = 1.0 / (n + 1)
     u0 = synth.uniform_field(n, n, n, 9, 1, 0, 1)
     f = synth.uniform_field(n, n, n, 9, 2, -1, 1)
@@ -161,3 +174,29 @@ def test_mixed_graph_replay_matches_oracle():
         assert res.sweeps == ro.sweeps == 5030 and len(res.history) == len(ro.history)
         assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
         assert np.array_equal(du.to_numpy(), uo), "call %d" % rep
+
+
+@pytest.mark.parametrize("mode,shape,every", [(j3d.MODE_FP64, (320, 300, 230), 5), (j3d.MODE_MIXED, (360, 350, 340), 7)])
+def test_large_grids_choose_three_sweep_passes(mode, shape, every, monkeypatch):
+    """Grids whose pass arrays overflow the cache (over 512 MB: FP64 u, w, f;
+    FP32 r, e0, e1) run three-sweep passes by themselves: same iterate and
+    history as the oracle."""
+    monkeypatch.delenv("J3D_SOLVE_SWEEPS_PER_PASS", raising=False)
+    nx, ny, nz = shape
+    say("large solve", mode, shape, every)
+    h = 1.0 / (max(shape) + 1)
+    u0 = synth.uniform_field(nx, ny, nz, 10, 1, 0, 1)
+    f = synth.uniform_field(nx, ny, nz, 10, 2, -1, 1)
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    if mode == j3d.MODE_FP64:
+        assert 24 * nx * ny * nz > 512e6
+        res = j3d.poisson_solve(du, df, h, rtol=0.0, max_sweeps=13, check_every=every)
+        uo, ro = oracle.solve_plain(u0, f, h, rtol=0.0, check_every=every, max_sweeps=13)
+    else:
+        assert 12 * nx * ny * nz > 512e6
+        res = j3d.poisson_solve(du, df, h, mode=j3d.MODE_MIXED, rtol=0.0, max_sweeps=2 * every,
+                                inner_sweeps=every)
+        uo, ro = oracle.solve_mixed(u0, f, h, rtol=0.0, inner=every, max_sweeps=2 * every)
+    assert res.sweeps == ro.sweeps and len(res.history) == len(ro.history)
+    assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
+    assert np.array_equal(du.to_numpy(), uo)
