@@ -3,17 +3,18 @@
 Default workload: 512^3 interior + halo, FP64, two ping-pong arrays plus f,
 u0 ~ U[0,1) (seed 2), f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z), h = 1/513;
 one step = 500 sweeps with the L2 residual fused into every 10th sweep
-(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  Each group of
-10 sweeps runs as two two-sweep passes, the first carrying the fused
-residual, and two three-sweep passes (jacobi3d_sweep3: the intermediate
-iterates stay on chip); --passes 2 runs 250 two-sweep passes instead,
---passes 1 500 single sweeps.  Throughput is grid-point updates per second (GLUP/s) over the timed
+(r_0, r_10, ..., r_490 fused, r_500 by a standalone pass).  The sweeps run
+as 166 three-sweep passes and a final two-sweep pass (jacobi3d_sweep3: the
+intermediate iterates stay on chip); the pass through which iterate 10g
+passes fuses its residual at the stage that forms it (the pass's input, or
+the iterate after its first or second sweep).  --passes 2 runs 250
+two-sweep passes instead, --passes 1 500 single sweeps.  Throughput is grid-point updates per second (GLUP/s) over the timed
 steps.
 
 The JSON line also carries
   roofline:     the dominant kernel (the multi-sweep pass without a fused
-                residual: the 100 three-sweep passes of a step, 54% of its
-                time), its average duration from HIP events on the stream it
+                residual: 116 of the 167 passes of a step), its average
+                duration from HIP events on the stream it
                 runs on, and its algorithmic bandwidth against the MI355X HBM
                 peak.  Algorithmic bytes per launch: 24 per interior point
                 (read u, read f, write the result) for every pass; a
@@ -73,6 +74,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def pass_plan(S: int, E: int, P: int):
+    """The passes of one step, in sweep order: (first sweep, sweeps in the
+    pass, residual stage).  Passes of P sweeps run straight through the S
+    sweeps; a pass through which iterate gE passes (g = 0, 1, ...) carries
+    its residual at the stage where that iterate is formed: 0 for the pass's
+    input, 1 or 2 for the iterate after its first or second sweep (three-sweep
+    passes only).  A shorter pass ends at the second residual point it would
+    hold, and a two-sweep pass whose second iterate is a residual point stops
+    before it; the last residual (iterate S, when E divides S) is left to a
+    standalone pass."""
+    plan = []
+    s = 0
+    while s < S:
+        m = min(P, S - s)
+        offs = [q * E - s for q in range(s // E, (s + m) // E + 1) if 0 <= q * E - s < m]
+        if len(offs) > 1:
+            m = offs[1]
+            offs = offs[:1]
+        if offs and offs[0] > 0 and m < 3:
+            m = offs[0]
+            offs = []
+        plan.append((s, m, offs[0] if offs else None))
+        s += m
+    return plan
+
+
 def measured_traffic(kernel_hash: str, passes: int, tile):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, if it was taken on the current kernel source with this tile
@@ -127,9 +154,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=500)
     ap.add_argument("--resid-every", type=int, default=10)
     ap.add_argument("--passes", type=int, default=3, choices=[1, 2, 3],
-                    help="sweeps per pass over memory (2, 3: temporally blocked passes; with 3 each residual "
-                         "group starts with two-sweep passes for E mod 3, the first carrying the residual, "
-                         "10 = 2+2+3+3)")
+                    help="sweeps per pass over memory (2, 3: temporally blocked passes, run straight through "
+                         "the step; residuals fused at the stage that forms their iterate)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="time the tile shapes first and use the fastest (default: the library's default "
@@ -177,42 +203,25 @@ def main():
     df = j3d.FArray.from_numpy(synth.manufactured_f(n, n, n, h))
     torch.cuda.synchronize()
     P = args.passes
-    if P == 2 and (E % 2 != 0 or S % 2 != 0):
-        raise SystemExit("two-sweep passes need even --sweeps and --resid-every")
-    if P == 3 and (S % E != 0 or E < 2):
-        raise SystemExit("three-sweep schedules need --sweeps a multiple of --resid-every >= 2")
     kind = {1: j3d.F64, 2: j3d.KIND_F64X2, 3: j3d.KIND_F64X3}[P]
+    plan = pass_plan(S, E, P)
+    lengths = sorted({m for _, m, _ in plan})
     if args.tile:
         j3d.j3d_tune_set_single(kind, n, n, n, tuple(int(x) for x in args.tile.split(",")))
     elif args.autotune:
         j3d.j3d_autotune_single(kind, n, n, n)
-        if P >= 2:
-            j3d.j3d_autotune_single(j3d.F64, n, n, n)  # the standalone residual pass
-        if P == 3 and E % 3 != 0:
-            j3d.j3d_autotune_single(j3d.KIND_F64X2, n, n, n)  # the two-sweep passes of each group
+        for m in lengths:  # the other pass lengths of the plan, and the standalone residual pass
+            if m != P:
+                j3d.j3d_autotune_single({1: j3d.F64, 2: j3d.KIND_F64X2}[m], n, n, n)
+        if 1 not in lengths:
+            j3d.j3d_autotune_single(j3d.F64, n, n, n)
     tune = j3d.j3d_tune_query_single(kind, n, n, n)  # the shape the timed passes use
     print("[bench] tile shape (rows, planes, variant, persistent, order, cols) = %s" % (tune,), file=sys.stderr, flush=True)
 
     nres = S // E + 1
     resid = torch.zeros(nres, dtype=torch.float64, device="cuda")
     sweeps_of = {1: j3d.jacobi3d_sweep, 2: j3d.jacobi3d_sweep2, 3: j3d.jacobi3d_sweep3}
-    # passes in sweep order: (first sweep, sweeps in the pass); a pass that
-    # starts a residual group carries the fused residual of its input
-    if P == 3:
-        # the remainder of E mod 3 runs first, in two-sweep passes whose first
-        # carries the group's fused residual (10 = 2+2+3+3; a single sweep
-        # leaves eight times as many per-tile partials to reduce)
-        n3, rem = divmod(E, 3)
-        group = [2, 2] + [3] * (n3 - 1) if (rem == 1 and n3 >= 1) else ([rem] if rem else []) + [3] * n3
-        plan = []
-        for g0 in range(0, S, E):
-            s = g0
-            for m in group:
-                plan.append((s, m))
-                s += m
-    else:
-        plan = [(s, P) for s in range(0, S, P)]
-    n_plain = sum(1 for s, m in plan if s % E != 0 and m == P)
+    n_plain = sum(1 for _, m, st in plan if st is None and m == P)
     events = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(n_plain)] for _ in range(args.steps)]
 
@@ -222,10 +231,14 @@ def main():
         cur, nxt = state["cur"], state["nxt"]
         timed = ev is not None
         q = 0
-        for s, m in plan:
+        for s, m, stage in plan:
             sweep = sweeps_of[m]
-            if s % E == 0:
-                sweep(cur, nxt, df, h, resid_out=resid[s // E:s // E + 1])
+            if stage is not None:
+                g = (s + stage) // E
+                if stage == 0:
+                    sweep(cur, nxt, df, h, resid_out=resid[g:g + 1])
+                else:
+                    sweep(cur, nxt, df, h, resid_out=resid[g:g + 1], resid_after=stage)
             elif timed and m == P:
                 ev[q][0].record()
                 sweep(cur, nxt, df, h)
@@ -299,7 +312,9 @@ def main():
         "config": {"workload": "jacobi3d-7pt-fp64-%dcubed-%dsweeps-resid%d" % (n, S, E),
                    "grid": [n, n, n], "halo": 1, "layout": "fortran-column-major",
                    "sweeps_per_step": S, "resid_every": E, "sweeps_per_pass": P,
-                   "passes_per_residual_group": [m for s, m in plan if s < E], "tile": tune,
+                   "passes_by_length": {str(m): sum(1 for _, x, _ in plan if x == m) for m in lengths},
+                   "residuals_fused_at_stage": [sum(1 for _, _, st in plan if st == k) for k in range(3)],
+                   "tile": tune,
                    "single_sweep_equivalent_gbs": round(glups * BYTES_PER_LUP_F64, 1)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -80,6 +80,11 @@ extern "C" {
 
 /* flags for jacobi3d_sweep */
 #define J3D_HOST_RESULT 1u  /* resid_out is a host pointer; the call waits for the stream */
+/* flags for jacobi3d_sweep3: the fused residual is that of the iterate after
+ * the pass's first sweep, J(u_in), or after its second, J(J(u_in)), instead
+ * of u_in's (at most one of the two) */
+#define J3D_RESID_AFTER_1 2u
+#define J3D_RESID_AFTER_2 4u
 
 /*
  * A Fortran array u(lbound[0]:ubound[0], lbound[1]:ubound[1], lbound[2]:ubound[2]).
@@ -151,7 +156,11 @@ int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
  * jacobi3d_sweep calls).  The two intermediate iterates stay on chip, so the
  * pass streams u_in and f once and writes u_out once for three sweeps' worth
  * of updates.  resid_out and flags as in jacobi3d_sweep (the residual of
- * u_in; FP64 only).
+ * u_in; FP64 only), and with J3D_RESID_AFTER_1 or J3D_RESID_AFTER_2 the
+ * residual of the first or second intermediate iterate, formed on chip from
+ * the same neighbour sum that produces the next sweep (so a fixed-length
+ * run of three-sweep passes can report the residual of any iterate it
+ * passes through; EINVAL if both are set or without resid_out).
  */
 int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
                     double h, uint32_t flags, double* resid_out, void* stream);

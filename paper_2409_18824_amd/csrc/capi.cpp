@@ -249,11 +249,17 @@ int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
   J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
   J3D_TRY(check_same_interior(a, c, "u_in", "f"));
   J3D_TRY(check_h(h));
-  if ((flags & ~J3D_HOST_RESULT) != 0) return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & ~(J3D_HOST_RESULT | J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2)) != 0)
+    return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  const unsigned after = flags & (J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2);
+  if (after == (J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2))
+    return fail(J3D_EINVAL, "J3D_RESID_AFTER_1 and J3D_RESID_AFTER_2 are exclusive");
+  if (after != 0 && resid_out == nullptr) return fail(J3D_EINVAL, "J3D_RESID_AFTER_*: resid_out is null");
   if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
   if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
   if (resid_out != nullptr && a.dtype != J3D_F64)
     return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
+  const unsigned res_flag = after == J3D_RESID_AFTER_1 ? F_RES1 : after == J3D_RESID_AFTER_2 ? F_RES2 : F_RES;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const TileCfg cfg = default_cfg3(a.dtype, a.nx(), a.ny(), a.nz());
   GridArgs g = make_args3(&a, &b, &c, nullptr, h, cfg, 0);
@@ -265,7 +271,7 @@ int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
   J3D_TRY(get_scratch(st, &s));
   const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
-  J3D_HIP(launch_sweep3_one(J3D_F64, F_WRITE | F_RES, cfg, g, s->partials, nullptr, st));
+  J3D_HIP(launch_sweep3_one(J3D_F64, F_WRITE | res_flag, cfg, g, s->partials, nullptr, st));
   const bool host = (flags & J3D_HOST_RESULT) != 0;
   double* dst = host ? &s->ctl->value : resid_out;
   J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));

@@ -41,6 +41,8 @@ enum : unsigned {
   F_FIRST = 8u,   // the input iterate is identically zero (not read)
   F_LAST = 16u,   // add (double) update to u64 instead of writing o
   F_NORM = 32u,   // accumulate sum of f^2 only
+  F_RES1 = 64u,   // three-sweep pass: sum of r^2 of the iterate after its first sweep (FP64)
+  F_RES2 = 128u,  // three-sweep pass: sum of r^2 of the iterate after its second sweep (FP64)
 };
 
 struct TileCfg {

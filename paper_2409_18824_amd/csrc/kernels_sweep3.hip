@@ -1,5 +1,6 @@
 // Instantiations of the FP64 three-sweep pass: plain sweeps, optionally
-// with the fused residual of the input iterate.
+// with the fused residual of the input iterate or of either intermediate
+// iterate.
 #include "sweep3.h"
 
 namespace j3d {
@@ -10,6 +11,8 @@ hipError_t dispatch_sweep3_f64(unsigned flags, const TileCfg& c, const GridArgs&
   switch (flags) {
     case F_WRITE: return by_shape3<double, F_WRITE>(c, g, partials, done, st);
     case F_WRITE | F_RES: return by_shape3<double, F_WRITE | F_RES>(c, g, partials, done, st);
+    case F_WRITE | F_RES1: return by_shape3<double, F_WRITE | F_RES1>(c, g, partials, done, st);
+    case F_WRITE | F_RES2: return by_shape3<double, F_WRITE | F_RES2>(c, g, partials, done, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -21,7 +21,10 @@
 // Each point of u1, u2 and u3 is computed with exactly the arithmetic of a
 // single sweep (same neighbour order, no contraction), so the result equals
 // three separate sweeps bit for bit.  The fused residual, when requested, is
-// that of u0 (the input), accumulated by the output columns only.
+// that of u0 (F_RES, in stage 1), u1 (F_RES1, stage 2) or u2 (F_RES2,
+// stage 3): each stage's neighbour sum is exactly the one the residual of
+// its input needs.  Only the output columns accumulate it, plane by plane
+// in increasing z whichever the stage.
 #pragma once
 
 #include "sweep.h"
@@ -41,8 +44,9 @@ struct Smem3 {
 };
 
 // Flags as for the two-sweep pass: F_WRITE (store u3 to g.o), F_RES (FP64:
-// residual of u0), F_FIRST (u0 is identically zero and not read), F_LAST
-// (add (double) u3 to g.u64 instead of storing it).
+// residual of u0; F_RES1, F_RES2: of u1, u2), F_FIRST (u0 is identically
+// zero and not read), F_LAST (add (double) u3 to g.u64 instead of storing
+// it).
 template <typename T, int BY, int VAR, unsigned FL>
 __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __restrict__ partials,
                                             Smem3<T, BY>& sm) {
@@ -53,7 +57,10 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   constexpr bool NT = (VAR & 4) != 0;
   constexpr bool ZERO = (FL & F_FIRST) != 0;
   static_assert(TR >= 5, "a block needs at least one output row");
-  static_assert(!(FL & F_RES) || sizeof(T) == 8, "the fused residual is an FP64 pass");
+  constexpr unsigned RES_ANY = FL & (F_RES | F_RES1 | F_RES2);
+  static_assert(RES_ANY == 0 || sizeof(T) == 8, "the fused residual is an FP64 pass");
+  static_assert(RES_ANY == 0 || RES_ANY == F_RES || RES_ANY == F_RES1 || RES_ANY == F_RES2,
+                "one fused residual per pass");
   const int lane = threadIdx.x;
   const int wy = threadIdx.y;
   const int tx = t % g.tiles_x;
@@ -166,6 +173,11 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
         s = s + u1[r];
         const bool pt_in = col_in[r] && k - 1 >= 1 && k - 1 <= g.nz;
         u2[r] = (pt_in && inner2[r]) ? div6(s + h2 * fm1[r]) : u1m1[r];
+        if (FL & F_RES1) {
+          const double res = static_cast<double>(fm1[r]) -
+                             (6.0 * static_cast<double>(u1m1[r]) - static_cast<double>(s)) / g.h2;
+          acc += (inner3[r] && pt_in && k - 1 >= k0 && k - 1 < k1) ? res * res : 0.0;
+        }
       }
     }
     // stage 3: u3 at plane k-2 (from u2 at k-3, k-2, k-1); the u2 edge rows
@@ -186,6 +198,11 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
           s = s + u2m2[r];
           s = s + u2[r];
           const T u3 = div6(s + h2 * fm2[r]);
+          if (FL & F_RES2) {
+            const double res = static_cast<double>(fm2[r]) -
+                               (6.0 * static_cast<double>(u2m1[r]) - static_cast<double>(s)) / g.h2;
+            acc += col_in[r] ? res * res : 0.0;
+          }
           if (col_in[r]) {
             if (FL & F_LAST) {
               double* q = u64 + co[r] + g.s64_z * (k - 2);
@@ -212,7 +229,7 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     }
   }
 
-  if (FL & F_RES) {
+  if (RES_ANY != 0) {
     const double tot = block_sum<BY>(acc, sm.red);
     if (wy == 0 && lane == 0) partials[g.tile0 + t] = tot;
   }

@@ -31,6 +31,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 F64, F32 = 0, 1
 OK, EINVAL, EDTYPE, EALIAS, ENOMEM, EBUDGET, EHIP, ENONFINITE, EAGAIN, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 HOST_RESULT = 1
+RESID_AFTER_1 = 2  # jacobi3d_sweep3: residual of the iterate after the pass's first sweep
+RESID_AFTER_2 = 4  # ... after its second sweep
 MODE_FP64, MODE_MIXED = 0, 1
 KIND_F64X2 = 2  # tuning kind of the two-sweep FP64 pass
 KIND_F32X2 = 3  # tuning kind of the two-sweep FP32 pass (also the mixed solve's correction sweeps)
@@ -333,8 +335,11 @@ def jacobi3d_sweep2(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=
 
 
 def jacobi3d_sweep3(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=None, host_result=False,
-                    stream=None, flags: int = 0):
-    """Three sweeps in one pass: u_out = J(J(J(u_in))).  Residual (of u_in) as in jacobi3d_sweep."""
+                    stream=None, flags: int = 0, resid_after: int = 0):
+    """Three sweeps in one pass: u_out = J(J(J(u_in))).  Residual as in jacobi3d_sweep, of u_in
+    (resid_after=0) or of the iterate after the pass's first or second sweep (resid_after=1, 2)."""
+    if resid_after:
+        flags |= {1: RESID_AFTER_1, 2: RESID_AFTER_2}[resid_after]
     a, b, c = u_in.desc(), u_out.desc(), f.desc()
     st = _stream_handle(stream)
     if host_result:

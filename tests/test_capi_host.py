@@ -343,3 +343,16 @@ def test_three_sweep_kind_defaults_and_validation():
     r = ctypes.c_double()
     assert lib.jacobi3d_sweep3(ctypes.byref(a32), ctypes.byref(b32), ctypes.byref(c32), 0.1, j3d.HOST_RESULT,
                                ctypes.cast(ctypes.byref(r), ctypes.c_void_p), None) == j3d.EDTYPE
+    rp = ctypes.cast(ctypes.byref(r), ctypes.c_void_p)
+    both = j3d.HOST_RESULT | j3d.RESID_AFTER_1 | j3d.RESID_AFTER_2
+    assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, both, rp, None) == j3d.EINVAL
+    assert "exclusive" in j3d.last_error()
+    assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, j3d.RESID_AFTER_2, None,
+                               None) == j3d.EINVAL
+    assert "resid_out" in j3d.last_error()
+    assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, 8, rp, None) == j3d.EINVAL
+    assert lib.jacobi3d_sweep3(ctypes.byref(a32), ctypes.byref(b32), ctypes.byref(c32), 0.1,
+                               j3d.HOST_RESULT | j3d.RESID_AFTER_1, rp, None) == j3d.EDTYPE
+    # the other sweep entries know no residual-stage flags
+    assert lib.jacobi3d_sweep2(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, j3d.RESID_AFTER_1, rp,
+                               None) == j3d.EINVAL

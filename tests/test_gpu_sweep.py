@@ -126,6 +126,32 @@ def test_sweep3_equals_three_sweeps(shape, tune):
     assert np.array_equal(du.to_numpy(), u)  # input untouched
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 5), (59, 12, 10), (117, 30, 17), (17, 45, 64), (200, 28, 3)])
+@pytest.mark.parametrize("tune", [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (2, 3, 20, 0, 2, 1)])
+@pytest.mark.parametrize("after", [1, 2])
+def test_sweep3_residual_of_intermediate_iterates(shape, tune, after):
+    """The residual fused at stage 2 or 3 of the pass is that of J(u) or
+    J(J(u)); the output is still three sweeps."""
+    nx, ny, nz = shape
+    say("sweep3 resid after", after, shape, tune)
+    u, f, h = make_inputs(nx, ny, nz, seed=11)
+    j3d.j3d_tune_set_single(j3d.KIND_F64X3, nx, ny, nz, tune)
+    du = j3d.FArray.from_numpy(u)
+    dv = j3d.FArray.from_numpy(u)
+    dv.view()[1:-1, 1:-1, 1:-1] = -7.0
+    df = j3d.FArray.from_numpy(f, ld_extra=3)
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r, resid_after=after)
+    hr = j3d.jacobi3d_sweep3(du, dv, df, h, host_result=True, resid_after=after)
+    torch.cuda.synchronize()
+    u1 = oracle.sweep(u, f, h)
+    u2 = oracle.sweep(u1, f, h)
+    assert np.array_equal(dv.to_numpy(), oracle.sweep(u2, f, h))
+    want = oracle.residual_l2(u1 if after == 1 else u2, f, h)
+    assert rel(float(r.item()), want) <= RESID_RTOL
+    assert float(r.item()) == hr  # same kernel, same partials, same reduction
+
+
 @pytest.mark.parametrize("shape", [(70, 13, 21), (1, 1, 1), (130, 40, 9), (58, 14, 33)])
 @pytest.mark.parametrize("tune", [(8, 32, 20, 0, 1, 1), (4, 16, 6, 0, 0, 1), (2, 8, 20, 0, 2, 1)])
 def test_sweep3_fp32_equals_three_fp32_sweeps(shape, tune):
@@ -155,13 +181,18 @@ def test_sweep3_full_size_512():
     dv = j3d.FArray.empty(n, n, n)
     df = j3d.FArray.from_numpy(f)
     say("tile", j3d.j3d_tune_query_single(j3d.KIND_F64X3, n, n, n))
-    r = torch.zeros(1, dtype=torch.float64, device="cuda")
-    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r)
+    r = torch.zeros(3, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r[0:1])
+    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r[1:2], resid_after=1)
+    j3d.jacobi3d_sweep3(du, dv, df, h, resid_out=r[2:3], resid_after=2)
     torch.cuda.synchronize()
     u = du.to_numpy()
-    want = oracle.sweep(oracle.sweep(oracle.sweep(u, f, h), f, h), f, h)
+    u1 = oracle.sweep(u, f, h)
+    u2 = oracle.sweep(u1, f, h)
+    want = oracle.sweep(u2, f, h)
     assert np.array_equal(dv.to_numpy()[1:-1, 1:-1, 1:-1], want[1:-1, 1:-1, 1:-1])
-    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+    for q, it in enumerate((u, u1, u2)):
+        assert rel(float(r[q].item()), oracle.residual_l2(it, f, h)) <= RESID_RTOL
 
 
 def test_sweep2_shapes_with_wide_tiles_rejected():
