@@ -347,7 +347,7 @@ def run_mixed(args):
     df = j3d.FArray.from_numpy(f)
     u = j3d.FArray.empty(n, n, n)
     if args.autotune:
-        for kind in (j3d.F64, j3d.F32, j3d.KIND_F64X2, j3d.KIND_F32X2):
+        for kind in (j3d.F64, j3d.F32, j3d.KIND_F64X2, j3d.KIND_F32X2, j3d.KIND_F64X3, j3d.KIND_F32X3):
             j3d.j3d_autotune_single(kind, n, n, n)
     res = {}
     chunk = max(50, args.chunk_sweeps // 50 * 50)

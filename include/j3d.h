@@ -363,16 +363,21 @@ int j3d_tune_get(int32_t index, j3d_tune* out);
  * ngrids * (nsweeps/resid_every + 1) doubles: row g holds ||f - A u||_2 of
  * grid g after sweeps 0, e, 2e, ... (e = resid_every), fused into the
  * following sweep where there is one.  Each grid's numbers equal those of
- * the same grid swept alone with the same tile shapes and pass kind (one or
- * two sweeps per pass, below), bit for bit; the iterates are the same bit
- * for bit in every case.
+ * the same grid swept alone with the same tile shapes and pass kind (one,
+ * two or up to three sweeps per pass, below), bit for bit; the iterates are
+ * the same bit for bit in every case, the residual norms agree to rounding.
  * tune = NULL selects the tile shape with the autotuner (timed once per
  * batch shape class and cached; J3D_TUNE_CACHE names an optional file).
  * When nsweeps >= 2 and resid_every is even (or resid_out is NULL), sweeps
  * run two per pass over memory (as jacobi3d_sweep2) if that is faster on
  * this batch shape class, timed once per process; the environment variable
- * J3D_BATCH_PAIRS=0 or =1 forces one-sweep or two-sweep passes.  Results
- * are the same bit for bit either way.
+ * J3D_BATCH_PAIRS=0 or =1 forces one-sweep or two-sweep passes.  When
+ * nsweeps >= 3 and the three-sweep pass (as jacobi3d_sweep3) is faster per
+ * sweep than those, the call runs three-sweep passes straight through, for
+ * any resid_every: each residual is fused into the pass that forms its
+ * iterate, at that stage of the pass (a shorter pass covers the rest, and
+ * one pass is split when needed to keep the u_a/u_b placement above);
+ * J3D_BATCH_TRIPLES=0 or =1 forces this off or on.
  */
 int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
                          int32_t resid_every, double* resid_out, const j3d_tune* tune,

@@ -201,16 +201,90 @@ void build_tables2(const BatchFields& bf, const TileCfg& c2, std::vector<GridArg
   *ntiles = tile0;
 }
 
+// Three-sweep tables (their own tile numbering): tab3[0]: u_a -> u_b,
+// tab3[1]: u_b -> u_a.
+void build_tables3(const BatchFields& bf, const TileCfg& c3, std::vector<GridArgs> tab3[2], int* ntiles) {
+  const int n = (int)bf.a.size();
+  for (int t = 0; t < 2; ++t) tab3[t].resize(n);
+  int tile0 = 0;
+  for (int g = 0; g < n; ++g) {
+    tab3[0][g] = make_args3(&bf.a[g], &bf.b[g], &bf.f[g], nullptr, bf.h[g], c3, tile0);
+    tab3[1][g] = make_args3(&bf.b[g], &bf.a[g], &bf.f[g], nullptr, bf.h[g], c3, tile0);
+    tab3[0][g].id = tab3[1][g].id = g;
+    tile0 += tab3[0][g].tiles_x * tab3[0][g].tiles_y * tab3[0][g].tiles_z;
+  }
+  *ntiles = tile0;
+}
+
+// The passes of a call with three-sweep passes: (sweeps in the pass, stage
+// of the residual it carries or -1).  Passes run straight through the call
+// (a batch has no early exit); the pass through which iterate q*E passes
+// carries its residual at the stage that forms it: 0 for the pass's input,
+// 1 or 2 for the iterate after its first or second sweep (three-sweep
+// passes form both on chip).  A pass ends at the second residual point it
+// would hold, and a shorter pass whose later iterate is a residual point
+// stops before it.  When the pass count has the wrong parity (the result
+// must land in u_a exactly when S is even) the last pass of two or more
+// sweeps is split in two.  E = 0: no residuals.
+struct PassStep {
+  int m;
+  int stage;
+};
+
+std::vector<PassStep> triple_schedule(int S, int E) {
+  std::vector<PassStep> v;
+  for (int s = 0; s < S;) {
+    int m = std::min(3, S - s);
+    int offs[3];
+    int no = 0;
+    for (int o = 0; E > 0 && o < m; ++o)
+      if ((s + o) % E == 0) offs[no++] = o;
+    if (no > 1) {
+      m = offs[1];
+      no = 1;
+    }
+    if (no == 1 && offs[0] > 0 && m < 3) {
+      m = offs[0];
+      no = 0;
+    }
+    v.push_back(PassStep{m, no == 1 ? offs[0] : -1});
+    s += m;
+  }
+  if ((int)(v.size() & 1) != (S & 1)) {
+    for (size_t i = v.size(); i-- > 0;) {
+      const PassStep q = v[i];
+      if (q.m < 2) continue;
+      PassStep a, b;
+      if (q.m == 3 && q.stage == 2) {
+        a = PassStep{2, -1};
+        b = PassStep{1, 0};
+      } else if (q.m == 3) {
+        a = PassStep{1, q.stage == 0 ? 0 : -1};
+        b = PassStep{2, q.stage == 1 ? 0 : -1};
+      } else {
+        a = PassStep{1, q.stage};
+        b = PassStep{1, -1};
+      }
+      v[i] = a;
+      v.insert(v.begin() + (long)i + 1, b);
+      break;
+    }
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------------
 // Plans (device tables + captured graph), cached per call signature
 // ---------------------------------------------------------------------
 struct Plan {
   std::string key;
   int device = 0;
-  int ngrids = 0, ntiles = 0, ntiles2 = 0;
+  int ngrids = 0, ntiles = 0, ntiles2 = 0, ntiles3 = 0;
   bool pairs = false;       // two sweeps per pass where the cadence allows
+  bool triples = false;     // passes of up to three sweeps (triple_schedule)
   TileCfg c2{};             // tile shape of the two-sweep passes
-  GridArgs* tab = nullptr;  // device: 4 * ngrids one-sweep, then 2 * ngrids two-sweep entries
+  TileCfg c3{};             // tile shape of the three-sweep passes
+  GridArgs* tab = nullptr;  // device: 4 * ngrids one-sweep, 2 * ngrids two-sweep, 2 * ngrids three-sweep entries
   double* partials = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -272,14 +346,39 @@ int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, doubl
     buf ^= 1;
     return J3D_OK;
   };
-  int npairs = p.pairs ? nsweeps / 2 : 0;
-  if (npairs & 1) {
-    J3D_TRY(one());
-    J3D_TRY(one());
-    --npairs;
+  if (p.triples) {
+    for (const PassStep& ps : triple_schedule(nsweeps, resid_out ? every : 0)) {
+      const bool check = ps.stage >= 0;
+      const GridArgs* t;
+      if (ps.m == 3) {
+        t = p.tab + (size_t)(6 + buf) * n;
+        const unsigned rf = !check ? 0u : ps.stage == 0 ? F_RES : ps.stage == 1 ? F_RES1 : F_RES2;
+        J3D_HIP(launch_sweep3_batch(F_WRITE | rf, p.c3, t, n, p.ntiles3, p.partials, nullptr, st));
+      } else if (ps.m == 2) {
+        t = p.tab + (size_t)(4 + buf) * n;
+        J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), p.c2, t, n, p.ntiles2,
+                                    p.partials, nullptr, st));
+      } else {
+        t = p.tab + (size_t)buf * n;
+        J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), c, t, n, p.ntiles, p.partials,
+                                  nullptr, st));
+      }
+      if (check)
+        J3D_HIP(launch_reduce_batch(p.partials, t, n, resid_out, nres, (s + ps.stage) / every, nullptr, nullptr,
+                                    0, nullptr, nullptr, nullptr, st));
+      s += ps.m;
+      buf ^= 1;
+    }
+  } else {
+    int npairs = p.pairs ? nsweeps / 2 : 0;
+    if (npairs & 1) {
+      J3D_TRY(one());
+      J3D_TRY(one());
+      --npairs;
+    }
+    for (int q = 0; q < npairs; ++q) J3D_TRY(two());
+    while (s < nsweeps) J3D_TRY(one());
   }
-  for (int q = 0; q < npairs; ++q) J3D_TRY(two());
-  while (s < nsweeps) J3D_TRY(one());
   if (resid_out && nsweeps % every == 0) {
     const GridArgs* t = p.tab + (size_t)(2 + buf) * n;
     J3D_HIP(launch_pass_batch(J3D_F64, F_RES, c, t, n, p.ntiles, p.partials, nullptr, st));
@@ -290,7 +389,7 @@ int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, doubl
 }
 
 int make_plan(const std::string& key, const BatchFields& bf, const TileCfg& c, bool pairs, const TileCfg& c2,
-              int nsweeps, int every, double* resid_out, Plan** out) {
+              bool triples, const TileCfg& c3, int nsweeps, int every, double* resid_out, Plan** out) {
   int dev = 0;
   J3D_HIP(hipGetDevice(&dev));
   Plan* p = new Plan();
@@ -299,17 +398,22 @@ int make_plan(const std::string& key, const BatchFields& bf, const TileCfg& c, b
   p->ngrids = (int)bf.a.size();
   p->pairs = pairs;
   p->c2 = c2;
-  std::vector<GridArgs> tab[4], tab2[2];
+  p->triples = triples;
+  p->c3 = c3;
+  std::vector<GridArgs> tab[4], tab2[2], tab3[2];
   build_tables(bf, c, tab, &p->ntiles);
   build_tables2(bf, c2, tab2, &p->ntiles2);
+  build_tables3(bf, c3, tab3, &p->ntiles3);
   std::vector<GridArgs> flat;
   for (int t = 0; t < 4; ++t) flat.insert(flat.end(), tab[t].begin(), tab[t].end());
   for (int t = 0; t < 2; ++t) flat.insert(flat.end(), tab2[t].begin(), tab2[t].end());
+  for (int t = 0; t < 2; ++t) flat.insert(flat.end(), tab3[t].begin(), tab3[t].end());
   void* mem = nullptr;
   int rc = dev_alloc(&mem, flat.size() * sizeof(GridArgs), "batch table");
   if (rc == J3D_OK) {
     p->tab = static_cast<GridArgs*>(mem);
-    rc = dev_alloc(&mem, (size_t)std::max(p->ntiles, p->ntiles2) * sizeof(double), "batch partials");
+    rc = dev_alloc(&mem, (size_t)std::max(p->ntiles, std::max(p->ntiles2, p->ntiles3)) * sizeof(double),
+                   "batch partials");
   }
   if (rc == J3D_OK) p->partials = static_cast<double*>(mem);
   if (rc != J3D_OK) {
@@ -607,6 +711,67 @@ int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, bool keep_c2
   return rc;
 }
 
+// Tunes the three-sweep batched pass (or, with keep_c3, times the shape in
+// *best3 only) and decides whether it beats the passes the batch would run
+// otherwise: two-sweep passes of shape c2 when `pairs`, else one-sweep
+// passes of shape c, compared per sweep.
+int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, const TileCfg& c2, bool keep_c3,
+                           TileCfg* best3, bool* use, hipStream_t st) {
+  const int n = (int)bf.a.size();
+  GridArgs* dtab = nullptr;
+  double* parts = nullptr;
+  int part_cap = 0;
+  int rc = dev_alloc(reinterpret_cast<void**>(&dtab), (size_t)n * sizeof(GridArgs), "tune table");
+  if (rc != J3D_OK) return rc;
+  auto upload = [&](const std::vector<GridArgs>& tab, int nt) -> int {
+    if (nt > part_cap) {
+      if (parts) (void)hipFree(parts);
+      parts = nullptr;
+      J3D_TRY(dev_alloc(reinterpret_cast<void**>(&parts), (size_t)nt * sizeof(double), "tune partials"));
+      part_cap = nt;
+    }
+    J3D_HIP(hipMemcpyAsync(dtab, tab.data(), (size_t)n * sizeof(GridArgs), hipMemcpyHostToDevice, st));
+    J3D_HIP(hipStreamSynchronize(st));
+    return J3D_OK;
+  };
+  auto launch3 = [&](const TileCfg& k3) -> int {
+    std::vector<GridArgs> tab3[2];
+    int nt = 0;
+    build_tables3(bf, k3, tab3, &nt);
+    J3D_TRY(upload(tab3[0], nt));
+    J3D_HIP(launch_sweep3_batch(F_WRITE, k3, dtab, n, nt, parts, nullptr, st));
+    return J3D_OK;
+  };
+  auto launch2 = [&](const TileCfg& k2) -> int {
+    std::vector<GridArgs> tab2[2];
+    int nt = 0;
+    build_tables2(bf, k2, tab2, &nt);
+    J3D_TRY(upload(tab2[0], nt));
+    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE, k2, dtab, n, nt, parts, nullptr, st));
+    return J3D_OK;
+  };
+  auto launch1 = [&](const TileCfg& k1) -> int {
+    std::vector<GridArgs> tab[4];
+    int nt = 0;
+    build_tables(bf, k1, tab, &nt);
+    J3D_TRY(upload(tab[0], nt));
+    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, k1, dtab, n, nt, parts, nullptr, st));
+    return J3D_OK;
+  };
+  float t3 = 0.f, tother = 0.f;
+  const std::vector<TileCfg> cand3 = keep_c3 ? std::vector<TileCfg>{*best3} : sweep3_candidates(J3D_F64);
+  rc = time_list(st, best3, cand3, launch3, &t3);
+  TileCfg other = pairs ? c2 : c;
+  if (rc == J3D_OK)
+    rc = pairs ? time_list(st, &other, std::vector<TileCfg>{c2}, launch2, &tother)
+               : time_list(st, &other, std::vector<TileCfg>{c}, launch1, &tother);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(dtab);
+  if (parts) (void)hipFree(parts);
+  *use = t3 / 3.f < tother / (pairs ? 2.f : 1.f);
+  return rc;
+}
+
 }  // namespace j3d
 
 using namespace j3d;
@@ -658,16 +823,43 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
       if (mode == 1) pairs = true;
     }
   }
+  // Passes of up to three sweeps (any residual cadence: residuals are fused
+  // at the stage that forms their iterate) when the three-sweep pass beats
+  // the passes chosen above, per sweep, on this batch (decided once per
+  // batch shape class).  J3D_BATCH_TRIPLES=0 / =1 turns the choice off / on
+  // regardless of timing; an explicit tile shape is used for the
+  // three-sweep passes when that kernel has it.
+  bool triples = false;
+  TileCfg c3 = default_cfg3(J3D_F64, 64, 64, 64);
+  if (tune != nullptr && tile3_cfg_supported(J3D_F64, c)) c3 = c;
+  const char* force3 = getenv("J3D_BATCH_TRIPLES");
+  const int mode3 = (force3 && *force3 == '0') ? 0 : (force3 && *force3 == '1') ? 1 : -1;
+  if (mode3 != 0 && nsweeps >= 3) {
+    if (mode3 == 1 && tune != nullptr) {
+      triples = true;
+    } else {
+      char sig[64];
+      snprintf(sig, sizeof sig, ":x3:%d:%d", tune != nullptr ? 1 : 0, pairs ? 1 : 0);
+      const std::string k3 = batch_key(ngrids, bf.a.data()) + sig;
+      if (!pair_lookup(k3, &c3, &triples)) {
+        J3D_TRY(autotune_batch3_fields(bf, c, pairs, c2, tune != nullptr, &c3, &triples, st));
+        pair_store(k3, c3, triples);
+      }
+      if (mode3 == 1) triples = true;
+    }
+  }
   // Plan key: every descriptor, h, counts, output and tile shapes.
   std::string key;
   key.append(reinterpret_cast<const char*>(grids), sizeof(j3d_grid) * (size_t)ngrids);
   int dev = 0;
   J3D_HIP(hipGetDevice(&dev));
-  const long long meta[10] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
+  const long long meta[12] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
                               c.rows * 1000000LL + c.planes * 1000 + c.variant * 10 + c.persistent,
                               dev, c.order, c.cols,
                               pairs ? 1 + c2.rows * 1000000LL + c2.planes * 1000 + c2.variant * 10 : 0,
-                              c2.order * 10 + c2.cols};
+                              c2.order * 10 + c2.cols,
+                              triples ? 1 + c3.rows * 1000000LL + c3.planes * 1000 + c3.variant * 10 : 0,
+                              c3.order};
   key.append(reinterpret_cast<const char*>(meta), sizeof meta);
   Plan* plan = nullptr;
   {
@@ -678,7 +870,7 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
         break;
       }
     if (plan == nullptr) {
-      J3D_TRY(make_plan(key, bf, c, pairs, c2, nsweeps, resid_every, resid_out, &plan));
+      J3D_TRY(make_plan(key, bf, c, pairs, c2, triples, c3, nsweeps, resid_every, resid_out, &plan));
       if (g_plans.size() >= kMaxPlans) {
         auto it = std::min_element(g_plans.begin(), g_plans.end(),
                                    [](Plan* x, Plan* y) { return x->stamp < y->stamp; });

@@ -254,6 +254,30 @@ __global__ void __launch_bounds__(WAVE * BY)
   }
 }
 
+// The three-sweep pass over a table of grids: grid g owns tiles
+// [table[g].tile0, table[g].tile0 + tiles(g)) of one flat list (found by
+// binary search over tile0), as the two-sweep batched pass.
+template <typename T, int BY, int VAR, unsigned FL>
+__global__ void __launch_bounds__(WAVE * BY)
+    k_sweep3_batch(const GridArgs* __restrict__ table, int ngrids, int ntiles, double* __restrict__ partials,
+                   const int* __restrict__ done, int order, int chunk) {
+  __shared__ Smem3<T, BY> sm;
+  const int nv = order == 0 ? ntiles : virtual_tiles(ntiles, order, chunk);
+  const int first = order == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  for (int vb = first; vb < nv; vb += gridDim.x) {
+    const int t = order == 2 ? xcd_chunked(vb, chunk) : vb;
+    if (t >= ntiles) continue;
+    int lo = 0, hi = ngrids - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (table[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    if (done != nullptr && done[table[lo].id] != 0) continue;
+    const GridArgs g = table[lo];
+    sweep3_tile<T, BY, VAR, FL>(g, t - g.tile0, partials, sm);
+  }
+}
+
 // Instantiated three-sweep shapes: one wavefront along x, blocks of 8 to 32
 // rows, 2 or 4 rows per thread, nontemporal stores.
 constexpr bool shape3_instantiated(int by, int var) {
@@ -270,6 +294,37 @@ hipError_t go3(const GridArgs& g, double* partials, const int* done, hipStream_t
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep3_one<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, st, g, partials, done);
     return hipGetLastError();
+  }
+}
+
+// Batched launch: one workgroup per tile of the flat list (order 0 remaps
+// blocks to XCDs, order 2 chunks the list per XCD in runs of kBatchChunk).
+template <typename T, int BY, int VAR, unsigned FL>
+hipError_t go3_batch(const TileCfg& c, const GridArgs* table, int ngrids, int ntiles, double* partials,
+                     const int* done, hipStream_t st) {
+  if constexpr (!shape3_instantiated(BY, VAR)) {
+    return hipErrorInvalidValue;
+  } else {
+    const int chunk = kBatchChunk;
+    const int grid = virtual_tiles(ntiles, c.order, chunk);
+    if (grid <= 0 || ngrids <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep3_batch<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, st, table, ngrids,
+                       ntiles, partials, done, c.order, chunk);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, unsigned FL>
+hipError_t by_shape3_batch(const TileCfg& c, const GridArgs* table, int ngrids, int ntiles, double* partials,
+                           const int* done, hipStream_t st) {
+  switch (c.rows * 100 + c.variant) {
+    case 206: return go3_batch<T, 2, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 220: return go3_batch<T, 2, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 406: return go3_batch<T, 4, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 420: return go3_batch<T, 4, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 806: return go3_batch<T, 8, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 820: return go3_batch<T, 8, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -290,6 +345,8 @@ hipError_t dispatch_sweep3_f64(unsigned flags, const TileCfg& c, const GridArgs&
                                const int* done, hipStream_t st);
 hipError_t dispatch_sweep3_f32(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
                                const int* done, hipStream_t st);
+hipError_t dispatch_sweep3_batch_f64(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
+                                     int ntiles, double* partials, const int* done, hipStream_t st);
 
 }  // namespace sweep_detail
 }  // namespace j3d

@@ -42,6 +42,17 @@ def test_batch_two_sweep_passes_match_oracle(monkeypatch, tune, nsweeps, every):
     check_batch_against_oracle(tune, nsweeps, every)
 
 
+@pytest.mark.parametrize("nsweeps,every", [(20, 4), (9, 2), (6, 2), (2, 2), (8, 8), (3, 2), (1, 2), (0, 2), (20, 10),
+                                            (13, 5), (7, 3), (11, 1), (10, 3), (17, 7), (4, 3), (5, 5)])
+@pytest.mark.parametrize("tune", [(4, 16, 20, 0, 1, 1), (8, 8, 6, 0, 2, 1), (1, 16, 20, 0, 1, 2)])
+def test_batch_three_sweep_passes_match_oracle(monkeypatch, tune, nsweeps, every):
+    """Passes of up to three sweeps (forced), residuals fused at the stage that
+    forms their iterate: iterates bit-exact, u_a/u_b placement by the parity
+    of nsweeps, every residual of the cadence."""
+    monkeypatch.setenv("J3D_BATCH_TRIPLES", "1")
+    check_batch_against_oracle(tune, nsweeps, every)
+
+
 def check_batch_against_oracle(tune, nsweeps, every):
     say("batch", tune, nsweeps, every)
     grids, host = make_batch(SHAPES)
@@ -64,11 +75,12 @@ def check_batch_against_oracle(tune, nsweeps, every):
         assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res[g], want)), (g, res[g], want)
 
 
-@pytest.mark.parametrize("pairs", ["0", "1"])
-def test_batch_equals_solo_bitwise_and_replays(monkeypatch, pairs):
+@pytest.mark.parametrize("pairs,triples", [("0", "0"), ("1", "0"), ("0", "1"), ("1", "1")])
+def test_batch_equals_solo_bitwise_and_replays(monkeypatch, pairs, triples):
     monkeypatch.setenv("J3D_BATCH_PAIRS", pairs)
-    tune = (4, 16, 0, 1, 0)
-    say("batch vs solo", pairs)
+    monkeypatch.setenv("J3D_BATCH_TRIPLES", triples)
+    tune = (4, 16, 0, 1, 0) if triples == "0" else (4, 16, 20, 0, 1, 1)
+    say("batch vs solo", pairs, triples)
     grids, host = make_batch(SHAPES, seed=7)
     nres = 10 // 2 + 1
     out = torch.zeros((len(grids), nres), dtype=torch.float64, device="cuda")
