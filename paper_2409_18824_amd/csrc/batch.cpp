@@ -353,7 +353,7 @@ int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, doubl
       if (ps.m == 3) {
         t = p.tab + (size_t)(6 + buf) * n;
         const unsigned rf = !check ? 0u : ps.stage == 0 ? F_RES : ps.stage == 1 ? F_RES1 : F_RES2;
-        J3D_HIP(launch_sweep3_batch(F_WRITE | rf, p.c3, t, n, p.ntiles3, p.partials, nullptr, st));
+        J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE | rf, p.c3, t, n, p.ntiles3, p.partials, nullptr, st));
       } else if (ps.m == 2) {
         t = p.tab + (size_t)(4 + buf) * n;
         J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), p.c2, t, n, p.ntiles2,
@@ -739,7 +739,7 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
     int nt = 0;
     build_tables3(bf, k3, tab3, &nt);
     J3D_TRY(upload(tab3[0], nt));
-    J3D_HIP(launch_sweep3_batch(F_WRITE, k3, dtab, n, nt, parts, nullptr, st));
+    J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE, k3, dtab, n, nt, parts, nullptr, st));
     return J3D_OK;
   };
   auto launch2 = [&](const TileCfg& k2) -> int {

@@ -86,10 +86,11 @@ bool tile3_cfg_supported(int dtype, const TileCfg& c);
 void tile3_counts(int nx, int ny, int nz, const TileCfg& c, int* tx, int* ty, int* tz);
 hipError_t launch_sweep3_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
                              double* partials, const int* done, hipStream_t st);
-// The FP64 three-sweep pass over a table of grids (flags F_WRITE with at most
-// one of F_RES, F_RES1, F_RES2).
-hipError_t launch_sweep3_batch(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids, int ntiles,
-                               double* partials, const int* done, hipStream_t st);
+// The three-sweep pass over a table of grids: FP64 with F_WRITE and at
+// most one of F_RES, F_RES1, F_RES2; FP32 with the flags of the correction
+// cycles (F_WRITE or F_LAST, each with or without F_FIRST).
+hipError_t launch_sweep3_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
+                               int ntiles, double* partials, const int* done, hipStream_t st);
 
 // Number of resident workgroups used for persistent launches.
 int persistent_grid(const TileCfg& c);

@@ -317,10 +317,12 @@ hipError_t launch_sweep3_one(int dtype, unsigned flags, const TileCfg& c, const 
   return sweep_detail::dispatch_sweep3_f32(flags, c, g, partials, done, st);
 }
 
-hipError_t launch_sweep3_batch(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids, int ntiles,
-                               double* partials, const int* done, hipStream_t st) {
-  if (!tile3_cfg_supported(J3D_F64, c)) return hipErrorInvalidValue;
-  return sweep_detail::dispatch_sweep3_batch_f64(flags, c, table, ngrids, ntiles, partials, done, st);
+hipError_t launch_sweep3_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
+                               int ntiles, double* partials, const int* done, hipStream_t st) {
+  if (!tile3_cfg_supported(dtype, c)) return hipErrorInvalidValue;
+  if (dtype == J3D_F64)
+    return sweep_detail::dispatch_sweep3_batch_f64(flags, c, table, ngrids, ntiles, partials, done, st);
+  return sweep_detail::dispatch_sweep3_batch_f32(flags, c, table, ngrids, ntiles, partials, done, st);
 }
 
 hipError_t launch_sweep2_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,

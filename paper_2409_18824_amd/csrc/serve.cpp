@@ -23,6 +23,7 @@
 #include <atomic>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -131,7 +132,7 @@ struct j3d_server {
   double* h_out = nullptr;    // pinned: resid[max_slots]
   int* h_flags = nullptr;     // pinned: done[max_slots], nonfinite[max_slots]
   hipEvent_t ev = nullptr;
-  TileCfg cd{}, cs{}, cs2{};  // defect, one-sweep and two-sweep FP32 passes
+  TileCfg cd{}, cs{}, cs2{}, cs3{};  // defect, one-, two- and three-sweep FP32 passes
 
   double now() const { return now_seconds() - t0; }
 };
@@ -139,10 +140,39 @@ struct j3d_server {
 namespace {
 
 // Launch tables of a cycle: the defect step, the one-sweep FP32 passes
-// (first sweep into e0; first and last sweep at once) and the two-sweep FP32
+// (first sweep into e0; first and last sweep at once), the two-sweep FP32
 // passes (first pair into e0; first and last pair at once; middle pairs
-// e0 -> e1 and e1 -> e0; last pairs from e0 and from e1).
-enum Kind { K_DEF = 0, K_FIRST1, K_FL1, K_FIRST2, K_FL2, K_MID2A, K_MID2B, K_LAST2A, K_LAST2B, K_NKINDS };
+// e0 -> e1 and e1 -> e0; last pairs from e0 and from e1) and the three-sweep
+// FP32 passes (the same six kinds).
+enum Kind {
+  K_DEF = 0,
+  K_FIRST1,
+  K_FL1,
+  K_FIRST2,
+  K_FL2,
+  K_MID2A,
+  K_MID2B,
+  K_LAST2A,
+  K_LAST2B,
+  K_FIRST3,
+  K_FL3,
+  K_MID3A,
+  K_MID3B,
+  K_LAST3A,
+  K_LAST3B,
+  K_NKINDS
+};
+
+// Three-sweep correction passes when the FP32 state the cycle sweeps (r,
+// e0, e1 of every slot) exceeds 512 MB, twice the last-level cache, as in
+// the solver; J3D_SERVE_TRIPLES=0 or =1 forces two-sweep or three-sweep
+// passes.  Every schedule gives the same iterates bit for bit.
+bool serve_triples(long long points) {
+  const char* e = std::getenv("J3D_SERVE_TRIPLES");
+  if (e != nullptr && *e == '0') return false;
+  if (e != nullptr && *e == '1') return true;
+  return 12.0 * (double)points > 512e6;
+}
 
 int serve_fail(j3d_server* s, int code, const char* what) {
   std::lock_guard<std::mutex> lk(s->mu);
@@ -176,6 +206,7 @@ int setup_device(j3d_server* s) {
   s->cd = default_cfg(J3D_F64, 128, 128, 128);
   s->cs = default_cfg(J3D_F32, 128, 128, 128);
   s->cs2 = default_cfg2(J3D_F32, 128, 128, 128);
+  s->cs3 = default_cfg3(J3D_F32, 256, 256, 256);
   s->cd.persistent = 0;
   s->cs.persistent = 0;
   s->cs2.persistent = 0;
@@ -290,7 +321,8 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   const int cyc = s->o.cycle_sweeps;
   GridArgs* T[K_NKINDS];
   for (int k = 0; k < K_NKINDS; ++k) T[k] = s->h_tab + (size_t)k * s->o.max_slots;
-  int nt_def = 0, nt_swp = 0, nt_swp2 = 0, n_in = 0;
+  int nt_def = 0, nt_swp = 0, nt_swp2 = 0, nt_swp3 = 0, n_in = 0;
+  long long pts_in = 0;
   for (int g = 0; g < n; ++g) {
     Slot* sl = slots[g];
     const Layout& L = sl->L;
@@ -310,12 +342,20 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
     a[K_MID2B] = make_args2(&L.e1, &L.e0, &L.r32, nullptr, h, s->cs2, nt_swp2);
     a[K_LAST2A] = make_args2(&L.e0, nullptr, &L.r32, &L.u, h, s->cs2, nt_swp2);
     a[K_LAST2B] = make_args2(&L.e1, nullptr, &L.r32, &L.u, h, s->cs2, nt_swp2);
+    a[K_FIRST3] = make_args3(nullptr, &L.e0, &L.r32, nullptr, h, s->cs3, nt_swp3);
+    a[K_FL3] = make_args3(nullptr, nullptr, &L.r32, &L.u, h, s->cs3, nt_swp3);
+    a[K_MID3A] = make_args3(&L.e0, &L.e1, &L.r32, nullptr, h, s->cs3, nt_swp3);
+    a[K_MID3B] = make_args3(&L.e1, &L.e0, &L.r32, nullptr, h, s->cs3, nt_swp3);
+    a[K_LAST3A] = make_args3(&L.e0, nullptr, &L.r32, &L.u, h, s->cs3, nt_swp3);
+    a[K_LAST3B] = make_args3(&L.e1, nullptr, &L.r32, &L.u, h, s->cs3, nt_swp3);
     for (int k = K_FIRST1; k < K_NKINDS; ++k) {
       a[k].id = sl->id;
       T[k][n_in] = a[k];
     }
     nt_swp += a[K_FIRST1].tiles_x * a[K_FIRST1].tiles_y * a[K_FIRST1].tiles_z;
     nt_swp2 += a[K_FIRST2].tiles_x * a[K_FIRST2].tiles_y * a[K_FIRST2].tiles_z;
+    nt_swp3 += a[K_FIRST3].tiles_x * a[K_FIRST3].tiles_y * a[K_FIRST3].tiles_z;
+    pts_in += (long long)L.u.nx() * L.u.ny() * L.u.nz();
     ++n_in;
   }
   if ((size_t)nt_def > s->part_cap) {
@@ -337,31 +377,29 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   J3D_HIP(launch_pass_batch(J3D_F64, F_RES | F_R32, s->cd, D[K_DEF], n, nt_def, s->d_part, done, s->st));
   J3D_HIP(launch_reduce_batch(s->d_part, D[K_DEF], n, s->d_resid, 1, 0, s->d_normf, s->d_rtol, 0, done,
                               s->d_conv, s->d_nonfinite, s->st));
-  // The correction sweeps, scheduled as in a solo mixed solve: the first
-  // pass takes one sweep when the count is odd, two when even.
+  // The correction sweeps in passes of `step` sweeps, as in a solo mixed
+  // solve: the first pass starts from zero (cyc mod step sweeps, step when
+  // step divides cyc), the middle passes ping-pong between e0 and e1, the
+  // last adds its result to u.
   if (n_in > 0) {
-    if (cyc == 1) {
-      J3D_HIP(launch_pass_batch(J3D_F32, F_LAST | F_FIRST, s->cs, D[K_FL1], n_in, nt_swp, nullptr, done,
-                                s->st));
-    } else if (cyc == 2) {
-      J3D_HIP(launch_sweep2_batch(J3D_F32, F_LAST | F_FIRST, s->cs2, D[K_FL2], n_in, nt_swp2, nullptr, done,
-                                  s->st));
+    const int step = serve_triples(pts_in) ? 3 : 2;
+    auto pass = [&](int len, unsigned fl, Kind k1, Kind k2, Kind k3) -> hipError_t {
+      if (len == 3) return launch_sweep3_batch(J3D_F32, fl, s->cs3, D[k3], n_in, nt_swp3, nullptr, done, s->st);
+      if (len == 2) return launch_sweep2_batch(J3D_F32, fl, s->cs2, D[k2], n_in, nt_swp2, nullptr, done, s->st);
+      return launch_pass_batch(J3D_F32, fl, s->cs, D[k1], n_in, nt_swp, nullptr, done, s->st);
+    };
+    if (cyc <= step) {
+      J3D_HIP(pass(cyc, F_LAST | F_FIRST, K_FL1, K_FL2, K_FL3));
     } else {
-      if (cyc & 1)
-        J3D_HIP(launch_pass_batch(J3D_F32, F_WRITE | F_FIRST, s->cs, D[K_FIRST1], n_in, nt_swp, nullptr,
-                                  done, s->st));
-      else
-        J3D_HIP(launch_sweep2_batch(J3D_F32, F_WRITE | F_FIRST, s->cs2, D[K_FIRST2], n_in, nt_swp2,
-                                    nullptr, done, s->st));
-      const int pairs = (cyc - 2 + (cyc & 1)) / 2;  // passes after the first, >= 1
+      const int lead = cyc % step == 0 ? step : cyc % step;
+      J3D_HIP(pass(lead, F_WRITE | F_FIRST, K_FIRST1, K_FIRST2, K_FIRST3));
+      const int rest = (cyc - lead) / step;  // passes after the first, >= 1
       bool in_e0 = true;
-      for (int p = 1; p < pairs; ++p) {
-        J3D_HIP(launch_sweep2_batch(J3D_F32, F_WRITE, s->cs2, in_e0 ? D[K_MID2A] : D[K_MID2B], n_in, nt_swp2,
-                                    nullptr, done, s->st));
+      for (int p = 1; p < rest; ++p) {
+        J3D_HIP(pass(step, F_WRITE, K_FIRST1, in_e0 ? K_MID2A : K_MID2B, in_e0 ? K_MID3A : K_MID3B));
         in_e0 = !in_e0;
       }
-      J3D_HIP(launch_sweep2_batch(J3D_F32, F_LAST, s->cs2, in_e0 ? D[K_LAST2A] : D[K_LAST2B], n_in, nt_swp2,
-                                  nullptr, done, s->st));
+      J3D_HIP(pass(step, F_LAST, K_FIRST1, in_e0 ? K_LAST2A : K_LAST2B, in_e0 ? K_LAST3A : K_LAST3B));
     }
   }
   // Residuals and flags of this cycle's defect step, for the host.

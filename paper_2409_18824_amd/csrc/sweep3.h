@@ -347,6 +347,8 @@ hipError_t dispatch_sweep3_f32(unsigned flags, const TileCfg& c, const GridArgs&
                                const int* done, hipStream_t st);
 hipError_t dispatch_sweep3_batch_f64(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
                                      int ntiles, double* partials, const int* done, hipStream_t st);
+hipError_t dispatch_sweep3_batch_f32(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
+                                     int ntiles, double* partials, const int* done, hipStream_t st);
 
 }  // namespace sweep_detail
 }  // namespace j3d

@@ -33,11 +33,14 @@ def run(server, reqs, gaps=None):
     return results, outs
 
 
-@pytest.mark.parametrize("cycle", [1, 2, 3, 6])
-def test_served_cycle_lengths_match_oracle(cycle):
-    """Cycle lengths that take each branch of the correction-sweep schedule."""
+@pytest.mark.parametrize("cycle", [1, 2, 3, 4, 5, 6, 7, 9])
+@pytest.mark.parametrize("triples", ["0", "1"])
+def test_served_cycle_lengths_match_oracle(cycle, triples, monkeypatch):
+    """Cycle lengths that take each branch of the correction-sweep schedule,
+    with two-sweep and with three-sweep passes."""
+    monkeypatch.setenv("J3D_SERVE_TRIPLES", triples)
     reqs = [(10, 1e-8, 400, 21, True), (13, 1e-6, 400, 22, False)]
-    say("serve cycle", cycle)
+    say("serve cycle", cycle, triples)
     with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=4, cycle_sweeps=cycle) as s:
         got, got_u = run(s, reqs)
     for k, (n, rtol, cap, seed, _) in enumerate(reqs):
@@ -50,10 +53,12 @@ def test_served_cycle_lengths_match_oracle(cycle):
         assert np.array_equal(got_u[k], uo)
 
 
-def test_served_equals_oracle_and_solo():
+@pytest.mark.parametrize("triples", ["0", "1"])
+def test_served_equals_oracle_and_solo(triples, monkeypatch):
+    monkeypatch.setenv("J3D_SERVE_TRIPLES", triples)
     reqs = [(12, 1e-8, 5000, 11, True), (16, 1e-6, 5000, 12, False), (20, 1e-8, 300, 13, True),
             (9, 1e-10, 5000, 14, False), (24, 1e-6, 200, 15, True)]
-    say("serve mix")
+    say("serve mix", triples)
     with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=8, cycle_sweeps=50) as s:
         mix, mix_u = run(s, reqs)
     for k, (n, rtol, cap, seed, _) in enumerate(reqs):
