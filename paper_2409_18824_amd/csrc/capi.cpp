@@ -53,17 +53,17 @@ TileCfg default_cfg3(int dtype, int nx, int ny, int nz) {
   const int kind = dtype == J3D_F32 ? J3D_KIND_F32X3 : J3D_KIND_F64X3;
   if (tune_cache_lookup_single(kind, nx, ny, nz, &c) && tile3_cfg_supported(dtype, c)) return c;
   // measured on cubes from 96^3 to 512^3 (nontemporal stores throughout):
-  // up to about 200^3 points, 4 wavefronts of 2 rows per thread and 16
-  // planes (more, thinner tiles); up to about 300^3, 4 rows per thread;
-  // beyond, 32 planes, and at 512^3 FP32 8 wavefronts.  Order: XCD-blocked
-  // for small grids, per-slab XCD chunks above, launch order for FP64 at
-  // 512^3.
+  // 4 wavefronts; up to about 200^3 points 2 rows per thread and 16 planes
+  // (more, thinner tiles); up to about 300^3, 4 rows per thread; beyond,
+  // 32 planes, and at 512^3 48 planes in FP64 and 24 in FP32.  Order:
+  // XCD-blocked for small grids, per-slab XCD chunks above, launch order for
+  // FP64 at 512^3.
   const long long pts = (long long)nx * ny * nz;
   const bool small = pts <= 200LL * 200 * 200;
   const bool large = pts > 300LL * 300 * 300;
   const bool huge = pts > 400LL * 400 * 400;
-  c.rows = (dtype == J3D_F32 && huge) ? 8 : 4;
-  c.planes = large ? 32 : 16;
+  c.rows = 4;
+  c.planes = huge ? (dtype == J3D_F32 ? 24 : 48) : large ? 32 : 16;
   c.variant = small ? 6 : 20;
   c.persistent = 0;
   c.order = small ? 0 : ((huge && dtype != J3D_F32) ? 1 : 2);

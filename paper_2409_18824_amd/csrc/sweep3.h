@@ -278,11 +278,13 @@ __global__ void __launch_bounds__(WAVE * BY)
   }
 }
 
-// Instantiated three-sweep shapes: one wavefront along x, blocks of 8 to 32
-// rows, 2 or 4 rows per thread, nontemporal stores.
+// Instantiated three-sweep shapes: one wavefront along x, 2, 4 or 8
+// wavefronts of 2 or 4 rows per thread (blocks of 8 to 32 rows),
+// nontemporal stores.
 constexpr bool shape3_instantiated(int by, int var) {
   const int tr = by * rows_per_thread(var);
-  return (var == 6 || var == 20) && tr >= 8 && tr <= 32 && by <= 16;
+  const bool by_ok = by == 2 || by == 4 || by == 8;
+  return (var == 6 || var == 20) && tr >= 8 && tr <= 32 && by_ok;
 }
 
 template <typename T, int BY, int VAR, unsigned FL>

@@ -324,13 +324,17 @@ def test_three_sweep_kind_defaults_and_validation():
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 97, 5, 3) == (4, 16, 6, 0, 0, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 256, 256, 256) == (4, 16, 20, 0, 2, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 384, 384, 384) == (4, 32, 20, 0, 2, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (4, 32, 20, 0, 1, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (8, 32, 20, 0, 2, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (4, 48, 20, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (4, 24, 20, 0, 2, 1)
     for bad in [(1, 16, 20, 0, 1, 1), (4, 16, 16, 0, 1, 1), (4, 16, 20, 1, 1, 1), (4, 16, 20, 0, 1, 2),
-                (16, 16, 20, 0, 1, 1)]:
+                (16, 16, 20, 0, 1, 1), (3, 16, 20, 0, 1, 1), (5, 16, 20, 0, 1, 1), (6, 8, 6, 0, 1, 1),
+                (7, 16, 20, 0, 1, 1), (4, 16, 6, 0, 3, 1)]:
         with pytest.raises(j3d.J3DError) as ei:
             j3d.j3d_tune_set_single(j3d.KIND_F64X3, 64, 64, 64, bad)
         assert ei.value.code == j3d.EINVAL
+    for good in [(2, 16, 20, 0, 1, 1), (8, 8, 6, 0, 2, 1), (4, 48, 6, 0, 0, 1), (8, 24, 20, 0, 1, 1)]:
+        j3d.j3d_tune_set_single(j3d.KIND_F32X3, 64, 64, 64, good)
+        assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 64, 64, 64) == good
     lib = j3d._lib
     a, b, c = fake_desc(10, 8, 6), fake_desc(10, 8, 6, base=0x900000), fake_desc(10, 8, 6, base=0x1900000)
     assert lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), -0.1, 0, None, None) == j3d.EINVAL

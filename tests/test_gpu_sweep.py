@@ -101,7 +101,7 @@ def test_sweep2_equals_two_sweeps(shape, tune):
 
 
 TUNES3 = [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (4, 7, 6, 0, 1, 1), (8, 64, 20, 0, 0, 1),
-          (2, 3, 20, 0, 2, 1)]
+          (2, 3, 20, 0, 2, 1), (4, 48, 20, 0, 1, 1), (4, 24, 20, 0, 2, 1)]
 SHAPES3 = [(1, 1, 1), (3, 4, 5), (58, 6, 9), (59, 12, 10), (57, 13, 8), (117, 30, 17), (17, 45, 64), (200, 28, 3)]
 
 
