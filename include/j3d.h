@@ -470,7 +470,10 @@ uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz);
  * mixed-precision cycle (FP64 defect step + cycle_sweeps FP32 sweeps over
  * all slots' tiles).  At every cycle boundary converged or capped requests
  * retire and waiting ones are admitted (continuous batching).  A request's
- * result does not depend on which others share its cycles.
+ * result does not depend on which others share its cycles.  The FP32 sweeps
+ * of a cycle run two per pass over memory, or three when the cycle's FP32
+ * state exceeds 512 MB (J3D_SERVE_TRIPLES=0 or =1 forces one or the other);
+ * the iterates are the same bit for bit either way.
  */
 int poisson_serve_create(const j3d_serve_opts* opts, j3d_server** out);
 /* Queue a request.  J3D_EBUDGET if it can never fit; J3D_EAGAIN if the queue
