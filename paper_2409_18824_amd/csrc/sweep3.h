@@ -100,25 +100,34 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   const int cym = xc + g.su_y * ylo, cyp = xc + g.su_y * yhi;
 
   double acc = 0.0;
-  T u0m[RY], u0c[RY], u1m2[RY], u1m1[RY], u2m2[RY], u2m1[RY], fm1[RY], fm2[RY];
+  // Three buffers per plane array, whose roles rotate with k (below,
+  // current, above for u0; k-2, k-1, k for u1 and f; k-3, k-2, k-1 for u2):
+  // the z loop is unrolled by three, so the rotation is a renaming, not
+  // register moves.
+  T u0A[RY], u0B[RY], u0C[RY], u1A[RY], u1B[RY], u1C[RY], u2A[RY], u2B[RY], u2C[RY];
+  T fA[RY], fB[RY], fC[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    u0m[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 3, 0)];
-    u0c[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 2, 0)];
-    u1m2[r] = u1m1[r] = u2m2[r] = u2m1[r] = fm1[r] = fm2[r] = T(0);
+    u0A[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 3, 0)];
+    u0B[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 2, 0)];
+    u1A[r] = u1B[r] = u2A[r] = u2B[r] = fA[r] = fB[r] = T(0);
   }
   if (!ZERO) {
-    sm.e0[(k0 - 2) & 1][wy][0][lane] = u0c[0];
-    sm.e0[(k0 - 2) & 1][wy][1][lane] = u0c[RY - 1];
+    sm.e0[(k0 - 2) & 1][wy][0][lane] = u0B[0];
+    sm.e0[(k0 - 2) & 1][wy][1][lane] = u0B[RY - 1];
   }
   __syncthreads();
 
-  for (int k = k0 - 2; k <= k1 + 1; ++k) {
+  // One plane step: u0m/u0c/u0p are u0 at planes k-1, k, k+1 (u0p loaded
+  // here), fm2/fm1/fk are f at k-2, k-1, k (fk loaded here), u1m2/u1m1/u1
+  // u1 at k-2, k-1, k (u1 computed here) and u2m2/u2m1/u2 u2 at k-3, k-2,
+  // k-1 (u2 computed here).
+  auto step = [&](int k, T(&u0m)[RY], T(&u0c)[RY], T(&u0p)[RY], T(&fm2)[RY], T(&fm1)[RY], T(&fk)[RY],
+                  T(&u1m2)[RY], T(&u1m1)[RY], T(&u1)[RY], T(&u2m2)[RY], T(&u2m1)[RY], T(&u2)[RY]) {
     const int kc = max(k, 0);
     const int kp = min(max(k + 1, 0), ztop);
     const int kf = min(max(k, 1), g.nz);
     const int zk = g.su_z * min(kc, ztop);
-    T u0p[RY], fk[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       fk[r] = f[cf[r] + g.sf_z * kf];
@@ -133,7 +142,6 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
       sm.e0[(k + 1) & 1][wy][1][lane] = u0p[RY - 1];
     }
     // stage 1: u1 at plane k on every row of the block
-    T u1[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const T nym = r == 0 ? nylo : u0c[r - 1];
@@ -156,7 +164,6 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     sm.e1[(k + 3) % 3][wy][1][lane] = u1[RY - 1];
     __syncthreads();
     // stage 2: u2 at plane k-1 (from u1 at k-2, k-1, k)
-    T u2[RY];
     {
       const int sl = (k + 2) % 3;  // slot of plane k-1
       const T below = wy > 0 ? sm.e1[sl][wy - 1][1][lane] : T(0);
@@ -216,17 +223,15 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     }
     sm.e2[(k - 1) & 1][wy][0][lane] = u2[0];
     sm.e2[(k - 1) & 1][wy][1][lane] = u2[RY - 1];
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      u0m[r] = u0c[r];
-      u0c[r] = u0p[r];
-      u1m2[r] = u1m1[r];
-      u1m1[r] = u1[r];
-      u2m2[r] = u2m1[r];
-      u2m1[r] = u2[r];
-      fm2[r] = fm1[r];
-      fm1[r] = fk[r];
-    }
+  };
+  // k runs from k0 - 2 to k1 + 1; the bounds are the same for the whole
+  // workgroup, so every wavefront takes the same steps and barriers.
+  for (int k = k0 - 2; k <= k1 + 1; k += 3) {
+    step(k, u0A, u0B, u0C, fA, fB, fC, u1A, u1B, u1C, u2A, u2B, u2C);
+    if (k + 1 > k1 + 1) break;
+    step(k + 1, u0B, u0C, u0A, fB, fC, fA, u1B, u1C, u1A, u2B, u2C, u2A);
+    if (k + 2 > k1 + 1) break;
+    step(k + 2, u0C, u0A, u0B, fC, fA, fB, u1C, u1A, u1B, u2C, u2A, u2B);
   }
 
   if (RES_ANY != 0) {
