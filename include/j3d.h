@@ -28,8 +28,13 @@
  * are accepted as they are, without a copy.  Kernels read the halo of their
  * input and never write any halo.
  *
- * INTENT.  Arguments marked const are intent(in); outputs are intent(out).
- * Scalars are passed by value.  Inputs and outputs of one call must not
+ * INTENT.  A pointer argument is const exactly when the call only reads
+ * what it points to (intent(in)).  An array descriptor, or a table of
+ * descriptors, is not const when the call writes the array it describes,
+ * whether it overwrites it (intent(out)) or reads and then overwrites it
+ * (intent(inout)); the descriptor struct itself is never modified.
+ * Scalars are passed by value (the paper lowers intent(in) scalars to
+ * values, Sec. "Handling of control structures").  Inputs and outputs of one call must not
  * overlap in memory (Fortran's rule for modified dummy arguments; an
  * in-place Jacobi sweep would turn into an order-dependent Gauss-Seidel
  * sweep): overlap is rejected with J3D_EALIAS.
@@ -135,7 +140,7 @@ int j3d_check_array(const j3d_array* a, int32_t dtype);
  * (then the call synchronises the stream).  The fused residual needs FP64
  * arrays (J3D_EDTYPE otherwise).  FP32 sweeps use h^2 = (float)(h*h).
  */
-int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
+int jacobi3d_sweep(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f,
                    double h, uint32_t flags, double* resid_out, void* stream);
 
 /*
@@ -147,7 +152,7 @@ int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_arra
  * flags are as in jacobi3d_sweep: the fused residual is that of u_in and
  * needs FP64 arrays.
  */
-int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
+int jacobi3d_sweep2(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f,
                     double h, uint32_t flags, double* resid_out, void* stream);
 
 /*
@@ -162,12 +167,15 @@ int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
  * run of three-sweep passes can report the residual of any iterate it
  * passes through; EINVAL if both are set or without resid_out).
  */
-int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f,
+int jacobi3d_sweep3(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f,
                     double h, uint32_t flags, double* resid_out, void* stream);
 
 /*
  * ||f - A u||_2 over the interior, in FP64 (u and f FP64).  `out` is a
- * device address (or host, with J3D_HOST_RESULT in flags).
+ * device address, or a host address with J3D_HOST_RESULT in flags (then
+ * the call synchronises the stream).  The flags argument is the same one
+ * jacobi3d_sweep takes for its resid_out: without it a caller that wants
+ * the number on the host would need a device buffer and a copy of its own.
  */
 int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags,
                 double* out, void* stream);
@@ -210,7 +218,7 @@ int j3d_dot(const double* x, const double* y, int64_t n, uint32_t flags, double*
  * bit the same as one sweep at a time).  Errors: J3D_EINVAL (bounds, rank,
  * nsweeps < 0, h with resid_out), J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
  */
-int jacobi2d_sweeps(const j3d_array* u_a, const j3d_array* u_b, int64_t nsweeps, double h,
+int jacobi2d_sweeps(j3d_array* u_a, j3d_array* u_b, int64_t nsweeps, double h,
                     uint32_t flags, double* resid_out, void* stream);
 
 /*
@@ -239,7 +247,7 @@ int jacobi2d_sweeps(const j3d_array* u_a, const j3d_array* u_b, int64_t nsweeps,
  * spacing), J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
  */
 int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_array* w,
-                 const j3d_array* su, const j3d_array* sv, const j3d_array* sw,
+                 j3d_array* su, j3d_array* sv, j3d_array* sw,
                  double dx, double dy, double dz, void* stream);
 
 /*
@@ -260,7 +268,7 @@ int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_array* w,
  * t_a and t_b may not overlap each other or u, v, w, r.  Asynchronous on
  * `stream`.  Errors: J3D_EINVAL, J3D_EDTYPE, J3D_EALIAS, J3D_EHIP.
  */
-int tracer_advection(const j3d_array* t_a, const j3d_array* t_b, const j3d_array* u,
+int tracer_advection(j3d_array* t_a, j3d_array* t_b, const j3d_array* u,
                      const j3d_array* v, const j3d_array* w, const j3d_array* r,
                      int64_t niter, void* stream);
 
@@ -315,7 +323,7 @@ typedef struct j3d_solve_result {
  * until the solve has finished.  Work arrays (one FP64 array in FP64 mode,
  * three FP32 arrays in MIXED mode) are allocated by the library and cached.
  */
-int poisson_solve(const j3d_array* u, const j3d_array* f, double h,
+int poisson_solve(j3d_array* u, const j3d_array* f, double h,
                   const j3d_solve_opts* opts, j3d_solve_result* result, void* stream);
 
 /* One grid of a batch: two ping-pong arrays with equal halos, and f (all FP64). */
@@ -379,14 +387,14 @@ int j3d_tune_get(int32_t index, j3d_tune* out);
  * one pass is split when needed to keep the u_a/u_b placement above);
  * J3D_BATCH_TRIPLES=0 or =1 forces this off or on.
  */
-int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
+int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsweeps,
                          int32_t resid_every, double* resid_out, const j3d_tune* tune,
                          void* stream);
 
 /* Autotune: time each supported tile shape on these grids (one sweep each,
  * after a warm-up) and write the fastest to *best.  Writes to u_b only.
  * Blocks until done. */
-int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* stream);
+int j3d_autotune(int32_t ngrids, j3d_grid* grids, j3d_tune* best, void* stream);
 
 /* Kernel kinds for the single-grid tuning calls: J3D_F64 and J3D_F32 name
  * the one-sweep passes of that element type, J3D_KIND_F64X2 and
@@ -501,11 +509,11 @@ int poisson_serve_destroy(j3d_server* s);
  * (Steele, Lea, Flood 2014) seeded with seed XOR (stream_id << 40); value
  * lo + (hi-lo) * ((bits >> 11) * 2^-53).  The halo is set to `halo`.
  */
-int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, double lo,
+int j3d_fill_uniform(j3d_array* a, uint64_t seed, uint32_t stream_id, double lo,
                      double hi, double halo, void* stream);
 
 /* Set every element (halo included) of an FP64 or FP32 array to `value`. */
-int j3d_fill_const(const j3d_array* a, double value, void* stream);
+int j3d_fill_const(j3d_array* a, double value, void* stream);
 
 /*
  * Streaming probe for the achievable memory bandwidth: copies n doubles from

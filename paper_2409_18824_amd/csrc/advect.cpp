@@ -57,8 +57,8 @@ int check_same_layout(const Field& a, const Field& b, const char* an, const char
 
 }  // namespace
 
-extern "C" int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_array* w, const j3d_array* su,
-                            const j3d_array* sv, const j3d_array* sw, double dx, double dy, double dz,
+extern "C" int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_array* w, j3d_array* su,
+                            j3d_array* sv, j3d_array* sw, double dx, double dy, double dz,
                             void* stream) {
   const j3d_array* d[6] = {u, v, w, su, sv, sw};
   const char* names[6] = {"u", "v", "w", "su", "sv", "sw"};
@@ -93,7 +93,7 @@ extern "C" int pw_advection(const j3d_array* u, const j3d_array* v, const j3d_ar
   return J3D_OK;
 }
 
-extern "C" int tracer_advection(const j3d_array* t_a, const j3d_array* t_b, const j3d_array* u,
+extern "C" int tracer_advection(j3d_array* t_a, j3d_array* t_b, const j3d_array* u,
                                 const j3d_array* v, const j3d_array* w, const j3d_array* r, int64_t niter,
                                 void* stream) {
   const j3d_array* d[6] = {t_a, t_b, u, v, w, r};

@@ -776,7 +776,7 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
 
 using namespace j3d;
 
-extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32_t nsweeps,
+extern "C" int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsweeps,
                                     int32_t resid_every, double* resid_out, const j3d_tune* tune,
                                     void* stream) {
   BatchFields bf;
@@ -853,14 +853,15 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
   key.append(reinterpret_cast<const char*>(grids), sizeof(j3d_grid) * (size_t)ngrids);
   int dev = 0;
   J3D_HIP(hipGetDevice(&dev));
-  const long long meta[12] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out,
-                              c.rows * 1000000LL + c.planes * 1000 + c.variant * 10 + c.persistent,
-                              dev, c.order, c.cols,
-                              pairs ? 1 + c2.rows * 1000000LL + c2.planes * 1000 + c2.variant * 10 : 0,
-                              c2.order * 10 + c2.cols,
-                              triples ? 1 + c3.rows * 1000000LL + c3.planes * 1000 + c3.variant * 10 : 0,
-                              c3.order};
+  const long long meta[7] = {ngrids, nsweeps, resid_every, (long long)(uintptr_t)resid_out, dev,
+                             pairs ? 1 : 0, triples ? 1 : 0};
   key.append(reinterpret_cast<const char*>(meta), sizeof meta);
+  // the tile shapes as they are (TileCfg holds ints only, so no padding);
+  // a shape a plan does not use is zeroed, keeping equal plans' keys equal
+  static_assert(sizeof(TileCfg) == 6 * sizeof(int), "TileCfg must have no padding");
+  const TileCfg none{};
+  const TileCfg shapes[3] = {c, pairs ? c2 : none, triples ? c3 : none};
+  key.append(reinterpret_cast<const char*>(shapes), sizeof shapes);
   Plan* plan = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -886,7 +887,7 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, const j3d_grid* grids, int32
   return J3D_OK;
 }
 
-extern "C" int j3d_autotune(int32_t ngrids, const j3d_grid* grids, j3d_tune* best, void* stream) {
+extern "C" int j3d_autotune(int32_t ngrids, j3d_grid* grids, j3d_tune* best, void* stream) {
   BatchFields bf;
   J3D_TRY(check_batch(ngrids, grids, &bf));
   if (best == nullptr) return fail(J3D_EINVAL, "best: null pointer");

@@ -101,6 +101,33 @@ static int norm_pass(unsigned flags, const Field& u, const Field& f, const Field
   return J3D_OK;
 }
 
+int check_sweep3_call(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+                      uint32_t flags, const double* resid_out, Sweep3Call* k) {
+  Field& a = k->a;
+  Field& b = k->b;
+  Field& c = k->c;
+  J3D_TRY(check_field(u_in, -1, &a, "u_in"));
+  J3D_TRY(check_field(u_out, a.dtype, &b, "u_out"));
+  J3D_TRY(check_field(f, a.dtype, &c, "f"));
+  J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
+  J3D_TRY(check_same_interior(a, c, "u_in", "f"));
+  J3D_TRY(check_h(h));
+  if ((flags & ~(J3D_HOST_RESULT | J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2)) != 0)
+    return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
+  const unsigned after = flags & (J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2);
+  if (after == (J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2))
+    return fail(J3D_EINVAL, "J3D_RESID_AFTER_1 and J3D_RESID_AFTER_2 are exclusive");
+  if (after != 0 && resid_out == nullptr) return fail(J3D_EINVAL, "J3D_RESID_AFTER_*: resid_out is null");
+  if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
+  if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
+  if (resid_out != nullptr && a.dtype != J3D_F64)
+    return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
+  k->res_flag = after == J3D_RESID_AFTER_1 ? F_RES1 : after == J3D_RESID_AFTER_2 ? F_RES2 : F_RES;
+  k->cfg = default_cfg3(a.dtype, a.nx(), a.ny(), a.nz());
+  k->g = make_args3(&a, &b, &c, nullptr, h, k->cfg, 0);
+  return J3D_OK;
+}
+
 }  // namespace j3d
 
 using namespace j3d;
@@ -164,7 +191,7 @@ int j3d_tune_get(int32_t index, j3d_tune* out) {
   return J3D_OK;
 }
 
-int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+int jacobi3d_sweep(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f, double h,
                    uint32_t flags, double* resid_out, void* stream) {
   Field a, b, c;
   J3D_TRY(check_field(u_in, -1, &a, "u_in"));
@@ -202,7 +229,7 @@ int jacobi3d_sweep(const j3d_array* u_in, const j3d_array* u_out, const j3d_arra
   return J3D_OK;
 }
 
-int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+int jacobi3d_sweep2(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f, double h,
                     uint32_t flags, double* resid_out, void* stream) {
   Field a, b, c;
   J3D_TRY(check_field(u_in, -1, &a, "u_in"));
@@ -240,38 +267,20 @@ int jacobi3d_sweep2(const j3d_array* u_in, const j3d_array* u_out, const j3d_arr
   return J3D_OK;
 }
 
-int jacobi3d_sweep3(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+int jacobi3d_sweep3(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f, double h,
                     uint32_t flags, double* resid_out, void* stream) {
-  Field a, b, c;
-  J3D_TRY(check_field(u_in, -1, &a, "u_in"));
-  J3D_TRY(check_field(u_out, a.dtype, &b, "u_out"));
-  J3D_TRY(check_field(f, a.dtype, &c, "f"));
-  J3D_TRY(check_same_interior(a, b, "u_in", "u_out"));
-  J3D_TRY(check_same_interior(a, c, "u_in", "f"));
-  J3D_TRY(check_h(h));
-  if ((flags & ~(J3D_HOST_RESULT | J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2)) != 0)
-    return fail(J3D_EINVAL, "unknown flags 0x%x", flags);
-  const unsigned after = flags & (J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2);
-  if (after == (J3D_RESID_AFTER_1 | J3D_RESID_AFTER_2))
-    return fail(J3D_EINVAL, "J3D_RESID_AFTER_1 and J3D_RESID_AFTER_2 are exclusive");
-  if (after != 0 && resid_out == nullptr) return fail(J3D_EINVAL, "J3D_RESID_AFTER_*: resid_out is null");
-  if (fields_overlap(a, b)) return fail(J3D_EALIAS, "u_in and u_out overlap");
-  if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
-  if (resid_out != nullptr && a.dtype != J3D_F64)
-    return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
-  const unsigned res_flag = after == J3D_RESID_AFTER_1 ? F_RES1 : after == J3D_RESID_AFTER_2 ? F_RES2 : F_RES;
+  Sweep3Call k;
+  J3D_TRY(check_sweep3_call(u_in, u_out, f, h, flags, resid_out, &k));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const TileCfg cfg = default_cfg3(a.dtype, a.nx(), a.ny(), a.nz());
-  GridArgs g = make_args3(&a, &b, &c, nullptr, h, cfg, 0);
   if (resid_out == nullptr) {
-    J3D_HIP(launch_sweep3_one(a.dtype, F_WRITE, cfg, g, nullptr, nullptr, st));
+    J3D_HIP(launch_sweep3_one(k.a.dtype, F_WRITE, k.cfg, k.g, nullptr, nullptr, st));
     return J3D_OK;
   }
   Scratch* s = nullptr;
   J3D_TRY(get_scratch(st, &s));
-  const int nt = g.tiles_x * g.tiles_y * g.tiles_z;
+  const int nt = k.g.tiles_x * k.g.tiles_y * k.g.tiles_z;
   J3D_TRY(ensure_partials(s, nt));
-  J3D_HIP(launch_sweep3_one(J3D_F64, F_WRITE | res_flag, cfg, g, s->partials, nullptr, st));
+  J3D_HIP(launch_sweep3_one(J3D_F64, F_WRITE | k.res_flag, k.cfg, k.g, s->partials, nullptr, st));
   const bool host = (flags & J3D_HOST_RESULT) != 0;
   double* dst = host ? &s->ctl->value : resid_out;
   J3D_HIP(launch_reduce_one(s->partials, 0, nt, dst, nullptr, 0.0, 0, nullptr, nullptr, nullptr, st));
@@ -308,7 +317,7 @@ int residual_l2(const j3d_array* u, const j3d_array* f, double h, uint32_t flags
   return J3D_OK;
 }
 
-int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, double lo, double hi,
+int j3d_fill_uniform(j3d_array* a, uint64_t seed, uint32_t stream_id, double lo, double hi,
                      double halo, void* stream) {
   Field x;
   J3D_TRY(check_field_wide(a, J3D_F64, &x, "a"));
@@ -319,7 +328,7 @@ int j3d_fill_uniform(const j3d_array* a, uint64_t seed, uint32_t stream_id, doub
   return J3D_OK;
 }
 
-int j3d_fill_const(const j3d_array* a, double value, void* stream) {
+int j3d_fill_const(j3d_array* a, double value, void* stream) {
   Field x;
   J3D_TRY(check_field_wide(a, -1, &x, "a"));
   if (x.ey > 65535 || x.ez > 65535) return fail(J3D_EINVAL, "fill: y/z extents above 65535");

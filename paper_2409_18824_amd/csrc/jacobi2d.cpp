@@ -40,7 +40,7 @@ constexpr long long kGraphLaunches = 64;  // even: the arrays return to their ro
 
 }  // namespace
 
-extern "C" int jacobi2d_sweeps(const j3d_array* u_a, const j3d_array* u_b, int64_t nsweeps, double h,
+extern "C" int jacobi2d_sweeps(j3d_array* u_a, j3d_array* u_b, int64_t nsweeps, double h,
                                uint32_t flags, double* resid_out, void* stream) {
   Field a, b;
   J3D_TRY(check_field2d(u_a, J3D_F64, &a, "u_a"));

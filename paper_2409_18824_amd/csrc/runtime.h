@@ -71,6 +71,19 @@ TileCfg default_cfg(int dtype, int nx, int ny, int nz);
 TileCfg default_cfg2(int dtype, int nx, int ny, int nz);  // two-sweep pass
 TileCfg default_cfg3(int dtype, int nx, int ny, int nz);  // three-sweep pass
 
+// A validated jacobi3d_sweep3 call: its fields, the residual flag of the
+// pass (F_RES, F_RES1 or F_RES2), the tile shape and the launch arguments.
+struct Sweep3Call {
+  Field a, b, c;
+  unsigned res_flag = 0;
+  TileCfg cfg{};
+  GridArgs g{};
+};
+// Checks the arguments of jacobi3d_sweep3 (and of its allocation-free
+// variant) without touching a device.
+int check_sweep3_call(const j3d_array* u_in, const j3d_array* u_out, const j3d_array* f, double h,
+                      uint32_t flags, const double* resid_out, Sweep3Call* k);
+
 // Per-(device, stream) scratch: tile partials, control words, pinned host
 // words.  Grows on demand; lives until j3d_release_cache().
 struct Control {

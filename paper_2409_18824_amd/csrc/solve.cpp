@@ -454,7 +454,7 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
 
 using namespace j3d;
 
-extern "C" int poisson_solve(const j3d_array* u, const j3d_array* f, double h,
+extern "C" int poisson_solve(j3d_array* u, const j3d_array* f, double h,
                              const j3d_solve_opts* opts, j3d_solve_result* result, void* stream) {
   Field a, b;
   J3D_TRY(check_field(u, J3D_F64, &a, "u"));

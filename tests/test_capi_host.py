@@ -31,6 +31,70 @@ def test_header_declares_the_boundary():
         assert must in names
 
 
+# Intent of every pointer argument of the boundary (stream and server
+# handles aside): "in" if the call only reads what it points to, "out" if it
+# writes it, "inout" if it reads and then writes it.  An array descriptor
+# counts by the array it describes (the paper types Fortran dummies by their
+# intent, Sec. "Handling of control structures").
+INTENT = {
+    "j3d_element_offset": {"a": "in", "offset": "out"},
+    "j3d_check_array": {"a": "in"},
+    "jacobi3d_sweep": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
+    "jacobi3d_sweep2": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
+    "jacobi3d_sweep3": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
+    "residual_l2": {"u": "in", "f": "in", "out": "out"},
+    "j3d_sum": {"x": "in", "out": "out"},
+    "j3d_dot": {"x": "in", "y": "in", "out": "out"},
+    "jacobi2d_sweeps": {"u_a": "inout", "u_b": "inout", "resid_out": "out"},
+    "pw_advection": {"u": "in", "v": "in", "w": "in", "su": "out", "sv": "out", "sw": "out"},
+    "tracer_advection": {"t_a": "inout", "t_b": "inout", "u": "in", "v": "in", "w": "in", "r": "in"},
+    "poisson_solve": {"u": "inout", "f": "in", "opts": "in", "result": "out"},
+    "j3d_tune_get": {"out": "out"},
+    "jacobi3d_sweep_batch": {"grids": "inout", "resid_out": "out", "tune": "in"},
+    "j3d_autotune": {"grids": "inout", "best": "out"},
+    "j3d_autotune_single": {"best": "out"},
+    "j3d_tune_set_single": {"t": "in"},
+    "j3d_tune_query_single": {"out": "out"},
+    "poisson_serve_create": {"opts": "in", "out": "out"},
+    "poisson_serve_submit": {"req": "in", "ticket": "out"},
+    "poisson_serve_poll": {"out": "out", "n": "out"},
+    "poisson_serve_stats": {"now": "out", "active": "out", "queued": "out", "finished": "out"},
+    "j3d_fill_uniform": {"a": "out"},
+    "j3d_fill_const": {"a": "out"},
+    "j3d_bandwidth_probe": {"src": "in", "dst": "out", "gbps": "out"},
+}
+
+
+def header_prototypes():
+    src = open(os.path.join(ROOT, "include", "j3d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    protos = {}
+    for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(([^)]*)\)\s*;",
+                         src, flags=re.M):
+        params = [" ".join(p.split()) for p in m.group(2).split(",")]
+        protos[m.group(1)] = [p for p in params if p and p != "void"]
+    return protos
+
+
+def test_exactly_the_intent_in_pointers_are_const():
+    protos = header_prototypes()
+    seen = set()
+    for fn, params in protos.items():
+        for p in params:
+            if "*" not in p:
+                continue
+            name = p.split("*")[-1].strip()
+            if name == "stream" or re.match(r"^j3d_server\* \w+$", p):
+                continue  # opaque handles
+            assert fn in INTENT and name in INTENT[fn], "no intent recorded for %s(%s)" % (fn, p)
+            want_const = INTENT[fn][name] == "in"
+            assert p.startswith("const ") == want_const, "%s: %s should %sbe const" % (
+                fn, p, "" if want_const else "not ")
+            seen.add((fn, name))
+    recorded = {(fn, n) for fn, d in INTENT.items() for n in d}
+    assert recorded == seen, recorded ^ seen
+
+
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(j3d.LIB_PATH)
     missing = [n for n in header_functions() if not hasattr(lib, n)]
@@ -360,3 +424,4 @@ def test_three_sweep_kind_defaults_and_validation():
     # the other sweep entries know no residual-stage flags
     assert lib.jacobi3d_sweep2(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, j3d.RESID_AFTER_1, rp,
                                None) == j3d.EINVAL
+
