@@ -171,6 +171,27 @@ int jacobi3d_sweep3(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f,
                     double h, uint32_t flags, double* resid_out, void* stream);
 
 /*
+ * jacobi3d_sweep3 with its fused residual, allocating nothing: for callers
+ * that cannot allocate device memory (code being captured into a HIP graph,
+ * serving loops that must not call hipMalloc, hosts that forbid it).
+ * Arguments, flags and results as in jacobi3d_sweep3, with the same tile
+ * shape and kernels (u_out and *resid_out are bit-identical to it), except:
+ * u_in, u_out, f are FP64 and resid_out is a non-null device address
+ * (J3D_HOST_RESULT is rejected).  The per-tile partial sums live in a
+ * static device array of 65536 doubles (512 KiB) that every GPU the library
+ * runs on holds until the process ends; a grid whose three-sweep tiling
+ * needs more tiles than that returns J3D_EINVAL before any device work
+ * (with the default tile shapes every cube up to 1270^3 fits; a smaller
+ * pinned or autotuned tile shape lowers that).  Every call on
+ * one GPU uses that GPU's one array, so calls that may overlap in time on
+ * the same GPU (other streams, other threads) race and must be ordered by
+ * the caller.  Errors: as jacobi3d_sweep3, and J3D_EINVAL for the cases
+ * above.
+ */
+int jacobi3d_sweep3_noalloc(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f,
+                            double h, uint32_t flags, double* resid_out, void* stream);
+
+/*
  * ||f - A u||_2 over the interior, in FP64 (u and f FP64).  `out` is a
  * device address, or a host address with J3D_HOST_RESULT in flags (then
  * the call synchronises the stream).  The flags argument is the same one

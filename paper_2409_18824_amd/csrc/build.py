@@ -32,7 +32,7 @@ HOST_SOURCES = ["runtime.cpp", "capi.cpp", "solve.cpp", "batch.cpp", "serve.cpp"
                 "advect.cpp"]
 DEVICE_SOURCES = ["kernels.hip", "kernels_f64.hip", "kernels_f32.hip", "kernels_sweep2.hip",
                   "kernels_sweep2_f32.hip", "kernels_sweep3.hip", "kernels_sweep3_f32.hip", "kernels_2d.hip",
-                  "kernels_advect.hip"]
+                  "kernels_advect.hip", "noalloc.hip"]
 
 
 def _run(cmd):

@@ -113,6 +113,7 @@ _SIGS = {
     "jacobi3d_sweep": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "jacobi3d_sweep2": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "jacobi3d_sweep3": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
+    "jacobi3d_sweep3_noalloc": ([_P(J3DArray), _P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "residual_l2": ([_P(J3DArray), _P(J3DArray), _D, _U32, _V, _V], ctypes.c_int),
     "poisson_solve": ([_P(J3DArray), _P(J3DArray), _D, _P(SolveOpts), _P(SolveResult), _V], ctypes.c_int),
     "j3d_tune_count": ([], ctypes.c_int),
@@ -352,6 +353,18 @@ def jacobi3d_sweep3(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out=
     _check(_lib.jacobi3d_sweep3(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h), flags, ptr, st),
            "jacobi3d_sweep3")
     return None
+
+
+def jacobi3d_sweep3_noalloc(u_in: FArray, u_out: FArray, f: FArray, h: float, resid_out, stream=None,
+                            flags: int = 0, resid_after: int = 0):
+    """jacobi3d_sweep3 with its fused residual into ``resid_out`` (a device float64 tensor), the
+    tile partials kept in the library's static device array instead of allocated scratch."""
+    if resid_after:
+        flags |= {1: RESID_AFTER_1, 2: RESID_AFTER_2}[resid_after]
+    a, b, c = u_in.desc(), u_out.desc(), f.desc()
+    ptr = None if resid_out is None else ctypes.c_void_p(resid_out.data_ptr())
+    _check(_lib.jacobi3d_sweep3_noalloc(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(h), flags, ptr,
+                                        _stream_handle(stream)), "jacobi3d_sweep3_noalloc")
 
 
 def residual_l2(u: FArray, f: FArray, h: float, out=None, stream=None):

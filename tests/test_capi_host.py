@@ -42,6 +42,7 @@ INTENT = {
     "jacobi3d_sweep": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
     "jacobi3d_sweep2": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
     "jacobi3d_sweep3": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
+    "jacobi3d_sweep3_noalloc": {"u_in": "in", "u_out": "out", "f": "in", "resid_out": "out"},
     "residual_l2": {"u": "in", "f": "in", "out": "out"},
     "j3d_sum": {"x": "in", "out": "out"},
     "j3d_dot": {"x": "in", "y": "in", "out": "out"},
@@ -425,3 +426,34 @@ def test_three_sweep_kind_defaults_and_validation():
     assert lib.jacobi3d_sweep2(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, j3d.RESID_AFTER_1, rp,
                                None) == j3d.EINVAL
 
+
+
+def test_noalloc_sweep3_validation():
+    """jacobi3d_sweep3_noalloc rejects, before any device work: a null or host
+    result, FP32 arrays, and a grid whose tiling needs more tile partials than
+    its static device array holds (65536)."""
+    lib = j3d._lib
+    a, b, c = fake_desc(10, 8, 6), fake_desc(10, 8, 6, base=0x900000), fake_desc(10, 8, 6, base=0x1900000)
+    r = ctypes.c_double()
+    rp = ctypes.cast(ctypes.byref(r), ctypes.c_void_p)
+    dev = ctypes.c_void_p(0x7000000)
+    assert lib.jacobi3d_sweep3_noalloc(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, 0, None,
+                                       None) == j3d.EINVAL
+    assert lib.jacobi3d_sweep3_noalloc(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), 0.1, j3d.HOST_RESULT,
+                                       rp, None) == j3d.EINVAL
+    assert "J3D_HOST_RESULT" in j3d.last_error()
+    a32 = fake_desc(10, 8, 6, dtype=j3d.F32)
+    b32 = fake_desc(10, 8, 6, dtype=j3d.F32, base=0x900000)
+    c32 = fake_desc(10, 8, 6, dtype=j3d.F32, base=0x1900000)
+    assert lib.jacobi3d_sweep3_noalloc(ctypes.byref(a32), ctypes.byref(b32), ctypes.byref(c32), 0.1, 0, dev,
+                                       None) == j3d.EDTYPE
+    assert lib.jacobi3d_sweep3_noalloc(ctypes.byref(a), ctypes.byref(a), ctypes.byref(c), 0.1, 0, dev,
+                                       None) == j3d.EALIAS
+    # 59 x 2173 x 8641 points: with the default shape of such grids (58
+    # columns, 12 rows, 48 planes per tile) 2 x 182 x 181 = 65884 tiles
+    nx, ny, nz = 59, 2173, 8641
+    span = (nx + 2) * (ny + 2) * (nz + 2) * 8
+    base = 1 << 40
+    big = [fake_desc(nx, ny, nz, base=base + q * (span + 4096)) for q in range(3)]
+    assert lib.jacobi3d_sweep3_noalloc(*[ctypes.byref(x) for x in big], 1e-4, 0, dev, None) == j3d.EINVAL
+    assert "65884 tile partials" in j3d.last_error()
