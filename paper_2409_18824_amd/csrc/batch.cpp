@@ -833,7 +833,10 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsw
   TileCfg c3 = default_cfg3(J3D_F64, 64, 64, 64);
   if (tune != nullptr && tile3_cfg_supported(J3D_F64, c)) c3 = c;
   const char* force3 = getenv("J3D_BATCH_TRIPLES");
-  const int mode3 = (force3 && *force3 == '0') ? 0 : (force3 && *force3 == '1') ? 1 : -1;
+  int mode3 = (force3 && *force3 == '0') ? 0 : (force3 && *force3 == '1') ? 1 : -1;
+  // the three-sweep pass needs every plane below 4 GiB
+  for (int g = 0; g < ngrids && mode3 != 0; ++g)
+    if (!plane_fits_u32(bf.a[g]) || !plane_fits_u32(bf.b[g]) || !plane_fits_u32(bf.f[g])) mode3 = 0;
   if (mode3 != 0 && nsweeps >= 3) {
     if (mode3 == 1 && tune != nullptr) {
       triples = true;
@@ -927,6 +930,8 @@ extern "C" int j3d_autotune_single(int32_t dtype, int32_t nx, int32_t ny, int32_
   a.sy = ((long long)a.ex + align - 1) / align * align;
   a.sz = a.sy * a.ey;
   if (a.sz * a.ez >= (1LL << 31) - align) return fail(J3D_EINVAL, "grid too large");
+  if (triple && !plane_fits_u32(a))
+    return fail(J3D_EINVAL, "a z-plane spans 4 GiB or more: the three-sweep pass needs smaller planes");
   const size_t bytes = ((size_t)(a.sz * a.ez + align) * es + 255) / 256 * 256;
   void* mem = nullptr;
   J3D_TRY(dev_alloc(&mem, 3 * bytes, "autotune arrays"));

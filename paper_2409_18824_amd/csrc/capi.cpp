@@ -122,6 +122,8 @@ int check_sweep3_call(const j3d_array* u_in, const j3d_array* u_out, const j3d_a
   if (fields_overlap(b, c)) return fail(J3D_EALIAS, "u_out and f overlap");
   if (resid_out != nullptr && a.dtype != J3D_F64)
     return fail(J3D_EDTYPE, "a fused residual needs FP64 arrays");
+  if (!plane_fits_u32(a) || !plane_fits_u32(b) || !plane_fits_u32(c))
+    return fail(J3D_EINVAL, "a z-plane spans 4 GiB or more: the three-sweep pass needs smaller planes");
   k->res_flag = after == J3D_RESID_AFTER_1 ? F_RES1 : after == J3D_RESID_AFTER_2 ? F_RES2 : F_RES;
   k->cfg = default_cfg3(a.dtype, a.nx(), a.ny(), a.nz());
   k->g = make_args3(&a, &b, &c, nullptr, h, k->cfg, 0);

@@ -130,6 +130,11 @@ int check_same_interior(const Field& a, const Field& b, const char* an, const ch
   return J3D_OK;
 }
 
+bool plane_fits_u32(const Field& a) {
+  const long long span = ((long long)(a.ey - 1) * a.sy + a.ex) * (long long)a.esize;
+  return span < (1LL << 32);
+}
+
 int check_h(double h) {
   if (!(h > 0.0) || !std::isfinite(h)) return fail(J3D_EINVAL, "h must be positive and finite");
   return J3D_OK;

@@ -49,6 +49,10 @@ int check_field_wide(const j3d_array* a, int dtype, Field* out, const char* name
 // extent 1 (lbound[2] == ubound[2]); ez = 1 in the result.
 int check_field2d(const j3d_array* a, int dtype, Field* out, const char* name);
 bool fields_overlap(const Field& a, const Field& b);
+// The three-sweep pass addresses each plane of an array through a buffer
+// descriptor with 32-bit byte offsets: true when every offset within one
+// plane of `a` is below 2^32 bytes.
+bool plane_fits_u32(const Field& a);
 int check_same_interior(const Field& a, const Field& b, const char* an, const char* bn);
 int check_h(double h);
 

@@ -326,6 +326,7 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   for (int k = 0; k < K_NKINDS; ++k) T[k] = s->h_tab + (size_t)k * s->o.max_slots;
   int nt_def = 0, nt_swp = 0, nt_swp2 = 0, nt_swp3 = 0, n_in = 0;
   long long pts_in = 0;
+  bool fit3 = true;  // every plane below 4 GiB (needed by three-sweep passes)
   for (int g = 0; g < n; ++g) {
     Slot* sl = slots[g];
     const Layout& L = sl->L;
@@ -359,6 +360,7 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
     nt_swp2 += a[K_FIRST2].tiles_x * a[K_FIRST2].tiles_y * a[K_FIRST2].tiles_z;
     nt_swp3 += a[K_FIRST3].tiles_x * a[K_FIRST3].tiles_y * a[K_FIRST3].tiles_z;
     pts_in += (long long)L.u.nx() * L.u.ny() * L.u.nz();
+    fit3 = fit3 && plane_fits_u32(L.u) && plane_fits_u32(L.r32) && plane_fits_u32(L.e0) && plane_fits_u32(L.e1);
     ++n_in;
   }
   if ((size_t)nt_def > s->part_cap) {
@@ -385,7 +387,7 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   // step divides cyc), the middle passes ping-pong between e0 and e1, the
   // last adds its result to u.
   if (n_in > 0) {
-    const int step = serve_triples(pts_in) ? 3 : 2;
+    const int step = (fit3 && serve_triples(pts_in)) ? 3 : 2;
     auto pass = [&](int len, unsigned fl, Kind k1, Kind k2, Kind k3) -> hipError_t {
       if (len == 3) return launch_sweep3_batch(J3D_F32, fl, s->cs3, D[k3], n_in, nt_swp3, nullptr, done, s->st);
       if (len == 2) return launch_sweep2_batch(J3D_F32, fl, s->cs2, D[k2], n_in, nt_swp2, nullptr, done, s->st);

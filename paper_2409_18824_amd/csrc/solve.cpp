@@ -122,8 +122,11 @@ int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o
   // residual of a single sweep leaves many more per-tile partials to
   // reduce.  A pass ends at the next check and at the end of the range it
   // belongs to.
-  const long long step = forced_step() != 0 ? forced_step()
-                         : three_sweep_passes_pay(24.0 * (double)points) ? 3 : ((c % 2) == 0 ? 2 : 1);
+  // (w has u's layout; a three-sweep pass needs planes below 4 GiB)
+  const bool fit3 = plane_fits_u32(u) && plane_fits_u32(f);
+  long long step = forced_step() != 0 ? forced_step()
+                   : three_sweep_passes_pay(24.0 * (double)points) ? 3 : ((c % 2) == 0 ? 2 : 1);
+  if (step == 3 && !fit3) step = 2;
   const long long lead = c % step;
   const bool two_pairs = step == 3 && lead == 1 && c >= 4;
   auto pass_len = [&](long long sw, long long to) -> int {
@@ -325,7 +328,8 @@ int solve_mixed(const Field& u, const Field& f, double h, const j3d_solve_opts& 
   // it (m mod step sweeps, step when step divides m), the middle passes
   // ping-pong between e0 and e1, and the last pass adds its result to u.
   const long long points = (long long)u.nx() * u.ny() * u.nz();
-  const int step = forced_step() != 0 ? forced_step() : three_sweep_passes_pay(12.0 * (double)points) ? 3 : 2;
+  int step = forced_step() != 0 ? forced_step() : three_sweep_passes_pay(12.0 * (double)points) ? 3 : 2;
+  if (step == 3 && !(plane_fits_u32(u) && plane_fits_u32(r32))) step = 2;
   const TileCfg cs2 = default_cfg2(J3D_F32, u.nx(), u.ny(), u.nz());
   const TileCfg cs3 = default_cfg3(J3D_F32, u.nx(), u.ny(), u.nz());
   const GridArgs defect = make_args(&u, nullptr, &f, nullptr, &r32, h, cd, 0);

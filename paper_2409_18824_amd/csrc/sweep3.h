@@ -43,10 +43,72 @@ struct Smem3 {
   double red[BY];
 };
 
+// Buffer resource for a wave-uniform base address: every load and store of
+// a plane then takes the plane's address in scalar registers and a per-lane
+// 32-bit byte offset that is fixed for the whole tile, so the z march needs
+// no per-lane address arithmetic.  The descriptor's range is the largest it
+// allows (4 GiB past the base; a plane of the three-sweep pass is smaller,
+// which the host checks); the kernel keeps every access inside the array
+// itself, as with plain pointers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
+}
+
+typedef unsigned buf_u2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Store; NT streams it past the caches (cache policy "nt").
+template <typename T, bool NT>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u2, v), r, off, 0, NT ? 2 : 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, NT ? 2 : 0);
+}
+
+// The value of lane l-1 (shl: l+1) of the wavefront; lane 0 (63) gets 0.
+// One DPP move per 32-bit half, with no copy of the destination first: the
+// three-sweep tile never uses the shifted value at its edge lanes.
+__device__ __forceinline__ double shift_in_left(double v) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_mov_dpp(a.x, 0x138, 0xF, 0xF, true);
+  r.y = __builtin_amdgcn_mov_dpp(a.y, 0x138, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double shift_in_right(double v) {
+  const dpp_i2 a = __builtin_bit_cast(dpp_i2, v);
+  dpp_i2 r;
+  r.x = __builtin_amdgcn_mov_dpp(a.x, 0x130, 0xF, 0xF, true);
+  r.y = __builtin_amdgcn_mov_dpp(a.y, 0x130, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ float shift_in_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float shift_in_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+
 // Flags as for the two-sweep pass: F_WRITE (store u3 to g.o), F_RES (FP64:
 // residual of u0; F_RES1, F_RES2: of u1, u2), F_FIRST (u0 is identically
 // zero and not read), F_LAST (add (double) u3 to g.u64 instead of storing
 // it).
+//
+// The loads of plane step k+1 (u0 at plane k+2, f at k+1, and the outer
+// wavefronts' u0 rows beyond the block at k+1) are issued at the start of
+// step k, before its arithmetic, so a whole step of work covers their
+// latency; one extra plane of registers per streamed array holds them.
 template <typename T, int BY, int VAR, unsigned FL>
 __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __restrict__ partials,
                                             Smem3<T, BY>& sm) {
@@ -56,13 +118,14 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   constexpr int H = TR - 4;    // output rows per tile
   constexpr bool NT = (VAR & 4) != 0;
   constexpr bool ZERO = (FL & F_FIRST) != 0;
+  constexpr uint32_t ES = sizeof(T);
   static_assert(TR >= 5, "a block needs at least one output row");
   constexpr unsigned RES_ANY = FL & (F_RES | F_RES1 | F_RES2);
   static_assert(RES_ANY == 0 || sizeof(T) == 8, "the fused residual is an FP64 pass");
   static_assert(RES_ANY == 0 || RES_ANY == F_RES || RES_ANY == F_RES1 || RES_ANY == F_RES2,
                 "one fused residual per pass");
   const int lane = threadIdx.x;
-  const int wy = threadIdx.y;
+  const int wy = __builtin_amdgcn_readfirstlane(threadIdx.y);  // uniform in the wavefront
   const int tx = t % g.tiles_x;
   const int t2 = t / g.tiles_x;
   const int ty = t2 % g.tiles_y;
@@ -73,90 +136,156 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   const bool lane_out = lane >= 3 && lane <= W + 2;
   const bool x_in = xi >= 1 && xi <= g.nx;
   const int xc = min(max(xi, 0), g.nx + 1);
-  const T* __restrict__ u0 = static_cast<const T*>(g.u);
-  const T* __restrict__ f = static_cast<const T*>(g.f);
-  T* __restrict__ out = static_cast<T*>(g.o);
-  double* __restrict__ u64 = g.u64;
+  const char* u0b = static_cast<const char*>(g.u);
+  const char* fb = static_cast<const char*>(g.f);
+  char* ob = static_cast<char*>(g.o);
+  char* u64b = reinterpret_cast<char*>(g.u64);
   const T h2 = h2_of<T>(g);
   const int ztop = g.nz + 1;
 
-  int cu[RY], cf[RY], co[RY];
+  // byte offsets within a plane of the thread's rows
+  uint32_t ou[RY], of[RY], oo[RY];
   bool inner2[RY], inner3[RY], col_in[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int br = wy * RY + r;       // block row
     const int yj = ty * H + br - 1;   // column y (block row 2 is the first output row)
     const int yc = min(max(yj, 0), g.ny + 1);
-    cu[r] = xc + g.su_y * yc;
-    cf[r] = xc + g.sf_y * yc;
-    co[r] = (FL & F_LAST) ? xc + g.s64_y * yc : xc + g.so_y * yc;
+    ou[r] = (uint32_t)(xc + g.su_y * yc) * ES;
+    of[r] = (uint32_t)(xc + g.sf_y * yc) * ES;
+    oo[r] = (FL & F_LAST) ? (uint32_t)(xc + g.s64_y * yc) * 8u : (uint32_t)(xc + g.so_y * yc) * ES;
     inner2[r] = br >= 1 && br <= TR - 2;
     inner3[r] = lane_out && br >= 2 && br <= TR - 3;
     col_in[r] = x_in && yj >= 1 && yj <= g.ny;
   }
-  // u0 rows just below and above this wavefront's rows (clamped)
+  // u0 rows just below and above this wavefront's rows (clamped); only the
+  // block's first and last wavefronts load them, the others take them from
+  // the neighbouring wavefront through LDS
   const int ylo = max(min(max(ty * H - 1 + wy * RY, 0), g.ny + 1) - 1, 0);
   const int yhi = min(max(ty * H - 1 + wy * RY + RY, 0), g.ny + 1);
-  const int cym = xc + g.su_y * ylo, cyp = xc + g.su_y * yhi;
+  const uint32_t oylo = (uint32_t)(xc + g.su_y * ylo) * ES, oyhi = (uint32_t)(xc + g.su_y * yhi) * ES;
+  const bool wlo = wy == 0, whi = wy == BY - 1;
+  const int wdn = wlo ? 0 : wy - 1, wup = whi ? BY - 1 : wy + 1;  // neighbouring wavefronts
+
+  auto u_plane = [&](int kk) { return plane_rsrc(u0b + (long long)g.su_z * kk * ES); };
+  auto f_plane = [&](int kk) { return plane_rsrc(fb + (long long)g.sf_z * kk * ES); };
 
   double acc = 0.0;
   // Three buffers per plane array, whose roles rotate with k (below,
   // current, above for u0; k-2, k-1, k for u1 and f; k-3, k-2, k-1 for u2):
   // the z loop is unrolled by three, so the rotation is a renaming, not
-  // register moves.
+  // register moves.  pu, pf, pylo, pyhi: the next step's loads in flight.
   T u0A[RY], u0B[RY], u0C[RY], u1A[RY], u1B[RY], u1C[RY], u2A[RY], u2B[RY], u2C[RY];
-  T fA[RY], fB[RY], fC[RY];
+  T fA[RY], fB[RY], fC[RY], pu[RY], pf[RY];
+  T pylo = T(0), pyhi = T(0);
+  // u3 of the plane the previous step computed, stored at the start of the
+  // next step together with that step's loads (so that a wait for loads
+  // never waits for stores issued just before it); with F_LAST, pq holds
+  // the FP64 values it is added to, loaded one step ahead like the
+  // streamed planes
+  T st[RY];
+  double pq[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    u0A[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 3, 0)];
-    u0B[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * max(k0 - 2, 0)];
-    u1A[r] = u1B[r] = u2A[r] = u2B[r] = fA[r] = fB[r] = T(0);
+    st[r] = T(0);
+    pq[r] = 0.0;
   }
+  auto out_plane = [&](int kk) {
+    return (FL & F_LAST) ? plane_rsrc(u64b + (long long)g.s64_z * kk * 8)
+                         : plane_rsrc(ob + (long long)g.so_z * kk * ES);
+  };
+  // store u3 of plane kk (held in st)
+  auto flush = [&](int kk) {
+    const auto ro = out_plane(kk);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (inner3[r] && col_in[r]) {
+        if (FL & F_LAST)
+          bstore<double, false>(pq[r] + static_cast<double>(st[r]), ro, oo[r]);
+        else
+          bstore<T, NT>(st[r], ro, oo[r]);
+      }
+    }
+  };
+  // the loads step k consumes: u0 at plane k+1, f at k, the outer rows at k
+  auto issue = [&](int k) {
+    const auto rp = u_plane(min(max(k + 1, 0), ztop));
+    const auto rf = f_plane(min(max(k, 1), g.nz));
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      pu[r] = ZERO ? T(0) : bload<T>(rp, ou[r]);
+      pf[r] = bload<T>(rf, of[r]);
+    }
+    if (!ZERO) {
+      const auto rc = u_plane(min(max(k, 0), ztop));
+      if (wlo) pylo = bload<T>(rc, oylo);
+      if (whi) pyhi = bload<T>(rc, oyhi);
+    }
+  };
+  {
+    const auto ra = u_plane(max(k0 - 3, 0));
+    const auto rb = u_plane(max(k0 - 2, 0));
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      u0A[r] = ZERO ? T(0) : bload<T>(ra, ou[r]);
+      u0B[r] = ZERO ? T(0) : bload<T>(rb, ou[r]);
+      u1A[r] = u1B[r] = u2A[r] = u2B[r] = fA[r] = fB[r] = T(0);
+    }
+  }
+  issue(k0 - 2);
   if (!ZERO) {
     sm.e0[(k0 - 2) & 1][wy][0][lane] = u0B[0];
     sm.e0[(k0 - 2) & 1][wy][1][lane] = u0B[RY - 1];
   }
   __syncthreads();
 
-  // One plane step: u0m/u0c/u0p are u0 at planes k-1, k, k+1 (u0p loaded
-  // here), fm2/fm1/fk are f at k-2, k-1, k (fk loaded here), u1m2/u1m1/u1
-  // u1 at k-2, k-1, k (u1 computed here) and u2m2/u2m1/u2 u2 at k-3, k-2,
-  // k-1 (u2 computed here).
+  // One plane step: u0m/u0c/u0p are u0 at planes k-1, k, k+1, fm2/fm1/fk
+  // are f at k-2, k-1, k, u1m2/u1m1/u1 u1 at k-2, k-1, k (u1 computed here)
+  // and u2m2/u2m1/u2 u2 at k-3, k-2, k-1 (u2 computed here).
   auto step = [&](int k, T(&u0m)[RY], T(&u0c)[RY], T(&u0p)[RY], T(&fm2)[RY], T(&fm1)[RY], T(&fk)[RY],
                   T(&u1m2)[RY], T(&u1m1)[RY], T(&u1)[RY], T(&u2m2)[RY], T(&u2m1)[RY], T(&u2)[RY]) {
-    const int kc = max(k, 0);
-    const int kp = min(max(k + 1, 0), ztop);
-    const int kf = min(max(k, 1), g.nz);
-    const int zk = g.su_z * min(kc, ztop);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      fk[r] = f[cf[r] + g.sf_z * kf];
-      u0p[r] = ZERO ? T(0) : u0[cu[r] + g.su_z * kp];
+      u0p[r] = pu[r];
+      fk[r] = pf[r];
+    }
+    const T elo = pylo, ehi = pyhi;
+    if (k <= k1) issue(k + 1);
+    if (k - 3 >= k0) flush(k - 3);
+    if ((FL & F_LAST) && k - 2 >= k0) {
+      const auto rq = out_plane(k - 2);
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (inner3[r] && col_in[r]) pq[r] = bload<double>(rq, oo[r]);
     }
     T nylo = T(0), nyhi = T(0);
     if (!ZERO) {
-      nylo = wy > 0 ? sm.e0[k & 1][wy - 1][1][lane] : u0[cym + zk];
-      nyhi = wy < BY - 1 ? sm.e0[k & 1][wy + 1][0][lane] : u0[cyp + zk];
+      nylo = wlo ? elo : sm.e0[k & 1][wdn][1][lane];
+      nyhi = whi ? ehi : sm.e0[k & 1][wup][0][lane];
       // plane k+1 for the next step (read after this step's barrier)
       sm.e0[(k + 1) & 1][wy][0][lane] = u0p[0];
       sm.e0[(k + 1) & 1][wy][1][lane] = u0p[RY - 1];
     }
+    const bool kin1 = k >= 1 && k <= g.nz;
+    const bool kout1 = k >= k0 && k < k1;
     // stage 1: u1 at plane k on every row of the block
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const T nym = r == 0 ? nylo : u0c[r - 1];
       const T nyp = r == RY - 1 ? nyhi : u0c[r + 1];
-      const bool pt_in = col_in[r] && k >= 1 && k <= g.nz;
-      T s = ZERO ? T(0) : from_left(u0c[r]) + from_right(u0c[r]);
+      const bool pt_in = col_in[r] && kin1;
+      T s = ZERO ? T(0) : shift_in_left(u0c[r]) + shift_in_right(u0c[r]);
       s = s + nym;
       s = s + nyp;
       s = s + u0m[r];
       s = s + u0p[r];
       u1[r] = pt_in ? div6(s + h2 * fk[r]) : u0c[r];
       if (FL & F_RES) {
-        const double res = static_cast<double>(fk[r]) -
-                           (6.0 * static_cast<double>(u0c[r]) - static_cast<double>(s)) / g.h2;
-        acc += (inner3[r] && pt_in && k >= k0 && k < k1) ? res * res : 0.0;
+        if (inner3[r] && pt_in && kout1) {
+          const double res = static_cast<double>(fk[r]) -
+                             (6.0 * static_cast<double>(u0c[r]) - static_cast<double>(s)) / g.h2;
+          acc += res * res;
+        }
       }
     }
     // slot of plane k (k starts at k0 - 2 >= -1: keep the index non-negative)
@@ -166,11 +295,13 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     // stage 2: u2 at plane k-1 (from u1 at k-2, k-1, k)
     {
       const int sl = (k + 2) % 3;  // slot of plane k-1
-      const T below = wy > 0 ? sm.e1[sl][wy - 1][1][lane] : T(0);
-      const T above = wy < BY - 1 ? sm.e1[sl][wy + 1][0][lane] : T(0);
+      const T below = wlo ? T(0) : sm.e1[sl][wdn][1][lane];
+      const T above = whi ? T(0) : sm.e1[sl][wup][0][lane];
+      const bool kin2 = k - 1 >= 1 && k - 1 <= g.nz;
+      const bool kout2 = k - 1 >= k0 && k - 1 < k1;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        const T xm = from_left(u1m1[r]), xp = from_right(u1m1[r]);
+        const T xm = shift_in_left(u1m1[r]), xp = shift_in_right(u1m1[r]);
         const T ym = r == 0 ? below : u1m1[r - 1];
         const T yp = r == RY - 1 ? above : u1m1[r + 1];
         T s = xm + xp;
@@ -178,12 +309,14 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
         s = s + yp;
         s = s + u1m2[r];
         s = s + u1[r];
-        const bool pt_in = col_in[r] && k - 1 >= 1 && k - 1 <= g.nz;
+        const bool pt_in = col_in[r] && kin2;
         u2[r] = (pt_in && inner2[r]) ? div6(s + h2 * fm1[r]) : u1m1[r];
         if (FL & F_RES1) {
-          const double res = static_cast<double>(fm1[r]) -
-                             (6.0 * static_cast<double>(u1m1[r]) - static_cast<double>(s)) / g.h2;
-          acc += (inner3[r] && pt_in && k - 1 >= k0 && k - 1 < k1) ? res * res : 0.0;
+          if (inner3[r] && pt_in && kout2) {
+            const double res = static_cast<double>(fm1[r]) -
+                               (6.0 * static_cast<double>(u1m1[r]) - static_cast<double>(s)) / g.h2;
+            acc += res * res;
+          }
         }
       }
     }
@@ -191,11 +324,11 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     // of plane k-2 were written in the previous step
     if (k - 2 >= k0) {
       const int sl = (k - 2) & 1;
-      const T below = wy > 0 ? sm.e2[sl][wy - 1][1][lane] : T(0);
-      const T above = wy < BY - 1 ? sm.e2[sl][wy + 1][0][lane] : T(0);
+      const T below = wlo ? T(0) : sm.e2[sl][wdn][1][lane];
+      const T above = whi ? T(0) : sm.e2[sl][wup][0][lane];
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        const T xm = from_left(u2m1[r]), xp = from_right(u2m1[r]);
+        const T xm = shift_in_left(u2m1[r]), xp = shift_in_right(u2m1[r]);
         if (inner3[r]) {
           const T ym = r == 0 ? below : u2m1[r - 1];
           const T yp = r == RY - 1 ? above : u2m1[r + 1];
@@ -204,18 +337,12 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
           s = s + yp;
           s = s + u2m2[r];
           s = s + u2[r];
-          const T u3 = div6(s + h2 * fm2[r]);
+          st[r] = div6(s + h2 * fm2[r]);
           if (FL & F_RES2) {
-            const double res = static_cast<double>(fm2[r]) -
-                               (6.0 * static_cast<double>(u2m1[r]) - static_cast<double>(s)) / g.h2;
-            acc += col_in[r] ? res * res : 0.0;
-          }
-          if (col_in[r]) {
-            if (FL & F_LAST) {
-              double* q = u64 + co[r] + g.s64_z * (k - 2);
-              q[0] = q[0] + static_cast<double>(u3);
-            } else {
-              put<T, NT>(out + co[r] + g.so_z * (k - 2), u3);
+            if (col_in[r]) {
+              const double res = static_cast<double>(fm2[r]) -
+                                 (6.0 * static_cast<double>(u2m1[r]) - static_cast<double>(s)) / g.h2;
+              acc += res * res;
             }
           }
         }
@@ -233,6 +360,7 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     if (k + 2 > k1 + 1) break;
     step(k + 2, u0C, u0A, u0B, fC, fA, fB, u1C, u1A, u1B, u2C, u2A, u2B);
   }
+  flush(k1 - 1);  // the last step computed u3 of plane k1 - 1
 
   if (RES_ANY != 0) {
     const double tot = block_sum<BY>(acc, sm.red);
