@@ -428,7 +428,7 @@ int j3d_autotune(int32_t ngrids, j3d_grid* grids, j3d_tune* best, void* stream);
 #define J3D_KIND_F32X2 3
 /* The three-sweep passes of jacobi3d_sweep3 (the FP32 one also runs the
  * correction sweeps of the mixed solve): one wavefront along x, not
- * persistent, rows 2, 4 or 8 wavefronts of 2 or 4 rows per thread
+ * persistent, rows 2, 4, 8 or 16 wavefronts of 2 or 4 rows per thread
  * (variants 6 and 20) with rows x rows-per-thread between 8 and 32; a block
  * has that many rows minus 4 output rows and 58 output columns. */
 #define J3D_KIND_F64X3 4

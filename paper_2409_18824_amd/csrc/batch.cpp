@@ -584,9 +584,9 @@ int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, L
 
 std::vector<TileCfg> sweep3_candidates(int dtype) {
   std::vector<TileCfg> v;
-  for (int rows : {2, 4, 8})
+  for (int rows : {2, 4, 8, 16})
     for (int var : {6, 20})
-      for (int planes : {16, 24, 32, 48, 64})
+      for (int planes : {16, 24, 32, 48, 64, 96})
         for (int order : {0, 1, 2}) {
           TileCfg c{rows, planes, var, 0, order, 1};
           if (tile3_cfg_supported(dtype, c)) v.push_back(c);

@@ -53,20 +53,23 @@ TileCfg default_cfg3(int dtype, int nx, int ny, int nz) {
   const int kind = dtype == J3D_F32 ? J3D_KIND_F32X3 : J3D_KIND_F64X3;
   if (tune_cache_lookup_single(kind, nx, ny, nz, &c) && tile3_cfg_supported(dtype, c)) return c;
   // measured on cubes from 96^3 to 512^3 (nontemporal stores throughout):
-  // 4 wavefronts; up to about 200^3 points 2 rows per thread and 16 planes
-  // (more, thinner tiles); up to about 300^3, 4 rows per thread; beyond,
-  // 32 planes, and at 512^3 48 planes in FP64 and 24 in FP32.  Order:
-  // XCD-blocked for small grids, per-slab XCD chunks above, launch order for
-  // FP64 at 512^3.
+  // up to about 200^3 points 4 wavefronts of 2 rows per thread and 16
+  // planes (more, thinner tiles), XCD-blocked; up to about 300^3, 4
+  // wavefronts of 4 rows per thread, per-slab XCD chunks; beyond, 8
+  // wavefronts of 2 rows per thread (about 95 registers per thread against
+  // 160 with 4 rows, so twice the wavefronts per CU), 32 planes in
+  // per-slab XCD chunks, and above 400^3 96 planes in launch order (512^3:
+  // 722 us per FP64 pass against 776 with 4 x 4 rows and 48 planes; FP32
+  // 445 against 452 us).
   const long long pts = (long long)nx * ny * nz;
   const bool small = pts <= 200LL * 200 * 200;
   const bool large = pts > 300LL * 300 * 300;
   const bool huge = pts > 400LL * 400 * 400;
-  c.rows = 4;
-  c.planes = huge ? (dtype == J3D_F32 ? 24 : 48) : large ? 32 : 16;
-  c.variant = small ? 6 : 20;
+  c.rows = large ? 8 : 4;
+  c.planes = huge ? 96 : large ? 32 : 16;
+  c.variant = (small || large) ? 6 : 20;
   c.persistent = 0;
-  c.order = small ? 0 : ((huge && dtype != J3D_F32) ? 1 : 2);
+  c.order = small ? 0 : huge ? 1 : 2;
   c.cols = 1;
   return c;
 }

@@ -78,8 +78,8 @@ hipError_t launch_sweep2_batch(int dtype, unsigned flags, const TileCfg& c, cons
                                int ngrids, int ntiles, double* partials, const int* done,
                                hipStream_t st);
 
-// Three sweeps in one pass: g.o = J(J(J(g.u))), tile shapes of rows 2, 4 or
-// 8 wavefronts of 2 or 4 rows per thread (variants 6 and 20), cols 1, not
+// Three sweeps in one pass: g.o = J(J(J(g.u))), tile shapes of rows 2, 4, 8
+// or 16 wavefronts of 2 or 4 rows per thread (variants 6 and 20), cols 1, not
 // persistent; 58 x (rows x rows-per-thread - 4) outputs per block.  Flags as
 // for the two-sweep pass.
 bool tile3_cfg_supported(int dtype, const TileCfg& c);

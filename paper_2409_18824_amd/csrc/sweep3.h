@@ -411,12 +411,12 @@ __global__ void __launch_bounds__(WAVE * BY)
   }
 }
 
-// Instantiated three-sweep shapes: one wavefront along x, 2, 4 or 8
+// Instantiated three-sweep shapes: one wavefront along x, 2, 4, 8 or 16
 // wavefronts of 2 or 4 rows per thread (blocks of 8 to 32 rows),
 // nontemporal stores.
 constexpr bool shape3_instantiated(int by, int var) {
   const int tr = by * rows_per_thread(var);
-  const bool by_ok = by == 2 || by == 4 || by == 8;
+  const bool by_ok = by == 2 || by == 4 || by == 8 || by == 16;
   return (var == 6 || var == 20) && tr >= 8 && tr <= 32 && by_ok;
 }
 
@@ -459,6 +459,7 @@ hipError_t by_shape3_batch(const TileCfg& c, const GridArgs* table, int ngrids, 
     case 420: return go3_batch<T, 4, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
     case 806: return go3_batch<T, 8, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
     case 820: return go3_batch<T, 8, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 1606: return go3_batch<T, 16, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -472,6 +473,7 @@ hipError_t by_shape3(const TileCfg& c, const GridArgs& g, double* partials, cons
     case 420: return go3<T, 4, 20, FL>(g, partials, done, st);
     case 806: return go3<T, 8, 6, FL>(g, partials, done, st);
     case 820: return go3<T, 8, 20, FL>(g, partials, done, st);
+    case 1606: return go3<T, 16, 6, FL>(g, partials, done, st);
     default: return hipErrorInvalidValue;
   }
 }
