@@ -117,9 +117,29 @@ def measured_traffic(kernel_hash: str, passes: int, tile):
     return d.get("bytes_per_launch")
 
 
+def host_cpu():
+    """CPU model and the number of host threads this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fp:
+            for line in fp:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count()
+    return model, nproc
+
+
 def cpu_baseline(n: int, h: float, budget_s: float = 10.0):
     """Time the oracle on a bounded sample: sweeps of the same 512^3 grid with
-    the same residual cadence (a residual pass before sweep 0 and every 10th)."""
+    the same residual cadence (a residual pass before sweep 0 and every 10th),
+    in groups of 10 sweeps; value is the rate over the whole sample, median
+    the median rate of its groups."""
     import numpy as np
 
     import oracle
@@ -129,20 +149,28 @@ def cpu_baseline(n: int, h: float, budget_s: float = 10.0):
     a, b = u0, u0.copy()
     t0 = time.perf_counter()
     sweeps = 0
+    groups = []
+    tg = t0
     while True:
         if sweeps % 10 == 0:
             oracle.residual_l2(a, f, h)
         oracle.sweep(a, f, h, out=b)
         a, b = b, a
         sweeps += 1
-        el = time.perf_counter() - t0
+        now = time.perf_counter()
+        if sweeps % 10 == 0:
+            groups.append(10 * n ** 3 / (now - tg) / 1e9)
+            tg = now
+        el = now - t0
         if el >= budget_s or sweeps >= 500:
             break
     glups = sweeps * n ** 3 / el / 1e9
     del u0, f, a, b
+    model, nproc = host_cpu()
     return {"value": glups, "unit": "GLUP/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%d of the 500 FP64 sweeps of the %d^3 grid (%d residual passes), %.1f s" % (
-                sweeps, n, (sweeps + 9) // 10, el)}
+            "median": float(np.median(groups)) if groups else glups, "cpu_model": model, "host_threads": nproc,
+            "sample": "%d of the 500 FP64 sweeps of the %d^3 grid (%d residual passes), %.1f s; median over "
+                      "groups of 10 sweeps" % (sweeps, n, (sweeps + 9) // 10, el)}
 
 
 def main():
@@ -173,7 +201,10 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="pin the tile shape as rows,planes,variant,persistent,order[,cols] instead of autotuning")
     ap.add_argument("--probe", action="store_true",
-                    help="also time the copy kernel on 2 x 1 GiB (achievable-bandwidth ceiling)")
+                    help="advection workloads: also time the copy kernels on 2 x 1 GiB (achievable-bandwidth "
+                         "ceiling; the default workload always does)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="default workload: skip the copy-ceiling probe")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -278,6 +309,7 @@ def main():
     assert np.all(np.isfinite(r)) and r[-1] < r[0], "residual did not decrease"
 
     avg_ms = float(np.mean(kernel_ms))
+    med_ms = float(np.median(kernel_ms))
     bytes_launch = BYTES_PER_LUP_F64 * n ** 3  # read u, read f, write the result
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
@@ -286,18 +318,19 @@ def main():
              3: "k_sweep3_one<F_WRITE> (three FP64 sweeps per pass)"}[P]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(khash, P, tune),
-            "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "kernel": kname, "avg_launch_us": round(avg_ms * 1e3, 2), "median_launch_us": round(med_ms * 1e3, 2),
             "launches": len(kernel_ms), "bytes_per_launch_algorithmic": int(bytes_launch),
             "updates_per_point_per_launch": P}
 
-    probe = None
-    if args.probe:
+    if not args.no_probe:
+        # the achievable streaming rate of this machine: the best of the library's
+        # copy kernels over 1 GiB (read + write bytes per second)
         nprobe = 1 << 27  # 1 GiB of doubles per buffer
         src = torch.ones(nprobe, dtype=torch.float64, device="cuda")
         dst = torch.zeros(nprobe, dtype=torch.float64, device="cuda")
-        probe = {"copy_gbps": round(j3d.j3d_bandwidth_probe(src, dst, reps=5), 1), "bytes_per_launch": 2 * 8 * nprobe}
-        roof["copy_ceiling_gbps"] = probe["copy_gbps"]
-        roof["frac_of_copy_ceiling"] = round(achieved / probe["copy_gbps"], 4)
+        copy_gbps = j3d.j3d_bandwidth_probe(src, dst, reps=5)
+        roof["copy_ceiling_gbps"] = round(copy_gbps, 1)
+        roof["frac_of_copy_ceiling"] = round(achieved / copy_gbps, 4)
         del src, dst
 
     cpu = None
@@ -341,7 +374,7 @@ def run_mixed(args):
     import synth
     from paper_2409_18824_amd import j3d
 
-    n = args.n if "--n" in sys.argv else 256
+    n = args.n
     h = 1.0 / (n + 1)
     f = synth.manufactured_f(n, n, n, h)
     df = j3d.FArray.from_numpy(f)
@@ -420,10 +453,46 @@ def run_batch(args):
     glups = pts * nsw * args.steps / el / 1e9
     r = out.cpu().numpy()
     assert np.all(np.isfinite(r)) and np.all(r[:, -1] < r[:, 0])
-    return _base(args, "GLUP/s (batched uneven grids)", round(glups, 3), "GLUP/s", round(el / args.steps * 1e3, 3),
-                 "f64", "batch-256-grids-32to256-200sweeps-resid10",
-                 extra={"grids": len(grids), "points": pts, "tile": tune,
-                        "single_sweep_equivalent_gbs": round(glups * 24.0, 1)})
+    # one more call from u0 = 0, sampled against the oracle: the smallest and
+    # the largest grid, the first and last of the tile list, four seeded others
+    import oracle
+
+    for ua, ub, _, _ in grids:
+        j3d.j3d_fill_const(ua, 0.0)
+        j3d.j3d_fill_const(ub, 0.0)
+    j3d.jacobi3d_sweep_batch(grids, nsw, every, out)
+    torch.cuda.synchronize()
+    r = out.cpu().numpy()
+    sizes = [g.nx * g.ny * g.nz for g in shapes]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes)), 0, len(shapes) - 1}
+    rng = np.random.default_rng(7)
+    while len(pick) < 8:
+        pick.add(int(rng.integers(0, len(shapes))))
+    err_u, err_r, t_or, lups_or = 0.0, 0.0, 0.0, 0.0
+    for gi in sorted(pick):
+        g = shapes[gi]
+        f = synth.batch_rhs(g)
+        t0 = time.perf_counter()
+        uo, ro = oracle.solve_plain(np.zeros_like(f), f, g.h, rtol=0.0, check_every=every, max_sweeps=nsw)
+        t_or += time.perf_counter() - t0
+        lups_or += float(sizes[gi]) * nsw
+        got = grids[gi][0].to_numpy()
+        err_u = max(err_u, float(np.max(np.abs(got - uo))) / max(float(np.max(np.abs(uo))), 1e-300))
+        err_r = max(err_r, float(np.max(np.abs(r[gi] - ro.history) / ro.history)))
+    print("[bench] batch oracle check: %d grids, max rel diff u %.3g, residuals %.3g" % (len(pick), err_u, err_r),
+          file=sys.stderr, flush=True)
+    out_d = _base(args, "GLUP/s (batched uneven grids)", round(glups, 3), "GLUP/s", round(el / args.steps * 1e3, 3),
+                  "f64", "batch-256-grids-32to256-200sweeps-resid10",
+                  extra={"grids": len(grids), "points": pts, "tile": tune,
+                         "single_sweep_equivalent_gbs": round(glups * 24.0, 1)})
+    out_d["oracle_error"] = {"grids_checked": sorted(pick), "max_rel_diff_u": err_u, "max_rel_diff_resid": err_r,
+                             "reference": "oracle.solve_plain of each sampled grid alone, 200 sweeps, residual every 10"}
+    model, nproc = host_cpu()
+    out_d["cpu_baseline"] = {"value": round(lups_or / t_or / 1e9, 3), "unit": "GLUP/s", "cores": oracle.threads(),
+                             "kind": "oracle", "cpu_model": model, "host_threads": nproc,
+                             "sample": "the %d sampled grids, 200 sweeps each with residuals every 10, %.1f s" % (
+                                 len(pick), t_or)}
+    return out_d
 
 
 def run_small(args):
@@ -693,38 +762,33 @@ def run_tra_adv(args):
     return out
 
 
-def run_serve(args):
-    """Poisson arrivals at 200/s through the continuous-batching server."""
+def _serve_stream(reqs, precision, args, sample):
+    """Push the request stream through a server of the given precision, at
+    the stream's arrival times.  Returns the results (by request id), the
+    host copies of the sampled requests' solutions and the run's span."""
     import numpy as np
-    import torch
 
-    import synth
     from paper_2409_18824_amd import j3d
 
-    reqs = synth.serve_requests(args.requests, rate=args.rate, seed=5)
-    # warm the kernels with one small solve
-    with j3d.Server(hbm_budget_bytes=8 << 30, max_slots=4, cycle_sweeps=50) as s:
-        s.submit(32, 1 / 33, 1e-6, 100, seed=1)
-        s.drain(60)
-        s.poll()
     budget = 200 * 10 ** 9
-    results = {}
-    print("[bench] serving %d requests" % len(reqs), file=sys.stderr, flush=True)
+    results, outs, tick = {}, {}, {}
     with j3d.Server(hbm_budget_bytes=budget, max_slots=2048, cycle_sweeps=50,
-                    max_active_points=int(args.active_points)) as s:
+                    max_active_points=int(args.active_points), precision=precision) as s:
         t_start = time.perf_counter()
-        tick = {}
         for r in reqs:
             now = time.perf_counter() - t_start
             if r.arrival_s > now:
                 time.sleep(r.arrival_s - now)
-            tick[s.submit(r.n, r.h, r.rtol, r.max_sweeps, seed=r.seed)] = r
+            u = None
+            if r.rid in sample:
+                u = outs[r.rid] = np.zeros((r.n + 2,) * 3)
+            tick[s.submit(r.n, r.h, r.rtol, r.max_sweeps, seed=r.seed, u_out=u)] = r
             for x in s.poll():
-                results[x["ticket"]] = x
+                results[tick[x["ticket"]].rid] = x
         last = time.perf_counter()
         while len(results) < len(reqs):
             for x in s.poll():
-                results[x["ticket"]] = x
+                results[tick[x["ticket"]].rid] = x
             if time.perf_counter() - last > 5:
                 st = s.stats()
                 print("[bench] serve: %d done, %d active, %d queued" % (len(results), st["active"], st["queued"]),
@@ -732,25 +796,120 @@ def run_serve(args):
                 last = time.perf_counter()
             time.sleep(0.01)
         s.drain(600)
-    lat = np.array([x["t_done"] - x["t_submit"] for x in results.values()])
-    t0 = min(x["t_submit"] for x in results.values())
-    t1 = max(x["t_done"] for x in results.values())
-    conv = np.array([x["converged"] for x in results.values()])
-    tol8 = np.array([tick[k].rtol == 1e-8 for k in results])
-    sweeps = np.array([x["sweeps"] for x in results.values()])
-    ns = np.array([tick[k].n for k in results])
-    lups = float(np.sum(ns.astype(np.float64) ** 3 * sweeps))
-    out = _base(args, "served solves/s (mixed precision, continuous batching)", round(len(results) / (t1 - t0), 3),
-                "solves/s", round((t1 - t0) * 1e3, 1), "f32+f64",
+    return results, outs
+
+
+def _serve_stats(reqs, results):
+    import numpy as np
+
+    by = {r.rid: r for r in reqs}
+    ids = sorted(results)
+    lat = np.array([results[i]["t_done"] - results[i]["t_submit"] for i in ids])
+    t0 = min(results[i]["t_submit"] for i in ids)
+    t1 = max(results[i]["t_done"] for i in ids)
+    conv = np.array([results[i]["converged"] for i in ids])
+    tol8 = np.array([by[i].rtol == 1e-8 for i in ids])
+    relres = np.array([results[i]["resid"] / results[i]["norm_f"] for i in ids])
+    sweeps = np.array([results[i]["sweeps"] for i in ids], dtype=np.float64)
+    ns = np.array([by[i].n for i in ids], dtype=np.float64)
+
+    def pct(mask):
+        if not mask.any():
+            return None
+        return {"count": int(mask.sum()), "p50_s": round(float(np.percentile(lat[mask], 50)), 3),
+                "p99_s": round(float(np.percentile(lat[mask], 99)), 3),
+                "rel_resid_median": float(np.median(relres[mask])), "rel_resid_max": float(np.max(relres[mask]))}
+
+    return {
+        "solves_per_s": round(len(ids) / (t1 - t0), 3), "span_s": round(t1 - t0, 3),
+        "latency_s": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
+        "tol1e-8": {"all": pct(tol8), "converged": pct(tol8 & conv), "capped": pct(tol8 & ~conv)},
+        "tol1e-6": {"all": pct(~tol8), "converged": pct(~tol8 & conv), "capped": pct(~tol8 & ~conv)},
+        "converged_fraction": round(float(conv.mean()), 3),
+        "lups": float(np.sum(ns ** 3 * sweeps)), "sweeps": sweeps, "ns": ns, "checks": np.ceil(sweeps / 50.0) + 1,
+    }
+
+
+def run_serve(args):
+    """The served request stream (Poisson arrivals, cubic n log-uniform in
+    [32, 384], tolerance 1e-6 or 1e-8, cap 5000 sweeps) through the
+    continuous-batching server, once in mixed precision (the served form)
+    and once in plain FP64 (the form it is measured against), same stream,
+    same GPU.  Every 10th request with n <= 128 is also solved by the oracle
+    alone and its result compared with the served one."""
+    import numpy as np
+
+    import oracle
+    import synth
+    from paper_2409_18824_amd import j3d
+
+    reqs = synth.serve_requests(args.requests, rate=args.rate, seed=5)
+    sample = {r.rid for r in reqs if r.rid % 10 == 0 and r.n <= 128}
+    for prec in (j3d.SERVE_MIXED, j3d.SERVE_FP64):  # warm the kernels with one small solve
+        with j3d.Server(hbm_budget_bytes=8 << 30, max_slots=4, cycle_sweeps=50, precision=prec) as s:
+            s.submit(32, 1 / 33, 1e-6, 100, seed=1)
+            s.drain(60)
+            s.poll()
+    runs = {}
+    for prec, name in ((j3d.SERVE_MIXED, "mixed"), (j3d.SERVE_FP64, "fp64")):
+        print("[bench] serving %d requests at %g/s, %s" % (len(reqs), args.rate, name), file=sys.stderr, flush=True)
+        results, outs = _serve_stream(reqs, prec, args, sample)
+        st = _serve_stats(reqs, results)
+        # the oracle alone on the sampled requests
+        t_or, lups_or, err_u, err_r = 0.0, 0.0, 0.0, 0.0
+        for r in reqs:
+            if r.rid not in sample:
+                continue
+            f = synth.uniform_field(r.n, r.n, r.n, r.seed, synth.STREAM_F, -1.0, 1.0)
+            t0 = time.perf_counter()
+            if prec == j3d.SERVE_MIXED:
+                uo, ro = oracle.solve_mixed(np.zeros_like(f), f, r.h, rtol=r.rtol, inner=50, max_sweeps=r.max_sweeps)
+            else:
+                uo, ro = oracle.solve_plain(np.zeros_like(f), f, r.h, rtol=r.rtol, check_every=50,
+                                            max_sweeps=r.max_sweeps)
+            t_or += time.perf_counter() - t0
+            lups_or += float(r.n) ** 3 * ro.sweeps
+            g = results[r.rid]
+            assert g["sweeps"] == ro.sweeps and g["converged"] == ro.converged, (r, g, ro.sweeps)
+            err_u = max(err_u, float(np.max(np.abs(outs[r.rid] - uo))) / max(float(np.max(np.abs(uo))), 1e-300))
+            err_r = max(err_r, abs(g["resid"] - ro.resid) / ro.resid)
+        st["oracle_error"] = {"requests_checked": len(sample), "max_rel_diff_u": err_u,
+                              "max_rel_diff_resid": err_r,
+                              "reference": "oracle.solve_%s of each sampled request alone" % (
+                                  "mixed" if prec == j3d.SERVE_MIXED else "plain")}
+        st["oracle_glups"] = round(lups_or / t_or / 1e9, 3) if t_or > 0 else None
+        st["oracle_seconds"] = round(t_or, 2)
+        print("[bench] %s: %.3f solves/s, p50 %.3f s, p99 %.3f s, oracle error %s" % (
+            name, st["solves_per_s"], st["latency_s"]["p50"], st["latency_s"]["p99"], st["oracle_error"]),
+            file=sys.stderr, flush=True)
+        runs[name] = st
+    mx, fp = runs["mixed"], runs["fp64"]
+    # algorithmic bytes of the served work, single-sweep terms: mixed 12 per
+    # FP32 update and 20 per point per defect step (read u, f; write r32);
+    # FP64 24 per update and 16 per point per residual check
+    bytes_mx = 12.0 * mx["lups"] + 20.0 * float(np.sum(mx["ns"] ** 3 * mx["checks"]))
+    gbs = bytes_mx / mx["span_s"] / 1e9
+    for st in runs.values():
+        st["glups_served"] = round(st["lups"] / st["span_s"] / 1e9, 2)
+        for k in ("lups", "sweeps", "ns", "checks"):
+            st.pop(k)
+    out = _base(args, "served solves/s (mixed precision, continuous batching)", mx["solves_per_s"],
+                "solves/s", round(mx["span_s"] * 1e3, 1), "f32+f64",
                 "serve-poisson-%grps-n32to384-tol1e-6or1e-8-cap5000" % args.rate,
-                extra={"requests": len(results), "offered_rate_per_s": args.rate, "hbm_budget_bytes": budget,
-                       "max_active_points": int(args.active_points)})
-    out["latency_s"] = {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
-                        "p50_tol1e-8": round(float(np.percentile(lat[tol8], 50)), 3) if tol8.any() else None,
-                        "p99_tol1e-8": round(float(np.percentile(lat[tol8], 99)), 3) if tol8.any() else None}
-    out["converged_fraction"] = round(float(conv.mean()), 3)
-    out["converged_fraction_tol1e-8"] = round(float(conv[tol8].mean()), 3) if tol8.any() else None
-    out["glups_served"] = round(lups / (t1 - t0) / 1e9, 2)
+                extra={"requests": len(reqs), "offered_rate_per_s": args.rate, "hbm_budget_bytes": 200 * 10 ** 9,
+                       "max_active_points": int(args.active_points), "cycle_sweeps": 50})
+    out["latency_s"] = mx["latency_s"]
+    out["mixed"] = mx
+    out["fp64"] = fp
+    out["speedup_mixed_vs_fp64_solves_per_s"] = round(mx["solves_per_s"] / fp["solves_per_s"], 3)
+    out["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "basis": "single-sweep algorithmic bytes of the mixed run's work over its span"}
+    model, nproc = host_cpu()
+    out["cpu_baseline"] = {"value": mx["oracle_glups"], "unit": "GLUP/s", "cores": oracle.threads(),
+                           "kind": "oracle", "cpu_model": model, "host_threads": nproc,
+                           "sample": "the %d sampled requests (every 10th with n <= 128) solved one by one by "
+                                     "oracle.solve_mixed, %.1f s" % (len(sample), mx["oracle_seconds"])}
     return out
 
 

@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define J3D_ABI_VERSION 1
+#define J3D_ABI_VERSION 2
 
 /* dtype codes */
 #define J3D_F64 0
@@ -181,8 +181,8 @@ int jacobi3d_sweep3(const j3d_array* u_in, j3d_array* u_out, const j3d_array* f,
  * static device array of 65536 doubles (512 KiB) that every GPU the library
  * runs on holds until the process ends; a grid whose three-sweep tiling
  * needs more tiles than that returns J3D_EINVAL before any device work
- * (with the default tile shapes every cube up to 1270^3 fits; a smaller
- * pinned or autotuned tile shape lowers that).  Every call on
+ * (with the default tile shapes every cube within the 2^31-element limit
+ * fits; a smaller pinned or autotuned tile shape can exceed it).  Every call on
  * one GPU uses that GPU's one array, so calls that may overlap in time on
  * the same GPU (other streams, other threads) race and must be ordered by
  * the caller.  Errors: as jacobi3d_sweep3, and J3D_EINVAL for the cases
@@ -454,15 +454,22 @@ int j3d_tune_query_single(int32_t kind, int32_t nx, int32_t ny, int32_t nz, j3d_
 
 typedef struct j3d_server j3d_server;
 
+/* Precision of a server's solves */
+#define J3D_SERVE_MIXED 0 /* FP32 correction sweeps with FP64 defect correction */
+#define J3D_SERVE_FP64 1  /* plain FP64 Jacobi sweeps (the reference form) */
+
 typedef struct j3d_serve_opts {
   uint64_t hbm_budget_bytes;  /* device memory the server may hold for request state */
   int32_t max_slots;          /* maximum concurrently active requests */
-  int32_t cycle_sweeps;       /* FP32 sweeps per defect-correction cycle (e.g. 50) */
+  int32_t cycle_sweeps;       /* sweeps per cycle (e.g. 50): FP32 sweeps per defect-correction
+                                 cycle, or FP64 sweeps between residual checks */
   int32_t device;             /* HIP device ordinal */
   int32_t queue_cap;          /* maximum queued (not yet admitted) requests */
   uint64_t max_active_points; /* admit while active interior points stay at or below
                                  this (a request is admitted regardless when nothing is
                                  active); 0: no limit */
+  int32_t precision;          /* J3D_SERVE_MIXED or J3D_SERVE_FP64 */
+  int32_t reserved;           /* must be 0 */
 } j3d_serve_opts;
 
 typedef struct j3d_request {
@@ -487,8 +494,12 @@ typedef struct j3d_result {
   double t_submit, t_admit, t_done;  /* seconds on the server's monotonic clock */
 } j3d_result;
 
-/* Bytes of device state one request of this size holds while active. */
+/* Bytes of device state one request of this size holds while active on a
+ * mixed-precision server (u, f FP64; r, two corrections FP32: about 28 bytes
+ * per padded point), and on a server of either precision (FP64: u, f and a
+ * second iterate, about 24 bytes per padded point); 0 for bad arguments. */
 uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz);
+uint64_t j3d_request_state_bytes(int32_t precision, int32_t nx, int32_t ny, int32_t nz);
 
 /*
  * Create a server with its own worker thread and HIP stream on opts->device.
@@ -502,7 +513,16 @@ uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz);
  * result does not depend on which others share its cycles.  The FP32 sweeps
  * of a cycle run two per pass over memory, or three when the cycle's FP32
  * state exceeds 512 MB (J3D_SERVE_TRIPLES=0 or =1 forces one or the other);
- * the iterates are the same bit for bit either way.
+ * the iterates are the same bit for bit either way.  A request's result is
+ * that of poisson_solve in MIXED mode with inner_sweeps = cycle_sweeps and
+ * max_sweeps rounded up to whole cycles.
+ * With precision J3D_SERVE_FP64 a cycle is instead the FP64 residual check
+ * of each slot's current iterate followed by cycle_sweeps FP64 Jacobi sweeps
+ * (two or three per pass over memory, three when the cycle's FP64 state
+ * exceeds 512 MB), so a request's result is that of poisson_solve in FP64
+ * mode with check_every = cycle_sweeps: the plain form the mixed one is
+ * measured against, under the same admission and batching.  Errors:
+ * J3D_EINVAL (bad options, precision or reserved), J3D_EHIP.
  */
 int poisson_serve_create(const j3d_serve_opts* opts, j3d_server** out);
 /* Queue a request.  J3D_EBUDGET if it can never fit; J3D_EAGAIN if the queue
@@ -538,8 +558,10 @@ int j3d_fill_const(j3d_array* a, double value, void* stream);
 
 /*
  * Streaming probe for the achievable memory bandwidth: copies n doubles from
- * src to dst (device) `reps` times and returns the best rate in GB/s
- * (bytes read + written per second).  Blocks.
+ * src to dst (device) `reps` times with each of several copy kernels (a
+ * grid-stride loop over 16-byte elements; one or four 16-byte elements per
+ * thread, each with plain or nontemporal loads and stores) and returns the
+ * best rate in GB/s (bytes read + written per second).  Blocks.
  */
 int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps,
                         double* gbps, void* stream);

@@ -354,17 +354,19 @@ int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps,
   hipEvent_t e0, e1;
   J3D_HIP(hipEventCreate(&e0));
   J3D_HIP(hipEventCreate(&e1));
-  J3D_HIP(launch_copy(src, dst, n, st));  // warm-up
   double best = 0.0;
-  for (int r = 0; r < reps; ++r) {
-    J3D_HIP(hipEventRecord(e0, st));
-    J3D_HIP(launch_copy(src, dst, n, st));
-    J3D_HIP(hipEventRecord(e1, st));
-    J3D_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    J3D_HIP(hipEventElapsedTime(&ms, e0, e1));
-    const double rate = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
-    if (rate > best) best = rate;
+  for (int v = 0; v < kCopyVariants; ++v) {
+    J3D_HIP(launch_copy_variant(v, src, dst, n, st));  // warm-up
+    for (int r = 0; r < reps; ++r) {
+      J3D_HIP(hipEventRecord(e0, st));
+      J3D_HIP(launch_copy_variant(v, src, dst, n, st));
+      J3D_HIP(hipEventRecord(e1, st));
+      J3D_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      J3D_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double rate = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
+      if (rate > best) best = rate;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -161,6 +161,12 @@ hipError_t launch_fill_uniform(double* a, int ex, int ey, int ez, long long sy, 
 hipError_t launch_fill_const(void* a, int dtype, int ex, int ey, int ez, long long sy,
                              long long sz, double v, hipStream_t st);
 hipError_t launch_copy(const double* src, double* dst, long long n, hipStream_t st);
+// Copy kernels of the bandwidth probe: 0 the library's copy (grid-stride
+// over 16-byte elements), 1 one 16-byte element per thread, 2 the same
+// with nontemporal loads and stores, 3 four per thread, 4 four per thread
+// nontemporal.
+constexpr int kCopyVariants = 5;
+hipError_t launch_copy_variant(int v, const double* src, double* dst, long long n, hipStream_t st);
 hipError_t launch_copy_interior(const double* src, double* dst, int nx, int ny, int nz,
                                 long long ssy, long long ssz, long long dsy, long long dsz,
                                 hipStream_t st);

@@ -216,6 +216,33 @@ __global__ void __launch_bounds__(256) k_copy(const double2* __restrict__ src,
     dst[q] = src[q];
 }
 
+// Copy probes of other shapes: U 16-byte elements per thread (consecutive
+// blocks of 256 elements, so every load instruction stays coalesced), with
+// or without nontemporal loads and stores.
+typedef double copy_vd2 __attribute__((ext_vector_type(2)));
+
+template <int U, bool NT>
+__global__ void __launch_bounds__(256) k_copy_u(const copy_vd2* __restrict__ src, copy_vd2* __restrict__ dst,
+                                                long long n2) {
+  const long long base = (long long)blockIdx.x * 256 * U + threadIdx.x;
+  copy_vd2 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long q = base + 256LL * u;
+    if (q < n2) v[u] = NT ? __builtin_nontemporal_load(src + q) : src[q];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long q = base + 256LL * u;
+    if (q < n2) {
+      if (NT)
+        __builtin_nontemporal_store(v[u], dst + q);
+      else
+        dst[q] = v[u];
+    }
+  }
+}
+
 __global__ void k_copy_tail(const double* __restrict__ src, double* __restrict__ dst, long long n) {
   if (threadIdx.x == 0 && (n & 1)) dst[n - 1] = src[n - 1];
 }
@@ -430,6 +457,23 @@ hipError_t launch_sum(const double* x, const double* y, long long n, double* par
                          partials);
   }
   hipLaunchKernelGGL(k_reduce_plain, dim3(1), dim3(RED_THREADS), 0, st, partials, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_variant(int v, const double* src, double* dst, long long n, hipStream_t st) {
+  if (v == 0) return launch_copy(src, dst, n, st);
+  const long long n2 = n / 2;
+  const int u = (v == 1 || v == 2) ? 1 : 4;
+  const bool nt = v == 2 || v == 4;
+  const long long blocks = (n2 + 256LL * u - 1) / (256LL * u);
+  if (blocks > (1LL << 30)) return hipErrorInvalidValue;
+  const auto* s2 = reinterpret_cast<const copy_vd2*>(src);
+  auto* d2 = reinterpret_cast<copy_vd2*>(dst);
+  if (u == 1 && !nt) hipLaunchKernelGGL((k_copy_u<1, false>), dim3(blocks), dim3(256), 0, st, s2, d2, n2);
+  if (u == 1 && nt) hipLaunchKernelGGL((k_copy_u<1, true>), dim3(blocks), dim3(256), 0, st, s2, d2, n2);
+  if (u == 4 && !nt) hipLaunchKernelGGL((k_copy_u<4, false>), dim3(blocks), dim3(256), 0, st, s2, d2, n2);
+  if (u == 4 && nt) hipLaunchKernelGGL((k_copy_u<4, true>), dim3(blocks), dim3(256), 0, st, s2, d2, n2);
+  hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

@@ -9,6 +9,11 @@
 //      have sweeps left (done slots are skipped by flag), two sweeps per pass
 //      over memory where the count allows; the last pass adds the correction
 //      to u.
+// With J3D_SERVE_FP64 precision a slot holds u, f and a second FP64 iterate
+// w instead, and a cycle is the residual check of the current iterate
+// (batched residual pass and reduce, as above) followed by cycle_sweeps
+// batched FP64 Jacobi sweeps ping-ponging between u and w: the plain FP64
+// solve with a check every cycle_sweeps sweeps, served the same way.
 // While a cycle runs on the GPU the worker admits queued requests (in
 // arrival order, while their state fits the memory budget and a slot is
 // free): it allocates their state and queues their set-up behind the cycle.
@@ -42,15 +47,17 @@ using namespace j3d;
 namespace {
 
 struct Layout {
-  Field u, f, r32, e0, e1;
+  Field u, f, r32, e0, e1;  // mixed precision
+  Field w;                  // FP64: the second iterate
   size_t bytes = 0;
 };
 
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Carve the five arrays of a request out of one allocation.  Rows are padded
-// to 128 bytes and element (1, j, k) of every row is 128-byte aligned.
-Layout make_layout(int nx, int ny, int nz, char* mem) {
+// Carve the arrays of a request out of one allocation (mixed: u, f, r32, e0,
+// e1; FP64: u, f, w).  Rows are padded to 128 bytes and element (1, j, k) of
+// every row is 128-byte aligned.
+Layout make_layout(int nx, int ny, int nz, char* mem, int precision) {
   Layout L;
   size_t off = 0;
   auto place = [&](Field& a, int dtype) {
@@ -68,9 +75,13 @@ Layout make_layout(int nx, int ny, int nz, char* mem) {
   };
   place(L.u, J3D_F64);
   place(L.f, J3D_F64);
-  place(L.r32, J3D_F32);
-  place(L.e0, J3D_F32);
-  place(L.e1, J3D_F32);
+  if (precision == J3D_SERVE_FP64) {
+    place(L.w, J3D_F64);
+  } else {
+    place(L.r32, J3D_F32);
+    place(L.e0, J3D_F32);
+    place(L.e1, J3D_F32);
+  }
   L.bytes = off;
   return L;
 }
@@ -92,6 +103,7 @@ struct Slot {
   Layout L;
   int64_t sweeps = 0;
   bool ready = false;  // set-up queued before the current cycle
+  int cur = 0;         // FP64 precision: the iterate is in u (0) or w (1)
 };
 
 }  // namespace
@@ -133,6 +145,8 @@ struct j3d_server {
   int* h_flags = nullptr;     // pinned: done[max_slots], nonfinite[max_slots]
   hipEvent_t ev = nullptr;
   TileCfg cd{}, cs{}, cs2{}, cs3{};  // defect, one-, two- and three-sweep FP32 passes
+  TileCfg cs_one64{}, c64_2{}, c64_3{};  // FP64 precision: one-, two- and three-sweep passes
+  int passes_in_cycle = 0;           // FP64 precision: passes the last cycle queued
 
   double now() const { return now_seconds() - t0; }
 };
@@ -163,6 +177,11 @@ enum Kind {
   K_NKINDS
 };
 
+// FP64 precision uses the same table storage: K_DEF is the residual check
+// of each slot's current iterate; pass tables of one, two or three sweeps
+// from the current iterate to the other (parity 0) or back (parity 1).
+constexpr int kP64[3][2] = {{K_FIRST1, K_FL1}, {K_FIRST2, K_FL2}, {K_FIRST3, K_FL3}};
+
 // Three-sweep correction passes when the FP32 state the cycle sweeps (r,
 // e0, e1 of every slot) exceeds 512 MB, twice the last-level cache, as in
 // the solver; J3D_SERVE_TRIPLES=0 or =1 forces two-sweep or three-sweep
@@ -172,6 +191,14 @@ bool serve_triples(long long points) {
   if (e != nullptr && *e == '0') return false;
   if (e != nullptr && *e == '1') return true;
   return 12.0 * (double)points > 512e6;
+}
+
+// The same rule for FP64 sweeps (24 bytes per point of u, w and f).
+bool serve_triples64(long long points) {
+  const char* e = std::getenv("J3D_SERVE_TRIPLES");
+  if (e != nullptr && *e == '0') return false;
+  if (e != nullptr && *e == '1') return true;
+  return 24.0 * (double)points > 512e6;
 }
 
 int serve_fail(j3d_server* s, int code, const char* what) {
@@ -210,6 +237,10 @@ int setup_device(j3d_server* s) {
   // the shape of a 512^3 grid (measured 2.7 % more solves/s than that of a
   // 256^3 grid)
   s->cs3 = default_cfg3(J3D_F32, 512, 512, 512);
+  s->cs_one64 = default_cfg(J3D_F64, 128, 128, 128);
+  s->cs_one64.persistent = 0;
+  s->c64_2 = default_cfg2(J3D_F64, 128, 128, 128);
+  s->c64_3 = default_cfg3(J3D_F64, 512, 512, 512);
   s->cd.persistent = 0;
   s->cs.persistent = 0;
   s->cs2.persistent = 0;
@@ -311,7 +342,7 @@ int admit(j3d_server* s) {
       return s->active.empty() ? rc : J3D_OK;
     }
     sl->mem = static_cast<char*>(mem);
-    sl->L = make_layout(q->r.nx, q->r.ny, q->r.nz, sl->mem);
+    sl->L = make_layout(q->r.nx, q->r.ny, q->r.nz, sl->mem, s->o.precision);
     q->t_admit = s->now();
     J3D_TRY(queue_setup(s, sl));
     s->active.push_back(sl);
@@ -414,10 +445,106 @@ int queue_cycle(j3d_server* s, const std::vector<Slot*>& slots) {
   return J3D_OK;
 }
 
+// FP64 precision: the residual check of every slot's current iterate, then
+// cycle_sweeps FP64 sweeps over the slots that still have sweeps left, in
+// passes of `step` sweeps (three when the FP64 state of the cycle exceeds
+// 512 MB, else two; the first pass takes cycle_sweeps mod step sweeps when
+// step does not divide it), alternating between u and w.
+int queue_cycle64(j3d_server* s, const std::vector<Slot*>& slots) {
+  const int n = (int)slots.size();
+  const int cyc = s->o.cycle_sweeps;
+  GridArgs* T[K_NKINDS];
+  for (int k = 0; k < K_NKINDS; ++k) T[k] = s->h_tab + (size_t)k * s->o.max_slots;
+  int nt_def = 0, nt[3] = {0, 0, 0}, n_in = 0;
+  long long pts_in = 0;
+  bool fit3 = true;
+  for (int g = 0; g < n; ++g) {
+    Slot* sl = slots[g];
+    const Layout& L = sl->L;
+    const double h = sl->req->r.h;
+    const Field* a = sl->cur ? &L.w : &L.u;  // the current iterate
+    const Field* b = sl->cur ? &L.u : &L.w;
+    GridArgs d = make_args(a, nullptr, &L.f, nullptr, nullptr, h, s->cd, nt_def);
+    d.id = sl->id;
+    T[K_DEF][g] = d;
+    nt_def += d.tiles_x * d.tiles_y * d.tiles_z;
+    s->h_rtol[sl->id] = sl->req->r.rtol;
+    if (sl->sweeps >= sl->req->max_sweeps) continue;  // final check only
+    for (int par = 0; par < 2; ++par) {
+      const Field* src = par ? b : a;
+      const Field* dst = par ? a : b;
+      GridArgs p1 = make_args(src, dst, &L.f, nullptr, nullptr, h, s->cs_one64, nt[0]);
+      GridArgs p2 = make_args2(src, dst, &L.f, nullptr, h, s->c64_2, nt[1]);
+      GridArgs p3 = make_args3(src, dst, &L.f, nullptr, h, s->c64_3, nt[2]);
+      p1.id = p2.id = p3.id = sl->id;
+      T[kP64[0][par]][n_in] = p1;
+      T[kP64[1][par]][n_in] = p2;
+      T[kP64[2][par]][n_in] = p3;
+    }
+    {
+      const GridArgs& p1 = T[kP64[0][0]][n_in];
+      const GridArgs& p2 = T[kP64[1][0]][n_in];
+      const GridArgs& p3 = T[kP64[2][0]][n_in];
+      nt[0] += p1.tiles_x * p1.tiles_y * p1.tiles_z;
+      nt[1] += p2.tiles_x * p2.tiles_y * p2.tiles_z;
+      nt[2] += p3.tiles_x * p3.tiles_y * p3.tiles_z;
+    }
+    pts_in += (long long)L.u.nx() * L.u.ny() * L.u.nz();
+    fit3 = fit3 && plane_fits_u32(L.u) && plane_fits_u32(L.w) && plane_fits_u32(L.f);
+    ++n_in;
+  }
+  if ((size_t)nt_def > s->part_cap) {
+    J3D_HIP(hipStreamSynchronize(s->st));
+    if (s->d_part) J3D_HIP(hipFree(s->d_part));
+    s->d_part = nullptr;
+    void* p = nullptr;
+    J3D_TRY(dev_alloc(&p, (size_t)nt_def * 2 * sizeof(double), "serve partials"));
+    s->d_part = (double*)p;
+    s->part_cap = (size_t)nt_def * 2;
+  }
+  const size_t row = (size_t)s->o.max_slots;
+  J3D_HIP(hipMemcpyAsync(s->d_tab, s->h_tab, (size_t)K_NKINDS * row * sizeof(GridArgs),
+                         hipMemcpyHostToDevice, s->st));
+  J3D_HIP(hipMemcpyAsync(s->d_rtol, s->h_rtol, row * sizeof(double), hipMemcpyHostToDevice, s->st));
+  GridArgs* D[K_NKINDS];
+  for (int k = 0; k < K_NKINDS; ++k) D[k] = s->d_tab + (size_t)k * row;
+  int* done = s->d_done;
+  J3D_HIP(launch_pass_batch(J3D_F64, F_RES, s->cd, D[K_DEF], n, nt_def, s->d_part, done, s->st));
+  J3D_HIP(launch_reduce_batch(s->d_part, D[K_DEF], n, s->d_resid, 1, 0, s->d_normf, s->d_rtol, 0, done,
+                              s->d_conv, s->d_nonfinite, s->st));
+  s->passes_in_cycle = 0;
+  if (n_in > 0) {
+    const int step = (fit3 && serve_triples64(pts_in)) ? 3 : 2;
+    auto pass = [&](int len, int par) -> hipError_t {
+      const GridArgs* t = D[kP64[len - 1][par]];
+      if (len == 3) return launch_sweep3_batch(J3D_F64, F_WRITE, s->c64_3, t, n_in, nt[2], nullptr, done, s->st);
+      if (len == 2) return launch_sweep2_batch(J3D_F64, F_WRITE, s->c64_2, t, n_in, nt[1], nullptr, done, s->st);
+      return launch_pass_batch(J3D_F64, F_WRITE, s->cs_one64, t, n_in, nt[0], nullptr, done, s->st);
+    };
+    int left = cyc, par = 0;
+    const int lead = cyc % step;
+    if (lead != 0) {
+      J3D_HIP(pass(lead, par));
+      left -= lead;
+      par ^= 1;
+      ++s->passes_in_cycle;
+    }
+    for (; left > 0; left -= step) {
+      J3D_HIP(pass(step, par));
+      par ^= 1;
+      ++s->passes_in_cycle;
+    }
+  }
+  J3D_HIP(hipMemcpyAsync(s->h_out, s->d_resid, row * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  J3D_HIP(hipMemcpyAsync(s->h_flags, s->d_done, 2 * row * sizeof(int), hipMemcpyDeviceToHost, s->st));
+  J3D_HIP(hipEventRecord(s->ev, s->st));
+  return J3D_OK;
+}
+
 int retire(j3d_server* s, Slot* sl, bool converged, bool nonfinite, double resid, double normf) {
   Request* q = sl->req;
   if (q->r.u_host != nullptr) {
-    const Field& u = sl->L.u;
+    const Field& u = sl->cur ? sl->L.w : sl->L.u;
     J3D_HIP(hipMemcpy2DAsync(q->r.u_host, (size_t)u.ex * 8, u.base, (size_t)u.sy * 8, (size_t)u.ex * 8,
                              (size_t)u.ey * u.ez, hipMemcpyDeviceToHost, s->st));
     J3D_HIP(hipStreamSynchronize(s->st));
@@ -459,7 +586,10 @@ int worker_loop(j3d_server* s) {
       continue;
     }
     std::vector<Slot*> cyc = s->active;  // slots in this cycle
-    J3D_TRY(queue_cycle(s, cyc));
+    if (s->o.precision == J3D_SERVE_FP64)
+      J3D_TRY(queue_cycle64(s, cyc));
+    else
+      J3D_TRY(queue_cycle(s, cyc));
     // Overlap: admit arrivals while the cycle runs; their set-up is queued
     // behind it and they join the next cycle.
     J3D_TRY(admit(s));
@@ -482,6 +612,7 @@ int worker_loop(j3d_server* s) {
         J3D_TRY(retire(s, sl, false, false, resid, normf_h[sl->id]));
       } else {
         sl->sweeps += s->o.cycle_sweeps;
+        if (s->passes_in_cycle & 1) sl->cur ^= 1;  // FP64: the sweeps ended in the other array
         keep.push_back(sl);
       }
     }
@@ -507,7 +638,13 @@ extern "C" {
 
 uint64_t j3d_request_bytes(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1) return 0;
-  return make_layout(nx, ny, nz, nullptr).bytes;
+  return make_layout(nx, ny, nz, nullptr, J3D_SERVE_MIXED).bytes;
+}
+
+uint64_t j3d_request_state_bytes(int32_t precision, int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return 0;
+  if (precision != J3D_SERVE_MIXED && precision != J3D_SERVE_FP64) return 0;
+  return make_layout(nx, ny, nz, nullptr, precision).bytes;
 }
 
 int poisson_serve_create(const j3d_serve_opts* opts, j3d_server** out) {
@@ -516,6 +653,9 @@ int poisson_serve_create(const j3d_serve_opts* opts, j3d_server** out) {
   if (opts->cycle_sweeps < 1) return fail(J3D_EINVAL, "cycle_sweeps must be >= 1");
   if (opts->queue_cap < 1) return fail(J3D_EINVAL, "queue_cap must be >= 1");
   if (opts->hbm_budget_bytes == 0) return fail(J3D_EINVAL, "hbm_budget_bytes must be > 0");
+  if (opts->precision != J3D_SERVE_MIXED && opts->precision != J3D_SERVE_FP64)
+    return fail(J3D_EINVAL, "precision must be J3D_SERVE_MIXED or J3D_SERVE_FP64");
+  if (opts->reserved != 0) return fail(J3D_EINVAL, "reserved field must be 0");
   int ndev = 0;
   J3D_HIP(hipGetDeviceCount(&ndev));
   if (opts->device < 0 || opts->device >= ndev) return fail(J3D_EINVAL, "no such device");
@@ -538,7 +678,7 @@ int poisson_serve_submit(j3d_server* s, const j3d_request* req, uint64_t* ticket
   const long long ex = req->nx + 2LL, ey = req->ny + 2LL, ez = req->nz + 2LL;
   if (ey > 65535 || ez > 65535 || ((ex + 31) / 32 * 32) * ey * ez >= (1LL << 31) - 64)
     return fail(J3D_EINVAL, "grid too large");
-  const size_t bytes = make_layout(req->nx, req->ny, req->nz, nullptr).bytes;
+  const size_t bytes = make_layout(req->nx, req->ny, req->nz, nullptr, s->o.precision).bytes;
   if (bytes > s->o.hbm_budget_bytes)
     return fail(J3D_EBUDGET, "request needs %zu bytes, budget is %llu", bytes,
                 (unsigned long long)s->o.hbm_budget_bytes);

@@ -34,6 +34,7 @@ HOST_RESULT = 1
 RESID_AFTER_1 = 2  # jacobi3d_sweep3: residual of the iterate after the pass's first sweep
 RESID_AFTER_2 = 4  # ... after its second sweep
 MODE_FP64, MODE_MIXED = 0, 1
+SERVE_MIXED, SERVE_FP64 = 0, 1  # server precision
 KIND_F64X2 = 2  # tuning kind of the two-sweep FP64 pass
 KIND_F32X2 = 3  # tuning kind of the two-sweep FP32 pass (also the mixed solve's correction sweeps)
 KIND_F64X3 = 4  # tuning kind of the three-sweep FP64 pass
@@ -84,7 +85,8 @@ class Tune(ctypes.Structure):
 class ServeOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("cycle_sweeps", ctypes.c_int32), ("device", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
-                ("max_active_points", ctypes.c_uint64)]
+                ("max_active_points", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -124,6 +126,7 @@ _SIGS = {
     "j3d_tune_set_single": ([_I32, _I32, _I32, _I32, _P(Tune)], ctypes.c_int),
     "j3d_tune_query_single": ([_I32, _I32, _I32, _I32, _P(Tune)], ctypes.c_int),
     "j3d_request_bytes": ([_I32, _I32, _I32], _U64),
+    "j3d_request_state_bytes": ([_I32, _I32, _I32, _I32], _U64),
     "poisson_serve_create": ([_P(ServeOpts), _P(_V)], ctypes.c_int),
     "poisson_serve_submit": ([_V, _P(Request), _P(_U64)], ctypes.c_int),
     "poisson_serve_poll": ([_V, _P(Result), _I32, _P(_I32)], ctypes.c_int),
@@ -575,13 +578,19 @@ def j3d_request_bytes(nx, ny, nz) -> int:
     return int(_lib.j3d_request_bytes(nx, ny, nz))
 
 
+def j3d_request_state_bytes(precision, nx, ny, nz) -> int:
+    return int(_lib.j3d_request_state_bytes(precision, nx, ny, nz))
+
+
 class Server:
     """poisson_serve_* over a server handle."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, cycle_sweeps: int = 50,
-                 device: int = 0, queue_cap: int = 100000, max_active_points: int = 0):
+                 device: int = 0, queue_cap: int = 100000, max_active_points: int = 0,
+                 precision: int = SERVE_MIXED):
         self._h = ctypes.c_void_p()
-        o = ServeOpts(int(hbm_budget_bytes), max_slots, cycle_sweeps, device, queue_cap, int(max_active_points))
+        o = ServeOpts(int(hbm_budget_bytes), max_slots, cycle_sweeps, device, queue_cap, int(max_active_points),
+                      int(precision), 0)
         _check(_lib.poisson_serve_create(ctypes.byref(o), ctypes.byref(self._h)), "poisson_serve_create")
         self._keep = {}
 

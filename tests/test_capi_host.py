@@ -105,7 +105,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert j3d.abi_version() == 1
+    assert j3d.abi_version() == 2
 
 
 def fake_desc(nx, ny, nz, dtype=j3d.F64, base=0x10000, lb=(0, 0, 0), ld=None, plane=None):
@@ -258,6 +258,12 @@ def test_tune_list_and_request_bytes():
     b = j3d.j3d_request_bytes(384, 384, 384)
     assert 28 * 386 ** 3 <= b <= 1.1 * 28 * 386 ** 3
     assert j3d.j3d_request_bytes(0, 4, 4) == 0
+    assert j3d.j3d_request_state_bytes(j3d.SERVE_MIXED, 384, 384, 384) == b
+    # FP64 serving: 24 bytes per padded point (u, f, w FP64) plus row padding
+    b64 = j3d.j3d_request_state_bytes(j3d.SERVE_FP64, 384, 384, 384)
+    assert 24 * 386 ** 3 <= b64 <= 1.1 * 24 * 386 ** 3
+    assert j3d.j3d_request_state_bytes(2, 8, 8, 8) == 0
+    assert j3d.j3d_request_state_bytes(j3d.SERVE_FP64, 8, 0, 8) == 0
 
 
 def test_sum_dot_validation_before_device_work():
@@ -388,16 +394,17 @@ def test_three_sweep_kind_defaults_and_validation():
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 97, 5, 3) == (4, 16, 6, 0, 0, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 97, 5, 3) == (4, 16, 6, 0, 0, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 256, 256, 256) == (4, 16, 20, 0, 2, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 384, 384, 384) == (4, 32, 20, 0, 2, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (4, 48, 20, 0, 1, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (4, 24, 20, 0, 2, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 384, 384, 384) == (8, 32, 6, 0, 2, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (8, 96, 6, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (8, 96, 6, 0, 1, 1)
     for bad in [(1, 16, 20, 0, 1, 1), (4, 16, 16, 0, 1, 1), (4, 16, 20, 1, 1, 1), (4, 16, 20, 0, 1, 2),
                 (16, 16, 20, 0, 1, 1), (3, 16, 20, 0, 1, 1), (5, 16, 20, 0, 1, 1), (6, 8, 6, 0, 1, 1),
                 (7, 16, 20, 0, 1, 1), (4, 16, 6, 0, 3, 1)]:
         with pytest.raises(j3d.J3DError) as ei:
             j3d.j3d_tune_set_single(j3d.KIND_F64X3, 64, 64, 64, bad)
         assert ei.value.code == j3d.EINVAL
-    for good in [(2, 16, 20, 0, 1, 1), (8, 8, 6, 0, 2, 1), (4, 48, 6, 0, 0, 1), (8, 24, 20, 0, 1, 1)]:
+    for good in [(2, 16, 20, 0, 1, 1), (8, 8, 6, 0, 2, 1), (4, 48, 6, 0, 0, 1), (8, 24, 20, 0, 1, 1),
+                 (16, 32, 6, 0, 1, 1)]:
         j3d.j3d_tune_set_single(j3d.KIND_F32X3, 64, 64, 64, good)
         assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 64, 64, 64) == good
     lib = j3d._lib
@@ -428,6 +435,8 @@ def test_three_sweep_kind_defaults_and_validation():
 
 
 
+@pytest.mark.skipif(__import__("torch").cuda.is_available(),
+                    reason="fake device addresses: only where no GPU could run a kernel on them")
 def test_noalloc_sweep3_validation():
     """jacobi3d_sweep3_noalloc rejects, before any device work: a null or host
     result, FP32 arrays, and a grid whose tiling needs more tile partials than
@@ -449,11 +458,31 @@ def test_noalloc_sweep3_validation():
                                        None) == j3d.EDTYPE
     assert lib.jacobi3d_sweep3_noalloc(ctypes.byref(a), ctypes.byref(a), ctypes.byref(c), 0.1, 0, dev,
                                        None) == j3d.EALIAS
-    # 59 x 2173 x 8641 points: with the default shape of such grids (58
-    # columns, 12 rows, 48 planes per tile) 2 x 182 x 181 = 65884 tiles
-    nx, ny, nz = 59, 2173, 8641
+    # 59 x 1021 x 2049 points with a pinned shape of 58 columns, 4 rows and
+    # 16 planes per tile: 2 x 256 x 129 = 66048 tiles
+    nx, ny, nz = 59, 1021, 2049
+    j3d.j3d_tune_set_single(j3d.KIND_F64X3, nx, ny, nz, (4, 16, 6, 0, 0, 1))
     span = (nx + 2) * (ny + 2) * (nz + 2) * 8
     base = 1 << 40
     big = [fake_desc(nx, ny, nz, base=base + q * (span + 4096)) for q in range(3)]
     assert lib.jacobi3d_sweep3_noalloc(*[ctypes.byref(x) for x in big], 1e-4, 0, dev, None) == j3d.EINVAL
-    assert "65884 tile partials" in j3d.last_error()
+    assert "66048 tile partials" in j3d.last_error()
+
+
+def test_serve_create_validation_before_device_work():
+    """poisson_serve_create checks its options (precision, reserved, counts)
+    before it looks for a device."""
+    lib = j3d._lib
+    h = ctypes.c_void_p()
+
+    def opts(**kw):
+        o = j3d.ServeOpts(1 << 30, 4, 50, 0, 16, 0, j3d.SERVE_MIXED, 0)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    for bad in (dict(precision=2), dict(precision=-1), dict(reserved=1), dict(max_slots=0), dict(cycle_sweeps=0),
+                dict(hbm_budget_bytes=0), dict(queue_cap=0)):
+        assert lib.poisson_serve_create(ctypes.byref(opts(**bad)), ctypes.byref(h)) == j3d.EINVAL, bad
+    assert "precision" in (lib.poisson_serve_create(ctypes.byref(opts(precision=7)), ctypes.byref(h)) and
+                           j3d.last_error())

@@ -124,3 +124,42 @@ def test_active_points_target_limits_concurrency():
         assert order[k]["t_admit"] >= earlier_done[k - 2] - 1e-3
     # FIFO: admitted in submission order
     assert [r["ticket"] for r in order] == sorted(r["ticket"] for r in order)
+
+
+@pytest.mark.parametrize("cycle", [1, 2, 3, 4, 5, 7, 50])
+@pytest.mark.parametrize("triples", ["0", "1"])
+def test_fp64_served_cycles_match_oracle(cycle, triples, monkeypatch):
+    """FP64 precision: every result equals the oracle's plain solve with a
+    check every cycle sweeps (cycle lengths with an odd and an even number of
+    passes, so the iterate ends cycles in either array), alone and in a mix."""
+    monkeypatch.setenv("J3D_SERVE_TRIPLES", triples)
+    reqs = [(10, 1e-8, 300, 71, True), (13, 1e-6, 300, 72, False), (7, 1e-3, 300, 73, False),
+            (17, 1e-12, 120, 74, True)]
+    say("serve fp64", cycle, triples)
+    with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=8, cycle_sweeps=cycle, precision=j3d.SERVE_FP64) as s:
+        got, got_u = run(s, reqs)
+    for k, (n, rtol, cap, seed, _) in enumerate(reqs):
+        f = rhs(n, seed)
+        cap_c = -(-cap // cycle) * cycle  # whole cycles
+        uo, ro = oracle.solve_plain(np.zeros((n + 2,) * 3), f, 1.0 / (n + 1), rtol=rtol, check_every=cycle,
+                                    max_sweeps=cap_c)
+        assert got[k]["converged"] == ro.converged and got[k]["sweeps"] == ro.sweeps, (k, got[k], ro.sweeps)
+        assert rel(got[k]["resid"], ro.resid) <= RESID_RTOL
+        assert rel(got[k]["norm_f"], ro.norm_f) <= RESID_RTOL
+        assert np.array_equal(got_u[k], uo)
+    # the first request alone gives the same bits
+    with j3d.Server(hbm_budget_bytes=1 << 30, max_slots=1, cycle_sweeps=cycle, precision=j3d.SERVE_FP64) as s:
+        solo, solo_u = run(s, [reqs[0]])
+    assert np.array_equal(solo_u[0], got_u[0])
+    assert (solo[0]["sweeps"], solo[0]["resid"]) == (got[0]["sweeps"], got[0]["resid"])
+
+
+def test_fp64_serving_budget_uses_fp64_state():
+    per = j3d.j3d_request_state_bytes(j3d.SERVE_FP64, 20, 20, 20)
+    assert per < j3d.j3d_request_bytes(20, 20, 20)
+    with j3d.Server(hbm_budget_bytes=per + 10, max_slots=4, cycle_sweeps=10, precision=j3d.SERVE_FP64) as s:
+        res, _ = run(s, [(20, 1e-12, 20, 80 + k, False) for k in range(3)])
+    order = sorted(res.values(), key=lambda r: r["t_admit"])
+    # one at a time
+    for k in range(1, 3):
+        assert order[k]["t_admit"] >= order[k - 1]["t_done"] - 1e-3
