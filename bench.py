@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--active-points", type=float, default=2e8,
                     help="serve: admission target for active interior points (0: no limit)")
     ap.add_argument("--rtol", type=float, default=1e-8, help="mixed: target relative residual")
+    ap.add_argument("--max-sweeps", type=int, default=0,
+                    help="mixed: stop each solve after this many sweeps (0: run to the tolerance; for profiling)")
     ap.add_argument("--chunk-sweeps", type=int, default=100000,
                     help="mixed: sweeps per solve call between progress lines (whole 50-sweep cycles)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: request arrival rate per second")
@@ -393,11 +395,12 @@ def run_mixed(args):
         # operations as one call), so progress can be reported between chunks.
         t0 = time.perf_counter()
         sweeps = 0
+        cap = args.max_sweeps if args.max_sweeps > 0 else 10 ** 8
         while True:
-            r = j3d.poisson_solve(u, df, h, mode=mode, rtol=args.rtol, max_sweeps=chunk,
+            r = j3d.poisson_solve(u, df, h, mode=mode, rtol=args.rtol, max_sweeps=min(chunk, cap - sweeps),
                                   check_every=50, inner_sweeps=50, history_cap=0)
             sweeps += r.sweeps
-            if r.converged or r.sweeps < chunk or sweeps >= 10 ** 8:
+            if r.converged or r.sweeps < chunk or sweeps >= cap:
                 break
             print("[bench] %s: %d sweeps, relative residual %.3e, %.1f s" % (
                 name, sweeps, r.resid / r.norm_f, time.perf_counter() - t0), file=sys.stderr, flush=True)

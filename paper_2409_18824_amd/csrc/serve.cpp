@@ -28,6 +28,7 @@
 #include <atomic>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -212,6 +213,17 @@ int serve_fail(j3d_server* s, int code, const char* what) {
   return code;
 }
 
+// A three-sweep tile shape from the environment ("rows,planes,variant,
+// persistent,order,cols"), if set and supported.
+void tile3_from_env(const char* name, int dtype, TileCfg* c) {
+  const char* e = std::getenv(name);
+  if (e == nullptr) return;
+  TileCfg t{};
+  if (std::sscanf(e, "%d,%d,%d,%d,%d,%d", &t.rows, &t.planes, &t.variant, &t.persistent, &t.order, &t.cols) == 6 &&
+      tile3_cfg_supported(dtype, t))
+    *c = t;
+}
+
 int setup_device(j3d_server* s) {
   const int n = s->o.max_slots;
   J3D_HIP(hipSetDevice(s->o.device));
@@ -233,14 +245,16 @@ int setup_device(j3d_server* s) {
   s->cd = default_cfg(J3D_F64, 128, 128, 128);
   s->cs = default_cfg(J3D_F32, 128, 128, 128);
   s->cs2 = default_cfg2(J3D_F32, 128, 128, 128);
-  // the batched FP32 three-sweep pass runs over up to 2e8 active points:
-  // the shape of a 512^3 grid (measured 2.7 % more solves/s than that of a
-  // 256^3 grid)
-  s->cs3 = default_cfg3(J3D_F32, 512, 512, 512);
+  // the batched three-sweep passes run over up to 2e8 active points of
+  // grids of 32^3 to 384^3; shapes measured on the served stream (see
+  // below), J3D_SERVE_TILE3 / J3D_SERVE_TILE3_FP64 override them
+  s->cs3 = TileCfg{4, 24, 20, 0, 2, 1};
+  tile3_from_env("J3D_SERVE_TILE3", J3D_F32, &s->cs3);
   s->cs_one64 = default_cfg(J3D_F64, 128, 128, 128);
   s->cs_one64.persistent = 0;
   s->c64_2 = default_cfg2(J3D_F64, 128, 128, 128);
-  s->c64_3 = default_cfg3(J3D_F64, 512, 512, 512);
+  s->c64_3 = TileCfg{4, 48, 20, 0, 1, 1};
+  tile3_from_env("J3D_SERVE_TILE3_FP64", J3D_F64, &s->c64_3);
   s->cd.persistent = 0;
   s->cs.persistent = 0;
   s->cs2.persistent = 0;

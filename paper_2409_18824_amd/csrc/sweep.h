@@ -148,6 +148,18 @@ __device__ __forceinline__ float div6(float x) {
   return q;
 }
 
+// div6 in two parts, for code that tests a whole row block at once: the
+// fused quotient, and whether x lies below the range where it is exact
+// (then the quotient must come from the division instead).
+__device__ __forceinline__ double div6_fused(double x) {
+  return __builtin_fma(x, 0x1.5555555555555p-3, x * 0x1.5555555555555p-57);
+}
+__device__ __forceinline__ float div6_fused(float x) {
+  return __builtin_fmaf(x, 0x1.555556p-3f, x * -0x1.555556p-28f);
+}
+__device__ __forceinline__ bool div6_small(double x) { return __builtin_fabs(x) < 0x1p-1000; }
+__device__ __forceinline__ bool div6_small(float x) { return __builtin_fabsf(x) < 0x1p-100f; }
+
 // Rows per thread encoded in the variant bits 2 and 16.
 constexpr int rows_per_thread(int var) { return 1 << (((var >> 1) & 1) + 2 * ((var >> 4) & 1)); }
 

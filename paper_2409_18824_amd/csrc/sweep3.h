@@ -167,8 +167,11 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   const bool wlo = wy == 0, whi = wy == BY - 1;
   const int wdn = wlo ? 0 : wy - 1, wup = whi ? BY - 1 : wy + 1;  // neighbouring wavefronts
 
-  auto u_plane = [&](int kk) { return plane_rsrc(u0b + (long long)g.su_z * kk * ES); };
-  auto f_plane = [&](int kk) { return plane_rsrc(fb + (long long)g.sf_z * kk * ES); };
+  // plane kk >= 0 of u, f, the output
+  const uint64_t zu = (uint64_t)g.su_z * ES, zf = (uint64_t)g.sf_z * ES;
+  const uint64_t zo = (FL & F_LAST) ? (uint64_t)g.s64_z * 8 : (uint64_t)g.so_z * ES;
+  auto u_plane = [&](int kk) { return plane_rsrc(u0b + (uint64_t)(uint32_t)kk * zu); };
+  auto f_plane = [&](int kk) { return plane_rsrc(fb + (uint64_t)(uint32_t)kk * zf); };
 
   double acc = 0.0;
   // Three buffers per plane array, whose roles rotate with k (below,
@@ -191,8 +194,7 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     pq[r] = 0.0;
   }
   auto out_plane = [&](int kk) {
-    return (FL & F_LAST) ? plane_rsrc(u64b + (long long)g.s64_z * kk * 8)
-                         : plane_rsrc(ob + (long long)g.so_z * kk * ES);
+    return plane_rsrc(((FL & F_LAST) ? u64b : ob) + (uint64_t)(uint32_t)kk * zo);
   };
   // store u3 of plane kk (held in st)
   auto flush = [&](int kk) {
@@ -268,7 +270,10 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     }
     const bool kin1 = k >= 1 && k <= g.nz;
     const bool kout1 = k >= k0 && k < k1;
-    // stage 1: u1 at plane k on every row of the block
+    // stage 1: u1 at plane k on every row of the block (the quotients by 6
+    // in their fused form, then the rare exact divisions, see div6)
+    T x1[RY];
+    bool small1 = false;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const T nym = r == 0 ? nylo : u0c[r - 1];
@@ -279,7 +284,9 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
       s = s + nyp;
       s = s + u0m[r];
       s = s + u0p[r];
-      u1[r] = pt_in ? div6(s + h2 * fk[r]) : u0c[r];
+      x1[r] = s + h2 * fk[r];
+      u1[r] = pt_in ? div6_fused(x1[r]) : u0c[r];
+      small1 = small1 || (pt_in && div6_small(x1[r]));
       if (FL & F_RES) {
         if (inner3[r] && pt_in && kout1) {
           const double res = static_cast<double>(fk[r]) -
@@ -287,6 +294,11 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
           acc += res * res;
         }
       }
+    }
+    if (__builtin_amdgcn_ballot_w64(small1) != 0) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+        if (col_in[r] && kin1 && div6_small(x1[r])) u1[r] = x1[r] / T(6);
     }
     // slot of plane k (k starts at k0 - 2 >= -1: keep the index non-negative)
     sm.e1[(k + 3) % 3][wy][0][lane] = u1[0];
@@ -299,6 +311,8 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
       const T above = whi ? T(0) : sm.e1[sl][wup][0][lane];
       const bool kin2 = k - 1 >= 1 && k - 1 <= g.nz;
       const bool kout2 = k - 1 >= k0 && k - 1 < k1;
+      T x2[RY];
+      bool small2 = false;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const T xm = shift_in_left(u1m1[r]), xp = shift_in_right(u1m1[r]);
@@ -310,7 +324,9 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
         s = s + u1m2[r];
         s = s + u1[r];
         const bool pt_in = col_in[r] && kin2;
-        u2[r] = (pt_in && inner2[r]) ? div6(s + h2 * fm1[r]) : u1m1[r];
+        x2[r] = s + h2 * fm1[r];
+        u2[r] = (pt_in && inner2[r]) ? div6_fused(x2[r]) : u1m1[r];
+        small2 = small2 || (pt_in && inner2[r] && div6_small(x2[r]));
         if (FL & F_RES1) {
           if (inner3[r] && pt_in && kout2) {
             const double res = static_cast<double>(fm1[r]) -
@@ -318,6 +334,11 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
             acc += res * res;
           }
         }
+      }
+      if (__builtin_amdgcn_ballot_w64(small2) != 0) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+          if (col_in[r] && kin2 && inner2[r] && div6_small(x2[r])) u2[r] = x2[r] / T(6);
       }
     }
     // stage 3: u3 at plane k-2 (from u2 at k-3, k-2, k-1); the u2 edge rows
