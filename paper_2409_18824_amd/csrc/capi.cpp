@@ -36,10 +36,11 @@ const std::vector<TileCfg>& tune_table() {
 TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   TileCfg c;
   if (tune_cache_lookup_single(dtype, nx, ny, nz, &c)) return c;
-  // FP64 grids of at most 64^3 points: one plane per tile, XCD-blocked
-  // (8.1 against 8.9 us per sweep at 64^3 with a residual after every sweep)
+  // FP64 grids of at most 64^3 points: four wavefronts, one plane per
+  // tile, XCD-blocked (7.6 against 7.9 us per sweep with one wavefront and
+  // 8.9 with the large-grid shape, at 64^3 with a residual after every sweep)
   const bool small = dtype == J3D_F64 && (long long)nx * ny * nz <= 64LL * 64 * 64;
-  c.rows = 1;
+  c.rows = small ? 4 : 1;
   c.planes = small ? 1 : 2;
   c.variant = 20;  // four rows per thread, nontemporal stores
   c.persistent = 0;

@@ -284,7 +284,7 @@ def test_sum_dot_validation_before_device_work():
 
 def test_tune_query_default_set_and_bad_kind():
     # defaults (no cache entry for this odd shape)
-    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (1, 1, 20, 0, 0, 1)  # at most 64^3 points
+    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (4, 1, 20, 0, 0, 1)  # at most 64^3 points
     assert j3d.j3d_tune_query_single(j3d.F64, 65, 64, 64) == (1, 2, 20, 0, 1, 1)
     assert j3d.j3d_tune_query_single(j3d.F32, 97, 5, 3) == (1, 2, 20, 0, 1, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X2, 97, 5, 3) == (4, 16, 20, 0, 1, 1)
@@ -292,7 +292,7 @@ def test_tune_query_default_set_and_bad_kind():
     # a pinned shape is what later calls of that kind and shape use
     j3d.j3d_tune_set_single(j3d.F32, 97, 5, 3, (2, 8, 6, 1, 2, 1))
     assert j3d.j3d_tune_query_single(j3d.F32, 97, 5, 3) == (2, 8, 6, 1, 2, 1)
-    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (1, 1, 20, 0, 0, 1)
+    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (4, 1, 20, 0, 0, 1)
     with pytest.raises(j3d.J3DError) as ei:
         j3d.j3d_tune_query_single(7, 97, 5, 3)
     assert ei.value.code == j3d.EDTYPE
