@@ -35,11 +35,15 @@ namespace sweep_detail {
 // Output columns per tile in x.
 constexpr int kSweep3Cols = WAVE - 6;
 
+// Edge rows exchanged between the wavefronts of a block, in three slots per
+// array: the slot of a plane is the phase (position in the z loop unrolled
+// by three) of the step that writes it, so every slot index is a
+// compile-time constant of the unrolled code.
 template <typename T, int BY>
 struct Smem3 {
-  T e0[2][BY][2][WAVE];  // u0: plane parity, wavefront, first/last row
-  T e1[3][BY][2][WAVE];  // u1: plane slot
-  T e2[2][BY][2][WAVE];  // u2: plane parity
+  T e0[3][BY][2][WAVE];  // u0: slot, wavefront, first/last row
+  T e1[3][BY][2][WAVE];  // u1
+  T e2[3][BY][2][WAVE];  // u2
   double red[BY];
 };
 
@@ -236,16 +240,21 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   }
   issue(k0 - 2);
   if (!ZERO) {
-    sm.e0[(k0 - 2) & 1][wy][0][lane] = u0B[0];
-    sm.e0[(k0 - 2) & 1][wy][1][lane] = u0B[RY - 1];
+    // plane k0-2 is read by the first step (phase 0)
+    sm.e0[0][wy][0][lane] = u0B[0];
+    sm.e0[0][wy][1][lane] = u0B[RY - 1];
   }
   __syncthreads();
 
   // One plane step: u0m/u0c/u0p are u0 at planes k-1, k, k+1, fm2/fm1/fk
   // are f at k-2, k-1, k, u1m2/u1m1/u1 u1 at k-2, k-1, k (u1 computed here)
   // and u2m2/u2m1/u2 u2 at k-3, k-2, k-1 (u2 computed here).
-  auto step = [&](int k, T(&u0m)[RY], T(&u0c)[RY], T(&u0p)[RY], T(&fm2)[RY], T(&fm1)[RY], T(&fk)[RY],
+  // ph: the step's phase p in the unrolled loop (std::integral_constant).
+  // Slots: e0 of plane k is p (written by step k-1 as its p+1), e1 of plane k
+  // p, of k-1 p+2; e2 of plane k-1 (formed here) p, of k-2 p+2 (mod 3).
+  auto step = [&](auto ph, int k, T(&u0m)[RY], T(&u0c)[RY], T(&u0p)[RY], T(&fm2)[RY], T(&fm1)[RY], T(&fk)[RY],
                   T(&u1m2)[RY], T(&u1m1)[RY], T(&u1)[RY], T(&u2m2)[RY], T(&u2m1)[RY], T(&u2)[RY]) {
+    constexpr int P = decltype(ph)::value, P1 = (P + 1) % 3, P2 = (P + 2) % 3;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       u0p[r] = pu[r];
@@ -262,18 +271,18 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     }
     T nylo = T(0), nyhi = T(0);
     if (!ZERO) {
-      nylo = wlo ? elo : sm.e0[k & 1][wdn][1][lane];
-      nyhi = whi ? ehi : sm.e0[k & 1][wup][0][lane];
+      nylo = wlo ? elo : sm.e0[P][wdn][1][lane];
+      nyhi = whi ? ehi : sm.e0[P][wup][0][lane];
       // plane k+1 for the next step (read after this step's barrier)
-      sm.e0[(k + 1) & 1][wy][0][lane] = u0p[0];
-      sm.e0[(k + 1) & 1][wy][1][lane] = u0p[RY - 1];
+      sm.e0[P1][wy][0][lane] = u0p[0];
+      sm.e0[P1][wy][1][lane] = u0p[RY - 1];
     }
     const bool kin1 = k >= 1 && k <= g.nz;
     const bool kout1 = k >= k0 && k < k1;
     // stage 1: u1 at plane k on every row of the block (the quotients by 6
     // in their fused form, then the rare exact divisions, see div6)
     T x1[RY];
-    bool small1 = false;
+    uint64_t small1 = 0;  // lanes whose quotient needs the division
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const T nym = r == 0 ? nylo : u0c[r - 1];
@@ -286,7 +295,7 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
       s = s + u0p[r];
       x1[r] = s + h2 * fk[r];
       u1[r] = pt_in ? div6_fused(x1[r]) : u0c[r];
-      small1 = small1 || (pt_in && div6_small(x1[r]));
+      small1 |= __builtin_amdgcn_ballot_w64(pt_in && div6_small(x1[r]));
       if (FL & F_RES) {
         if (inner3[r] && pt_in && kout1) {
           const double res = static_cast<double>(fk[r]) -
@@ -295,24 +304,22 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
         }
       }
     }
-    if (__builtin_amdgcn_ballot_w64(small1) != 0) {
+    if (small1 != 0) {
 #pragma unroll
       for (int r = 0; r < RY; ++r)
         if (col_in[r] && kin1 && div6_small(x1[r])) u1[r] = x1[r] / T(6);
     }
-    // slot of plane k (k starts at k0 - 2 >= -1: keep the index non-negative)
-    sm.e1[(k + 3) % 3][wy][0][lane] = u1[0];
-    sm.e1[(k + 3) % 3][wy][1][lane] = u1[RY - 1];
+    sm.e1[P][wy][0][lane] = u1[0];
+    sm.e1[P][wy][1][lane] = u1[RY - 1];
     __syncthreads();
     // stage 2: u2 at plane k-1 (from u1 at k-2, k-1, k)
     {
-      const int sl = (k + 2) % 3;  // slot of plane k-1
-      const T below = wlo ? T(0) : sm.e1[sl][wdn][1][lane];
-      const T above = whi ? T(0) : sm.e1[sl][wup][0][lane];
+      const T below = wlo ? T(0) : sm.e1[P2][wdn][1][lane];
+      const T above = whi ? T(0) : sm.e1[P2][wup][0][lane];
       const bool kin2 = k - 1 >= 1 && k - 1 <= g.nz;
       const bool kout2 = k - 1 >= k0 && k - 1 < k1;
       T x2[RY];
-      bool small2 = false;
+      uint64_t small2 = 0;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const T xm = shift_in_left(u1m1[r]), xp = shift_in_right(u1m1[r]);
@@ -326,7 +333,7 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
         const bool pt_in = col_in[r] && kin2;
         x2[r] = s + h2 * fm1[r];
         u2[r] = (pt_in && inner2[r]) ? div6_fused(x2[r]) : u1m1[r];
-        small2 = small2 || (pt_in && inner2[r] && div6_small(x2[r]));
+        small2 |= __builtin_amdgcn_ballot_w64(pt_in && inner2[r] && div6_small(x2[r]));
         if (FL & F_RES1) {
           if (inner3[r] && pt_in && kout2) {
             const double res = static_cast<double>(fm1[r]) -
@@ -335,7 +342,7 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
           }
         }
       }
-      if (__builtin_amdgcn_ballot_w64(small2) != 0) {
+      if (small2 != 0) {
 #pragma unroll
         for (int r = 0; r < RY; ++r)
           if (col_in[r] && kin2 && inner2[r] && div6_small(x2[r])) u2[r] = x2[r] / T(6);
@@ -344,9 +351,8 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
     // stage 3: u3 at plane k-2 (from u2 at k-3, k-2, k-1); the u2 edge rows
     // of plane k-2 were written in the previous step
     if (k - 2 >= k0) {
-      const int sl = (k - 2) & 1;
-      const T below = wlo ? T(0) : sm.e2[sl][wdn][1][lane];
-      const T above = whi ? T(0) : sm.e2[sl][wup][0][lane];
+      const T below = wlo ? T(0) : sm.e2[P2][wdn][1][lane];
+      const T above = whi ? T(0) : sm.e2[P2][wup][0][lane];
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const T xm = shift_in_left(u2m1[r]), xp = shift_in_right(u2m1[r]);
@@ -369,17 +375,17 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
         }
       }
     }
-    sm.e2[(k - 1) & 1][wy][0][lane] = u2[0];
-    sm.e2[(k - 1) & 1][wy][1][lane] = u2[RY - 1];
+    sm.e2[P][wy][0][lane] = u2[0];
+    sm.e2[P][wy][1][lane] = u2[RY - 1];
   };
   // k runs from k0 - 2 to k1 + 1; the bounds are the same for the whole
   // workgroup, so every wavefront takes the same steps and barriers.
   for (int k = k0 - 2; k <= k1 + 1; k += 3) {
-    step(k, u0A, u0B, u0C, fA, fB, fC, u1A, u1B, u1C, u2A, u2B, u2C);
+    step(std::integral_constant<int, 0>(), k, u0A, u0B, u0C, fA, fB, fC, u1A, u1B, u1C, u2A, u2B, u2C);
     if (k + 1 > k1 + 1) break;
-    step(k + 1, u0B, u0C, u0A, fB, fC, fA, u1B, u1C, u1A, u2B, u2C, u2A);
+    step(std::integral_constant<int, 1>(), k + 1, u0B, u0C, u0A, fB, fC, fA, u1B, u1C, u1A, u2B, u2C, u2A);
     if (k + 2 > k1 + 1) break;
-    step(k + 2, u0C, u0A, u0B, fC, fA, fB, u1C, u1A, u1B, u2C, u2A, u2B);
+    step(std::integral_constant<int, 2>(), k + 2, u0C, u0A, u0B, fC, fA, fB, u1C, u1A, u1B, u2C, u2A, u2B);
   }
   flush(k1 - 1);  // the last step computed u3 of plane k1 - 1
 
