@@ -61,14 +61,17 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP_F64 = 24.0
 
 
-KERNEL_SOURCES = ("sweep.h", "sweep2.h", "sweep3.h", "kernels.hip", "kernels_f64.hip", "kernels_f32.hip",
-                  "kernels_sweep2.hip", "kernels_sweep3.hip", "j3d_internal.h")
+# device sources of the FP64 pass of each length
+KERNEL_SOURCES = {1: ("sweep.h", "kernels_f64.hip", "j3d_internal.h"),
+                  2: ("sweep.h", "sweep2.h", "kernels_sweep2.hip", "j3d_internal.h"),
+                  3: ("sweep.h", "sweep3.h", "kernels_sweep3.hip", "j3d_internal.h")}
 
 
-def kernel_source_hash() -> str:
-    """Hash of the device sources; counter summaries name the hash they were taken on."""
+def kernel_source_hash(passes: int = 3) -> str:
+    """Hash of the device sources of the pass of that length; counter
+    summaries name the hash they were taken on."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[passes]:
         with open(os.path.join(ROOT, "paper_2409_18824_amd", "csrc", name), "rb") as fp:
             h.update(fp.read())
     return h.hexdigest()[:16]
@@ -314,7 +317,7 @@ def main():
     med_ms = float(np.median(kernel_ms))
     bytes_launch = BYTES_PER_LUP_F64 * n ** 3  # read u, read f, write the result
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    khash = kernel_source_hash()
+    khash = kernel_source_hash(P)
     kname = {1: "k_pass_one<double, F_WRITE> (FP64 sweep)",
              2: "k_sweep2_one<F_WRITE> (two FP64 sweeps per pass)",
              3: "k_sweep3_one<F_WRITE> (three FP64 sweeps per pass)"}[P]
@@ -333,7 +336,12 @@ def main():
         copy_gbps = j3d.j3d_bandwidth_probe(src, dst, reps=5)
         roof["copy_ceiling_gbps"] = round(copy_gbps, 1)
         roof["frac_of_copy_ceiling"] = round(achieved / copy_gbps, 4)
-        del src, dst
+        # the pass's own mix (two streams read, one written: dst = a + b)
+        src2 = torch.ones(nprobe, dtype=torch.float64, device="cuda")
+        triad_gbps = j3d.j3d_bandwidth_probe_triad(src, src2, dst, reps=5)
+        roof["triad_ceiling_gbps"] = round(triad_gbps, 1)
+        roof["frac_of_triad_ceiling"] = round(achieved / triad_gbps, 4)
+        del src, src2, dst
 
     cpu = None
     if not args.no_cpu_baseline:

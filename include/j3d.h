@@ -566,6 +566,17 @@ int j3d_fill_const(j3d_array* a, double value, void* stream);
 int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps,
                         double* gbps, void* stream);
 
+/*
+ * The same for the traffic mix of the sweep passes (two streams read, one
+ * written, in equal lengths): dst[i] = a[i] + b[i] over n doubles (device),
+ * `reps` times with each of three kernels (one or four 16-byte elements per
+ * thread, nontemporal or plain stores); returns the best rate in GB/s
+ * (bytes read + written per second).  dst may not overlap a or b; a and b
+ * may coincide.  Buffers 16-byte aligned, n >= 2.  Blocks.
+ */
+int j3d_bandwidth_probe_triad(const double* a, const double* b, double* dst, int64_t n,
+                              int32_t reps, double* gbps, void* stream);
+
 /* Free every cached scratch buffer and graph of the calling process. */
 int j3d_release_cache(void);
 

@@ -36,15 +36,19 @@ const std::vector<TileCfg>& tune_table() {
 TileCfg default_cfg(int dtype, int nx, int ny, int nz) {
   TileCfg c;
   if (tune_cache_lookup_single(dtype, nx, ny, nz, &c)) return c;
-  // FP64 grids of at most 64^3 points: four wavefronts, one plane per
-  // tile, XCD-blocked (7.6 against 7.9 us per sweep with one wavefront and
-  // 8.9 with the large-grid shape, at 64^3 with a residual after every sweep)
+  // FP64 grids of at most 64^3 points: four wavefronts of two rows per
+  // thread, two planes per tile, XCD-blocked (7.45 us per sweep at 64^3 with
+  // a residual after every sweep, against 7.8 with four rows per thread and
+  // one plane, 16.0 with the large-grid shape).  Otherwise one wavefront of
+  // four rows per thread, 16 planes per tile (the loads run one plane
+  // ahead, so deep tiles cost no latency), per-slab XCD chunks: 572 us per
+  // FP64 pass at 512^3 against 643 with 2 planes, 70.7 us at 256^3.
   const bool small = dtype == J3D_F64 && (long long)nx * ny * nz <= 64LL * 64 * 64;
   c.rows = small ? 4 : 1;
-  c.planes = small ? 1 : 2;
-  c.variant = 20;  // four rows per thread, nontemporal stores
+  c.planes = small ? 2 : 16;
+  c.variant = small ? 6 : 20;  // two or four rows per thread, nontemporal stores
   c.persistent = 0;
-  c.order = small ? 0 : 1;
+  c.order = small ? 0 : 2;
   c.cols = 1;
   return c;
 }
@@ -60,8 +64,9 @@ TileCfg default_cfg3(int dtype, int nx, int ny, int nz) {
   // wavefronts of 2 rows per thread (about 95 registers per thread against
   // 160 with 4 rows, so twice the wavefronts per CU), 32 planes in
   // per-slab XCD chunks, and above 400^3 96 planes in launch order (512^3:
-  // 722 us per FP64 pass against 776 with 4 x 4 rows and 48 planes; FP32
-  // 445 against 452 us).
+  // 722 us per FP64 pass against 776 with 4 x 4 rows and 48 planes).  FP32
+  // above 400^3: 4 wavefronts of 4 rows per thread, 24 planes, per-slab XCD
+  // chunks (442 us per pass at 512^3 against 450 with the FP64 shape).
   const long long pts = (long long)nx * ny * nz;
   const bool small = pts <= 200LL * 200 * 200;
   const bool large = pts > 300LL * 300 * 300;
@@ -72,6 +77,12 @@ TileCfg default_cfg3(int dtype, int nx, int ny, int nz) {
   c.persistent = 0;
   c.order = small ? 0 : huge ? 1 : 2;
   c.cols = 1;
+  if (dtype == J3D_F32 && huge) {
+    c.rows = 4;
+    c.planes = 24;
+    c.variant = 20;
+    c.order = 2;
+  }
   return c;
 }
 
@@ -366,6 +377,38 @@ int j3d_bandwidth_probe(const double* src, double* dst, int64_t n, int32_t reps,
       float ms = 0.f;
       J3D_HIP(hipEventElapsedTime(&ms, e0, e1));
       const double rate = 2.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
+      if (rate > best) best = rate;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *gbps = best;
+  return J3D_OK;
+}
+
+int j3d_bandwidth_probe_triad(const double* a, const double* b, double* dst, int64_t n, int32_t reps,
+                              double* gbps, void* stream) {
+  if (a == nullptr || b == nullptr || dst == nullptr || gbps == nullptr || n < 2 || reps < 1)
+    return fail(J3D_EINVAL, "triad probe: bad arguments");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(J3D_EINVAL, "triad probe: buffers must be 16-byte aligned");
+  auto overlap = [n](const double* x, const double* y) { return x < y + n && y < x + n; };
+  if (overlap(a, dst) || overlap(b, dst)) return fail(J3D_EALIAS, "triad probe: dst overlaps a source");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  J3D_HIP(hipEventCreate(&e0));
+  J3D_HIP(hipEventCreate(&e1));
+  double best = 0.0;
+  for (int v = 0; v < kTriadVariants; ++v) {
+    J3D_HIP(launch_triad_variant(v, a, b, dst, n, st));  // warm-up
+    for (int r = 0; r < reps; ++r) {
+      J3D_HIP(hipEventRecord(e0, st));
+      J3D_HIP(launch_triad_variant(v, a, b, dst, n, st));
+      J3D_HIP(hipEventRecord(e1, st));
+      J3D_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      J3D_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double rate = 3.0 * 8.0 * (double)n / (ms * 1e-3) / 1e9;
       if (rate > best) best = rate;
     }
   }

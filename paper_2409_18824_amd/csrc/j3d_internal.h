@@ -31,6 +31,8 @@ struct GridArgs {
   float h2f;        // (float)(h*h)
   int order;        // tile order: 0 XCD-blocked, 1 as launched, 2 chunked per XCD
   int chunk;        // order 2: tiles per XCD chunk
+  int wide_planes;  // some plane of an array spans 2^31 bytes or more: the one-sweep
+                    // pass takes its pointer-addressed path
 };
 
 // Kernel pass flags (compile-time).
@@ -167,6 +169,12 @@ hipError_t launch_copy(const double* src, double* dst, long long n, hipStream_t 
 // nontemporal.
 constexpr int kCopyVariants = 5;
 hipError_t launch_copy_variant(int v, const double* src, double* dst, long long n, hipStream_t st);
+// Kernels of the two-reads-one-write probe (dst = a + b): 0 one 16-byte
+// element per thread with nontemporal stores, 1 the same with plain
+// stores, 2 four per thread with nontemporal stores.
+constexpr int kTriadVariants = 3;
+hipError_t launch_triad_variant(int v, const double* a, const double* b, double* dst, long long n,
+                                hipStream_t st);
 hipError_t launch_copy_interior(const double* src, double* dst, int nx, int ny, int nz,
                                 long long ssy, long long ssz, long long dsy, long long dsz,
                                 hipStream_t st);

@@ -247,6 +247,39 @@ __global__ void k_copy_tail(const double* __restrict__ src, double* __restrict__
   if (threadIdx.x == 0 && (n & 1)) dst[n - 1] = src[n - 1];
 }
 
+// Two streams read, one written (dst = a + b), the traffic mix of the sweep
+// passes: U 16-byte elements per thread, plain or nontemporal stores.
+template <int U, bool NT>
+__global__ void __launch_bounds__(256) k_triad_u(const copy_vd2* __restrict__ a, const copy_vd2* __restrict__ b,
+                                                 copy_vd2* __restrict__ dst, long long n2) {
+  const long long base = (long long)blockIdx.x * 256 * U + threadIdx.x;
+  copy_vd2 v[U], w[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long q = base + 256LL * u;
+    if (q < n2) {
+      v[u] = a[q];
+      w[u] = b[q];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long q = base + 256LL * u;
+    if (q < n2) {
+      const copy_vd2 s = v[u] + w[u];
+      if (NT)
+        __builtin_nontemporal_store(s, dst + q);
+      else
+        dst[q] = s;
+    }
+  }
+}
+
+__global__ void k_triad_tail(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ dst,
+                             long long n) {
+  if (threadIdx.x == 0 && (n & 1)) dst[n - 1] = a[n - 1] + b[n - 1];
+}
+
 __global__ void __launch_bounds__(256)
     k_copy_interior(const double* __restrict__ src, double* __restrict__ dst, int nx, long long ssy,
                     long long ssz, long long dsy, long long dsz) {
@@ -474,6 +507,25 @@ hipError_t launch_copy_variant(int v, const double* src, double* dst, long long 
   if (u == 4 && !nt) hipLaunchKernelGGL((k_copy_u<4, false>), dim3(blocks), dim3(256), 0, st, s2, d2, n2);
   if (u == 4 && nt) hipLaunchKernelGGL((k_copy_u<4, true>), dim3(blocks), dim3(256), 0, st, s2, d2, n2);
   hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_triad_variant(int v, const double* a, const double* b, double* dst, long long n,
+                                hipStream_t st) {
+  const long long n2 = n / 2;
+  const int u = v == 2 ? 4 : 1;
+  const bool nt = v != 1;
+  const long long blocks = (n2 + 256LL * u - 1) / (256LL * u);
+  if (blocks > (1LL << 30)) return hipErrorInvalidValue;
+  const auto* a2 = reinterpret_cast<const copy_vd2*>(a);
+  const auto* b2 = reinterpret_cast<const copy_vd2*>(b);
+  auto* d2 = reinterpret_cast<copy_vd2*>(dst);
+  if (blocks > 0) {
+    if (u == 1 && nt) hipLaunchKernelGGL((k_triad_u<1, true>), dim3(blocks), dim3(256), 0, st, a2, b2, d2, n2);
+    if (u == 1 && !nt) hipLaunchKernelGGL((k_triad_u<1, false>), dim3(blocks), dim3(256), 0, st, a2, b2, d2, n2);
+    if (u == 4) hipLaunchKernelGGL((k_triad_u<4, true>), dim3(blocks), dim3(256), 0, st, a2, b2, d2, n2);
+  }
+  hipLaunchKernelGGL(k_triad_tail, dim3(1), dim3(64), 0, st, a, b, dst, n);
   return hipGetLastError();
 }
 

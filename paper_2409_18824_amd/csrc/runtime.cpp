@@ -169,6 +169,11 @@ GridArgs make_args(const Field* u, const Field* o, const Field* f, const Field* 
   g.h2f = static_cast<float>(h * h);
   g.order = c.order;
   g.chunk = (g.tiles_x * g.tiles_y + 7) / 8;
+  // the buffer-addressed one-sweep path needs every plane (interior and
+  // halo) under 2^31 bytes
+  const Field* fs[5] = {u, o, f, u64, r32};
+  for (const Field* a : fs)
+    if (a && ((long long)(g.ny + 1) * a->sy + (g.nx + 2)) * a->esize >= (1LL << 31)) g.wide_planes = 1;
   return g;
 }
 

@@ -160,6 +160,39 @@ __device__ __forceinline__ float div6_fused(float x) {
 __device__ __forceinline__ bool div6_small(double x) { return __builtin_fabs(x) < 0x1p-1000; }
 __device__ __forceinline__ bool div6_small(float x) { return __builtin_fabsf(x) < 0x1p-100f; }
 
+// Buffer resource for a wave-uniform base address: every load and store of
+// a plane then takes the plane's address in scalar registers and a per-lane
+// 32-bit byte offset that is fixed for the whole tile, so the z march needs
+// no per-lane address arithmetic.  The descriptor's range is the largest it
+// allows (4 GiB past the base; a plane of the three-sweep pass is smaller,
+// which the host checks); the kernel keeps every access inside the array
+// itself, as with plain pointers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
+}
+
+typedef unsigned buf_u2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Store; NT streams it past the caches (cache policy "nt").
+template <typename T, bool NT>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u2, v), r, off, 0, NT ? 2 : 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, NT ? 2 : 0);
+}
+
 // Rows per thread encoded in the variant bits 2 and 16.
 constexpr int rows_per_thread(int var) { return 1 << (((var >> 1) & 1) + 2 * ((var >> 4) & 1)); }
 
@@ -191,8 +224,249 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return tot;
 }
 
+// Offset that puts a buffer access out of range: the buffer-addressed path
+// runs only on grids whose planes are all shorter than 2^31 bytes
+// (GridArgs::wide_planes == 0), and the hardware drops stores whose offset
+// lies past the resource's range, so a store given this offset writes
+// nothing.
+constexpr uint32_t kDropOffset = 0x80000000u;
+
+// Buffer resource for plane kk of an array with base b and plane stride z
+// bytes, covering rec bytes (the plane's interior and halo).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_n(const void* b, uint64_t z, int kk, uint32_t rec) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(static_cast<const char*>(b)) + (uint64_t)(uint32_t)kk * z, 0, (int)rec, 0x00020000);
+}
+
+// One tile of the cache-fed variants (x-neighbours from the adjacent lanes,
+// the wavefront's two halo columns from one gather, y-neighbours from
+// registers inside the row block and two edge loads outside it).
+//
+// Loads run one plane ahead: step k takes the loads issued one step
+// earlier (its one wait), issues the loads of plane k+1, stores the results
+// of step k-1 and computes plane k, so the loads it waits for had a whole
+// step of arithmetic to arrive, and the stores it issues are waited for only
+// at the start of the next step.  Every memory operation of a step is issued by every
+// lane on every step: loads come from in-bounds addresses (lanes and rows
+// past the interior are clamped onto the halo; the last step reloads its
+// own plane), stores of masked lanes (and the empty store of the first
+// step) are given an out-of-range offset and dropped by the hardware.  The
+// loop therefore has no branches around memory operations, which lets the
+// compiler count exactly which loads a wait needs.  Addresses are a scalar
+// per-plane buffer resource plus a per-lane byte offset fixed for the tile.
+// The arithmetic and its order are those of the LDS variant (same bits).
+template <typename T, int BY, int WX, int VAR, unsigned FL>
+__device__ __forceinline__ void sweep_tile_cf(const GridArgs& g, int t, double* __restrict__ partials,
+                                              Smem<T, BY, WX, VAR>& sm) {
+  constexpr bool STENCIL = !(FL & (F_FIRST | F_NORM));
+  constexpr int RY = rows_per_thread(VAR);
+  constexpr int TX = WAVE * WX;
+  constexpr bool NT = (VAR & 4) != 0;
+  constexpr bool OUT = (FL & (F_WRITE | F_LAST | F_R32)) != 0;
+  constexpr uint32_t ES = sizeof(T);
+  const int lane = threadIdx.x;
+  const int wy = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int tx = t % g.tiles_x;
+  const int t2 = t / g.tiles_x;
+  const int ty = t2 % g.tiles_y;
+  const int tz = t2 / g.tiles_y;
+  const int i = 1 + tx * TX + lane;
+  const int jb = 1 + ty * (BY * RY) + wy * RY;  // first row of this thread
+  const int k0 = 1 + tz * g.planes;
+  const int k1 = min(k0 + g.planes, g.nz + 1);
+  const bool ix = i <= g.nx;
+  const int ic = min(i, g.nx + 1);  // lanes past the interior read the halo column
+
+  // byte offsets within a plane: rows jb .. jb+RY-1 clamped onto the halo
+  // row ny+1 (so the register of row r+1 is the y-neighbour of row r on
+  // every interior row), stores of rows and lanes outside the interior
+  // dropped
+  uint32_t ou[RY], of[RY], oo[RY], orr[RY], oq[RY];
+  bool act[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int y = min(jb + r, g.ny + 1);
+    act[r] = ix && (jb + r <= g.ny);
+    ou[r] = (uint32_t)(ic + g.su_y * y) * ES;
+    of[r] = (uint32_t)(ic + g.sf_y * y) * ES;
+    oo[r] = act[r] ? (uint32_t)(ic + g.so_y * y) * ES : kDropOffset;
+    orr[r] = act[r] ? (uint32_t)(ic + g.sr_y * y) * 4u : kDropOffset;
+    oq[r] = (uint32_t)(ic + g.s64_y * y) * 8u;
+  }
+  // the halo gather: lane q < RY reads the column left of the wavefront in
+  // row q, lane 32 + q the column right of it; the other lanes read a
+  // clamped row of the same columns, whose values go unused
+  const int lw = lane & (WAVE - 1);
+  const int xw = 1 + tx * TX + (lane - lw);
+  const int gq = lw < 32 ? lw : lw - 32;
+  const int gx = lw < 32 ? xw - 1 : min(xw + WAVE, g.nx + 1);
+  const uint32_t oh = (uint32_t)(gx + g.su_y * min(jb + min(gq, RY - 1), g.ny + 1)) * ES;
+  const uint32_t ob = (uint32_t)(ic + g.su_y * (min(jb, g.ny) - 1)) * ES;
+  const uint32_t oa = (uint32_t)(ic + g.su_y * min(jb + RY, g.ny + 1)) * ES;
+
+  // planes: a resource per array and plane, each covering the plane's
+  // interior and halo
+  const uint32_t nxy = (uint32_t)(g.nx + 1);
+  const uint32_t ru = (nxy + (uint32_t)g.su_y * (uint32_t)(g.ny + 1) + 1u) * ES;
+  const uint32_t rf = (nxy + (uint32_t)g.sf_y * (uint32_t)(g.ny + 1) + 1u) * ES;
+  const uint32_t ro = (nxy + (uint32_t)g.so_y * (uint32_t)(g.ny + 1) + 1u) * ES;
+  const uint32_t rr = (nxy + (uint32_t)g.sr_y * (uint32_t)(g.ny + 1) + 1u) * 4u;
+  const uint32_t rq = (nxy + (uint32_t)g.s64_y * (uint32_t)(g.ny + 1) + 1u) * 8u;
+  const uint64_t zu = (uint64_t)g.su_z * ES, zf = (uint64_t)g.sf_z * ES, zo = (uint64_t)g.so_z * ES;
+  const uint64_t zr = (uint64_t)g.sr_z * 4, zq = (uint64_t)g.s64_z * 8;
+  const T h2 = h2_of<T>(g);
+
+  double acc = 0.0;
+  T um[RY], uc[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    um[r] = uc[r] = T(0);
+    if (STENCIL) {
+      um[r] = bload<T>(plane_rsrc_n(g.u, zu, k0 - 1, ru), ou[r]);
+      uc[r] = bload<T>(plane_rsrc_n(g.u, zu, k0, ru), ou[r]);
+    }
+  }
+
+  // the loads a step consumes: f at its plane, u one plane above, the halo
+  // gather and the rows below and above the block at its plane, and (F_LAST)
+  // the FP64 values the update is added to
+  struct Loads {
+    T f[RY], u[RY], halo, below, above;
+    double q[RY];
+  };
+  auto issue = [&](Loads& L, int kk) {
+    const auto pf = plane_rsrc_n(g.f, zf, kk, rf);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) L.f[r] = bload<T>(pf, of[r]);
+    if (STENCIL) {
+      const auto pu1 = plane_rsrc_n(g.u, zu, kk + 1, ru);
+      const auto pu0 = plane_rsrc_n(g.u, zu, kk, ru);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) L.u[r] = bload<T>(pu1, ou[r]);
+      L.halo = bload<T>(pu0, oh);
+      L.below = bload<T>(pu0, ob);
+      L.above = bload<T>(pu0, oa);
+    }
+    if (FL & F_LAST) {
+      const auto pq = plane_rsrc_n(g.u64, zq, kk, rq);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) L.q[r] = bload<double>(pq, oq[r]);
+    }
+  };
+  // results of the previous step, stored at the start of the next one
+  T sv[RY];
+  float sr[RY];
+  double sq[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    sv[r] = T(0);
+    sr[r] = 0.0f;
+    sq[r] = 0.0;
+  }
+  auto flush = [&](int kk, bool any) {
+    if (FL & F_WRITE) {
+      const auto p = plane_rsrc_n(g.o, zo, kk, ro);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) bstore<T, NT>(sv[r], p, any ? oo[r] : kDropOffset);
+    }
+    if (FL & F_R32) {
+      const auto p = plane_rsrc_n(g.r32, zr, kk, rr);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) bstore<float, NT>(sr[r], p, any ? orr[r] : kDropOffset);
+    }
+    if (FL & F_LAST) {
+      const auto p = plane_rsrc_n(g.u64, zq, kk, rq);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) bstore<double, false>(sq[r], p, any && act[r] ? oq[r] : kDropOffset);
+    }
+  };
+  // plane k from the loads in L
+  auto compute = [&](const Loads& L) {
+    T s[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      s[r] = T(0);
+      if (STENCIL) {
+        T xm = from_left(uc[r]), xp = from_right(uc[r]);
+        const T hl = lane_value(L.halo, r), hr = lane_value(L.halo, 32 + r);
+        if (lw == 0) xm = hl;
+        if (lw == WAVE - 1) xp = hr;
+        const T ym = r == 0 ? L.below : uc[r - 1];
+        const T yp = r + 1 < RY ? uc[r + 1] : L.above;
+        T v = xm + xp;
+        v = v + ym;
+        v = v + yp;
+        v = v + um[r];
+        v = v + L.u[r];
+        s[r] = v;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (FL & F_NORM) {
+        const double v = static_cast<double>(L.f[r]) * static_cast<double>(L.f[r]);
+        acc += act[r] ? v : 0.0;
+      }
+      if (STENCIL && (FL & (F_RES | F_R32))) {
+        const double res = static_cast<double>(L.f[r]) -
+                           (6.0 * static_cast<double>(uc[r]) - static_cast<double>(s[r])) / g.h2;
+        if (FL & F_RES) acc += act[r] ? res * res : 0.0;
+        sr[r] = static_cast<float>(res);
+      }
+    }
+    if (FL & (F_WRITE | F_LAST)) {
+      // the quotients by 6 in their fused form, then the rare exact
+      // divisions (see div6)
+      T x[RY];
+      uint64_t small = 0;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        x[r] = s[r] + h2 * L.f[r];
+        sv[r] = div6_fused(x[r]);
+        small |= __builtin_amdgcn_ballot_w64(div6_small(x[r]));
+      }
+      if (small != 0) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) sv[r] = div6(x[r]);
+      }
+      if (FL & F_LAST) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) sq[r] = L.q[r] + static_cast<double>(sv[r]);
+      }
+    }
+    if (STENCIL) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        um[r] = uc[r];
+        uc[r] = L.u[r];
+      }
+    }
+  };
+
+  // N: the loads in flight; C: the ones the step consumes (taking them is
+  // the step's one wait)
+  Loads N, C;
+  issue(N, k0);
+  for (int k = k0; k < k1; ++k) {
+    C = N;
+    issue(N, min(k + 1, k1 - 1));
+    if (OUT) flush(k - 1, k > k0);
+    compute(C);
+  }
+  if (OUT) flush(k1 - 1, true);
+
+  if (FL & (F_RES | F_NORM)) {
+    const double tot = block_sum<BY * WX>(acc, sm.red);
+    if (wy == 0 && lane == 0) partials[g.tile0 + t] = tot;
+  }
+  // The next tile of a persistent workgroup reuses the shared buffers.
+  __syncthreads();
+}
+
 // One tile: local tile index t of grid g.  Writes the tile's partial sum
-// (F_RES / F_NORM) to partials[g.tile0 + t].
+// (F_RES / F_NORM) to partials[g.tile0 + t].  The cache-fed variants run
+// sweep_tile_cf unless a plane of the grid spans 2^31 bytes or more; this
+// pointer-addressed body serves the LDS variants and those grids.
 //
 // Each thread owns RY consecutive rows of its column (register blocking in
 // y as well as z): per plane it issues the 2*RY HBM loads of its rows at
@@ -210,6 +484,12 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
   constexpr int TR = BY * RY;      // rows per tile
   constexpr int TX = WAVE * WX;    // columns per tile
   constexpr bool NT = (VAR & 4) != 0;
+  if constexpr ((VAR & 1) == 0) {
+    if (g.wide_planes == 0) {
+      sweep_tile_cf<T, BY, WX, VAR, FL>(g, t, partials, sm);
+      return;
+    }
+  }
   const int lane = threadIdx.x;    // column within the tile
   const int wy = threadIdx.y;
   const int tx = t % g.tiles_x;

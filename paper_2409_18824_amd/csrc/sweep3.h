@@ -47,39 +47,6 @@ struct Smem3 {
   double red[BY];
 };
 
-// Buffer resource for a wave-uniform base address: every load and store of
-// a plane then takes the plane's address in scalar registers and a per-lane
-// 32-bit byte offset that is fixed for the whole tile, so the z march needs
-// no per-lane address arithmetic.  The descriptor's range is the largest it
-// allows (4 GiB past the base; a plane of the three-sweep pass is smaller,
-// which the host checks); the kernel keeps every access inside the array
-// itself, as with plain pointers.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, -1, 0x00020000);
-}
-
-typedef unsigned buf_u2 __attribute__((ext_vector_type(2)));
-
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-
-// Store; NT streams it past the caches (cache policy "nt").
-template <typename T, bool NT>
-__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-  if constexpr (sizeof(T) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u2, v), r, off, 0, NT ? 2 : 0);
-  else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, NT ? 2 : 0);
-}
-
 // The value of lane l-1 (shl: l+1) of the wavefront; lane 0 (63) gets 0.
 // One DPP move per 32-bit half, with no copy of the destination first: the
 // three-sweep tile never uses the shifted value at its edge lanes.

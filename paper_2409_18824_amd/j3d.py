@@ -136,6 +136,7 @@ _SIGS = {
     "j3d_fill_uniform": ([_P(J3DArray), _U64, _U32, _D, _D, _D, _V], ctypes.c_int),
     "j3d_fill_const": ([_P(J3DArray), _D, _V], ctypes.c_int),
     "j3d_bandwidth_probe": ([_V, _V, _I64, _I32, _P(_D), _V], ctypes.c_int),
+    "j3d_bandwidth_probe_triad": ([_V, _V, _V, _I64, _I32, _P(_D), _V], ctypes.c_int),
     "j3d_sum": ([_V, _I64, _U32, _V, _V], ctypes.c_int),
     "jacobi2d_sweeps": ([_P(J3DArray), _P(J3DArray), _I64, _D, _U32, _V, _V], ctypes.c_int),
     "j3d_dot": ([_V, _V, _I64, _U32, _V, _V], ctypes.c_int),
@@ -567,6 +568,16 @@ def j3d_bandwidth_probe(src: torch.Tensor, dst: torch.Tensor, reps: int = 10, st
     n = min(src.numel(), dst.numel())
     _check(_lib.j3d_bandwidth_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, reps,
                                     ctypes.byref(g), _stream_handle(stream)), "j3d_bandwidth_probe")
+    return g.value
+
+
+def j3d_bandwidth_probe_triad(a: torch.Tensor, b: torch.Tensor, dst: torch.Tensor, reps: int = 10,
+                              stream=None) -> float:
+    g = ctypes.c_double()
+    n = min(a.numel(), b.numel(), dst.numel())
+    _check(_lib.j3d_bandwidth_probe_triad(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                          ctypes.c_void_p(dst.data_ptr()), n, reps, ctypes.byref(g),
+                                          _stream_handle(stream)), "j3d_bandwidth_probe_triad")
     return g.value
 
 

@@ -63,6 +63,7 @@ INTENT = {
     "j3d_fill_uniform": {"a": "out"},
     "j3d_fill_const": {"a": "out"},
     "j3d_bandwidth_probe": {"src": "in", "dst": "out", "gbps": "out"},
+    "j3d_bandwidth_probe_triad": {"a": "in", "b": "in", "dst": "out", "gbps": "out"},
 }
 
 
@@ -282,17 +283,31 @@ def test_sum_dot_validation_before_device_work():
     assert "overlaps" in j3d.last_error()
 
 
+def test_bandwidth_probes_validate_before_device_work():
+    lib = j3d._lib
+    g = ctypes.c_double()
+    pg = ctypes.byref(g)
+    a, b, d = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    assert lib.j3d_bandwidth_probe_triad(a, b, None, 64, 1, pg, None) == j3d.EINVAL  # null dst
+    assert lib.j3d_bandwidth_probe_triad(a, b, d, 1, 1, pg, None) == j3d.EINVAL  # n < 2
+    assert lib.j3d_bandwidth_probe_triad(a, b, d, 64, 0, pg, None) == j3d.EINVAL  # reps < 1
+    assert lib.j3d_bandwidth_probe_triad(a, b, ctypes.c_void_p(0x300008), 64, 1, pg, None) == j3d.EINVAL  # misaligned
+    assert lib.j3d_bandwidth_probe_triad(a, b, ctypes.c_void_p(0x200000 + 256), 64, 1, pg, None) == j3d.EALIAS
+    assert lib.j3d_bandwidth_probe(a, ctypes.c_void_p(0x100000 + 256), 64, 1, pg, None) == j3d.EALIAS
+    assert lib.j3d_bandwidth_probe(a, None, 64, 1, pg, None) == j3d.EINVAL
+
+
 def test_tune_query_default_set_and_bad_kind():
     # defaults (no cache entry for this odd shape)
-    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (4, 1, 20, 0, 0, 1)  # at most 64^3 points
-    assert j3d.j3d_tune_query_single(j3d.F64, 65, 64, 64) == (1, 2, 20, 0, 1, 1)
-    assert j3d.j3d_tune_query_single(j3d.F32, 97, 5, 3) == (1, 2, 20, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (4, 2, 6, 0, 0, 1)  # at most 64^3 points
+    assert j3d.j3d_tune_query_single(j3d.F64, 65, 64, 64) == (1, 16, 20, 0, 2, 1)
+    assert j3d.j3d_tune_query_single(j3d.F32, 97, 5, 3) == (1, 16, 20, 0, 2, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X2, 97, 5, 3) == (4, 16, 20, 0, 1, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X2, 97, 5, 3) == (8, 8, 20, 0, 0, 1)
     # a pinned shape is what later calls of that kind and shape use
     j3d.j3d_tune_set_single(j3d.F32, 97, 5, 3, (2, 8, 6, 1, 2, 1))
     assert j3d.j3d_tune_query_single(j3d.F32, 97, 5, 3) == (2, 8, 6, 1, 2, 1)
-    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (4, 1, 20, 0, 0, 1)
+    assert j3d.j3d_tune_query_single(j3d.F64, 97, 5, 3) == (4, 2, 6, 0, 0, 1)
     with pytest.raises(j3d.J3DError) as ei:
         j3d.j3d_tune_query_single(7, 97, 5, 3)
     assert ei.value.code == j3d.EDTYPE
@@ -396,7 +411,7 @@ def test_three_sweep_kind_defaults_and_validation():
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 256, 256, 256) == (4, 16, 20, 0, 2, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 384, 384, 384) == (8, 32, 6, 0, 2, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (8, 96, 6, 0, 1, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (8, 96, 6, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (4, 24, 20, 0, 2, 1)
     for bad in [(1, 16, 20, 0, 1, 1), (4, 16, 16, 0, 1, 1), (4, 16, 20, 1, 1, 1), (4, 16, 20, 0, 1, 2),
                 (16, 16, 20, 0, 1, 1), (3, 16, 20, 0, 1, 1), (5, 16, 20, 0, 1, 1), (6, 8, 6, 0, 1, 1),
                 (7, 16, 20, 0, 1, 1), (4, 16, 6, 0, 3, 1)]:

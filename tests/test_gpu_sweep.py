@@ -326,6 +326,38 @@ def test_full_size_sweep_512():
     assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
 
 
+@pytest.mark.parametrize("tune", [(1, 2, 20, 0, 1, 1), (2, 4, 6, 0, 2, 2)])
+def test_sweep_output_plane_of_2gib(tune):
+    """An output array whose rows are padded so that one plane spans more
+    than 2^31 bytes (9.5 GB in all): the pass must take its pointer-addressed
+    path, give the oracle's bits and leave every element outside the interior
+    (halo and padding) unchanged."""
+    nx, ny, nz = 70, 9, 2
+    ld = (1 << 28) // (ny + 1) + 64
+    say("sweep with an output plane over 2 GiB", tune, "row stride", ld)
+    u, f, h = make_inputs(nx, ny, nz)
+    j3d.j3d_tune_set_single(j3d.F64, nx, ny, nz, tune)
+    du = j3d.FArray.from_numpy(u)
+    df = j3d.FArray.from_numpy(f)
+    dv = j3d.FArray.empty(nx, ny, nz, ld_extra=ld - 80)
+    assert dv.stride[1] * (ny + 1) * 8 >= 1 << 31
+    dv.storage.fill_(0.375)
+    dv.copy_from(u)
+    before = dv.storage.clone()
+    r = torch.zeros(1, dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep(du, dv, df, h, resid_out=r)
+    torch.cuda.synchronize()
+    want = oracle.sweep(u, f, h)
+    assert np.array_equal(dv.to_numpy(), want)
+    assert rel(float(r.item()), oracle.residual_l2(u, f, h)) <= RESID_RTOL
+    # outside the interior nothing changed
+    dv.view()[1:-1, 1:-1, 1:-1] = 0.0
+    after = dv.storage
+    bv = torch.as_strided(before, dv.view().shape, dv.view().stride(), dv.offset)
+    bv[1:-1, 1:-1, 1:-1] = 0.0
+    assert torch.equal(before, after)
+
+
 def test_bandwidth_probe_sane():
     n = 1 << 27
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -334,3 +366,8 @@ def test_bandwidth_probe_sane():
     say("copy GB/s", g)
     assert torch.equal(a, b)
     assert 500.0 < g < 8000.0 * 1.05
+    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+    g3 = j3d.j3d_bandwidth_probe_triad(a, c, b, reps=3)
+    say("two reads + one write GB/s", g3)
+    assert torch.equal(b, torch.full_like(b, 3.0))
+    assert 500.0 < g3 < 8000.0 * 1.05
