@@ -21,14 +21,18 @@ struct AdvArgs {
   long long soz;
   double cx, cy, cz;    // momentum: 0.25 / spacing
   int tiles_x, tiles_y, yblocks, planes;  // set by the launchers
+  int buffer_ok;        // every plane of every field spans less than 2^31 bytes
 };
 
 // Tile shape of the advection kernels: rows per thread (2, 4 or 8), z-planes
-// per wavefront, nontemporal stores (0 or 1).
+// per wavefront, nontemporal stores (0 or 1), and for the momentum advection
+// whether its loads run one plane ahead (pf = 1: 2 or 4 rows per thread;
+// taken only where AdvArgs::buffer_ok, else the kernel without it runs).
 struct AdvectCfg {
   int ry;
   int planes;
   int nt;
+  int pf = 0;
 };
 bool advect_cfg_supported(const AdvectCfg& c);
 hipError_t launch_pw_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st);

@@ -181,6 +181,121 @@ __global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect(AdvArgs a) {
   }
 }
 
+// The momentum advection with the loads of plane k+2 issued at the start of
+// step k (one plane ahead of the three-plane window the step uses), the
+// results of step k stored at the start of step k+1, and every plane
+// addressed through a scalar buffer resource with 32-bit per-lane offsets:
+// no branch surrounds a memory operation (lanes and rows outside the
+// interior store with an out-of-range offset, which the hardware drops),
+// so the compiler's waits cover exactly the loads a step consumes.  Needs
+// every plane of the six fields under 2^31 bytes (AdvArgs::buffer_ok).
+// Same arithmetic and order as k_pw_advect.
+template <int RY, bool NT>
+__global__ void __launch_bounds__(WAVE * kWaves) k_pw_advect_pf(AdvArgs a) {
+  using sweep_detail::bload;
+  using sweep_detail::bstore;
+  using sweep_detail::kDropOffset;
+  using sweep_detail::plane_rsrc_n;
+  constexpr int R = RY + 2;
+  const TileMap m = tile_of(a, RY);
+  if (!m.valid) return;  // the whole wavefront leaves together
+  const int lane = m.lane;
+  uint32_t roff[R];  // byte offsets of rows j0-1 .. j0+RY (clamped)
+#pragma unroll
+  for (int r = 0; r < R; ++r) roff[r] = (uint32_t)(m.xc + a.siy * min(m.j0 - 1 + r, a.ny + 1)) * 8u;
+  const uint32_t goff = (uint32_t)m.goff * 8u;  // every lane loads; only the gather lanes' values are used
+  const bool lane_out = m.x <= a.nx;
+  uint32_t oo[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int j = m.j0 + r;
+    oo[r] = (lane_out && j <= a.ny) ? (uint32_t)(m.x + a.soy * j) * 8u : kDropOffset;
+  }
+  const uint32_t rin = ((uint32_t)(a.nx + 1) + (uint32_t)a.siy * (uint32_t)(a.ny + 1) + 1u) * 8u;
+  const uint32_t rout = ((uint32_t)(a.nx + 1) + (uint32_t)a.soy * (uint32_t)(a.ny + 1) + 1u) * 8u;
+  const uint64_t zin = (uint64_t)a.siz * 8u, zout = (uint64_t)a.soz * 8u;
+  struct Plane {
+    double u[R], v[R], w[R], gu, gv, gw;
+  };
+  auto load = [&](Plane& p, int k) {
+    const auto ru = plane_rsrc_n(a.in[0], zin, k, rin);
+    const auto rv = plane_rsrc_n(a.in[1], zin, k, rin);
+    const auto rw = plane_rsrc_n(a.in[2], zin, k, rin);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      p.u[r] = bload<double>(ru, roff[r]);
+      p.v[r] = bload<double>(rv, roff[r]);
+      p.w[r] = bload<double>(rw, roff[r]);
+    }
+    p.gu = bload<double>(ru, goff);
+    p.gv = bload<double>(rv, goff);
+    p.gw = bload<double>(rw, goff);
+  };
+  // tendencies of the previous step, stored at the start of the next one
+  double ts[3][RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) ts[0][r] = ts[1][r] = ts[2][r] = 0.0;
+  auto flush = [&](int kk, bool any) {
+    const auto o0 = plane_rsrc_n(a.out[0], zout, kk, rout);
+    const auto o1 = plane_rsrc_n(a.out[1], zout, kk, rout);
+    const auto o2 = plane_rsrc_n(a.out[2], zout, kk, rout);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const uint32_t off = any ? oo[r] : kDropOffset;
+      bstore<double, NT>(ts[0][r], o0, off);
+      bstore<double, NT>(ts[1][r], o1, off);
+      bstore<double, NT>(ts[2][r], o2, off);
+    }
+  };
+  // planes k-1, k, k+1 of the step, and the next plane in flight
+  Plane P0, P1, P2, N;
+  load(P0, m.k0 - 1);
+  load(P1, m.k0);
+  load(N, m.k0 + 1);
+  const double cx = a.cx, cy = a.cy, cz = a.cz;
+  for (int k = m.k0; k < m.k1; ++k) {
+    P2 = N;
+    load(N, min(k + 2, a.nz + 1));
+    flush(max(k - 1, 0), k > m.k0);
+#pragma unroll
+    for (int r = 1; r <= RY; ++r) {
+      const double u = P1.u[r], v = P1.v[r], w = P1.w[r];
+      const double uL = nb_left(u, P1.gu, r, lane), uR = nb_right(u, P1.gu, r, lane);
+      const double vL = nb_left(v, P1.gv, r, lane), vR = nb_right(v, P1.gv, r, lane);
+      const double wL = nb_left(w, P1.gw, r, lane), wR = nb_right(w, P1.gw, r, lane);
+      // u at the east face (i+1/2, j, k)
+      const double sxm = uL + u, sxp = u + uR;
+      double tx = flux_diff(sxm, sxm, sxp, sxp, cx);
+      const double vs = P1.v[r - 1];
+      double ty = flux_diff(vs + nb_right(vs, P1.gv, r - 1, lane), P1.u[r - 1] + u, v + vR, u + P1.u[r + 1], cy);
+      const double wb = P0.w[r];
+      double tz = flux_diff(wb + nb_right(wb, P0.gw, r, lane), P0.u[r] + u, w + wR, u + P2.u[r], cz);
+      const double su = (tx + ty) + tz;
+      // v at the north face (i, j+1/2, k)
+      const double un = P1.u[r + 1];
+      tx = flux_diff(uL + nb_left(un, P1.gu, r + 1, lane), vL + v, u + un, v + vR, cx);
+      const double syn = vs + v, syp = v + P1.v[r + 1];
+      ty = flux_diff(syn, syn, syp, syp, cy);
+      tz = flux_diff(wb + P0.w[r + 1], P0.v[r] + v, w + P1.w[r + 1], v + P2.v[r], cz);
+      const double sv = (tx + ty) + tz;
+      // w at the top face (i, j, k+1/2)
+      const double ut = P2.u[r];
+      tx = flux_diff(uL + nb_left(ut, P2.gu, r, lane), wL + w, u + ut, w + wR, cx);
+      const double vt = P2.v[r - 1];
+      ty = flux_diff(vs + vt, P1.w[r - 1] + w, v + P2.v[r], w + P1.w[r + 1], cy);
+      const double szm = wb + w, szp = w + P2.w[r];
+      tz = flux_diff(szm, szm, szp, szp, cz);
+      const double sw = (tx + ty) + tz;
+      ts[0][r - 1] = su;
+      ts[1][r - 1] = sv;
+      ts[2][r - 1] = sw;
+    }
+    P0 = P1;
+    P1 = P2;
+  }
+  flush(m.k1 - 1, true);
+}
+
 __device__ __forceinline__ double upwind(double q, double below, double above) {
   const double qp = q > 0.0 ? q : 0.0;
   const double qm = q < 0.0 ? q : 0.0;
@@ -437,13 +552,23 @@ hipError_t go(Kernel kern, AdvArgs a, int ry, hipStream_t st) {
 }  // namespace
 
 bool advect_cfg_supported(const AdvectCfg& c) {
-  return (c.ry == 2 || c.ry == 4 || c.ry == 8) && c.planes >= 1 && (c.nt == 0 || c.nt == 1);
+  return (c.ry == 2 || c.ry == 4 || c.ry == 8) && c.planes >= 1 && (c.nt == 0 || c.nt == 1) &&
+         (c.pf == 0 || c.pf == 1);
 }
 
 hipError_t launch_pw_advect(const AdvArgs& a, const AdvectCfg& c, hipStream_t st) {
   if (!advect_cfg_supported(c)) return hipErrorInvalidValue;
   AdvArgs g = a;
   g.planes = c.planes;
+  if (c.pf && a.buffer_ok) {
+    switch (c.ry * 2 + c.nt) {
+      case 4: return go(k_pw_advect_pf<2, false>, g, 2, st);
+      case 5: return go(k_pw_advect_pf<2, true>, g, 2, st);
+      case 8: return go(k_pw_advect_pf<4, false>, g, 4, st);
+      case 9: return go(k_pw_advect_pf<4, true>, g, 4, st);
+      default: break;  // 8 rows: the kernel without the prefetch
+    }
+  }
   switch (c.ry * 2 + c.nt) {
     case 4: return go(k_pw_advect<2, false>, g, 2, st);
     case 5: return go(k_pw_advect<2, true>, g, 2, st);

@@ -16,8 +16,9 @@ from paper_2409_18824_amd import j3d
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
-# rows per thread, z-planes per wavefront, nontemporal stores
-TILES = ["2,7,0", "2,128,1", "4,5,1", "4,128,0", "8,3,0", "8,64,1"]
+# rows per thread, z-planes per wavefront, nontemporal stores[, loads one plane ahead]
+TILES = ["2,7,0", "2,128,1", "4,5,1", "4,128,0", "8,3,0", "8,64,1", "2,7,0,1", "2,128,1,1", "4,5,1,1", "4,128,0,1",
+         "8,3,0,1"]
 # x tiles are 64 wide, y tiles 4 x rows-per-thread, z chunks `planes` deep
 SHAPES = [(1, 1, 1), (64, 4, 3), (65, 8, 2), (63, 17, 9), (130, 37, 19), (125, 9, 131)]
 
