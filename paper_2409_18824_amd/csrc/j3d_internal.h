@@ -103,6 +103,33 @@ int persistent_grid(const TileCfg& c);
 hipError_t launch_pass_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
                            double* partials, const int* done, hipStream_t st);
 
+// The check of the previous pass, reduced by one extra workgroup of a
+// one-sweep pass instead of by a kernel of its own: the sum of
+// partials[0 .. n) in the order of the reduction kernels (launch_reduce_*:
+// 1024 threads, thread q adding slots q, q + 1024, ... in turn, then each
+// wavefront's butterfly, then the 16 wavefront sums in order), then what
+// launch_reduce_count does with it: hist[*qnext] = sqrt(sum), *done and
+// *conv_at set when it is not finite or at most rtol * *normf (*nonfinite
+// too when not finite), *qnext advanced.  partials == nullptr: no check.
+struct PreReduce {
+  const double* partials;
+  int n;
+  double* hist;
+  const double* normf;
+  double rtol;
+  int* done;
+  long long* conv_at;
+  int* nonfinite;
+  long long* qnext;
+};
+
+// launch_pass_one with the previous pass's check reduced by an extra
+// workgroup of the same launch (which then must not run when *pr.done is
+// set: pass done == pr.done).  pr.partials must not be the partials this
+// pass writes.
+hipError_t launch_pass_one_pre(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                               double* partials, const int* done, const PreReduce& pr, hipStream_t st);
+
 // Launch one pass over a table of grids in device memory (tile0 ascending,
 // tiles of grid g are [tile0[g], tile0[g] + tx*ty*tz)).  done, if not
 // null, is a flag array indexed by GridArgs::id; tiles of done grids are

@@ -416,6 +416,13 @@ hipError_t launch_pass_one(int dtype, unsigned flags, const TileCfg& c, const Gr
   return dispatch(dtype, flags, L);
 }
 
+hipError_t launch_pass_one_pre(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,
+                               double* partials, const int* done, const PreReduce& pr, hipStream_t st) {
+  sweep_detail::Launch L{false, &c, &g, nullptr, 1, 0, partials, done, st};
+  L.pr = pr;
+  return dispatch(dtype, flags, L);
+}
+
 hipError_t launch_pass_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table,
                              int ngrids, int ntiles, double* partials, const int* done,
                              hipStream_t st) {

@@ -103,8 +103,145 @@ void fill_result(j3d_solve_result* r, long long sweeps, double resid, const std:
 // ---------------------------------------------------------------------
 // FP64 mode
 // ---------------------------------------------------------------------
+
+// Solves that check after every sweep on grids of at most 2^24 points,
+// where a check's reduction kernel costs about half a sweep: each pass's
+// check is reduced by an extra workgroup of the next pass
+// (launch_pass_one_pre).  That pass runs before the check's verdict is
+// known, so the iterates rotate through three arrays (the pass after a
+// converged check writes the array of the iterate before it, never the
+// converged one) and the per-tile partials through two.  Same kernels,
+// same reduction order, same results as the schedule with a reduction
+// kernel per check.  J3D_SOLVE_FUSED_CHECKS=0 turns it off.
+bool fused_checks_apply(long long c, long long points) {
+  const char* e = std::getenv("J3D_SOLVE_FUSED_CHECKS");
+  if (e != nullptr && std::atoi(e) == 0) return false;
+  return c == 1 && points <= (1LL << 24);
+}
+
+int solve_fp64_fused_checks(const Field& u, const Field& f, double h, const j3d_solve_opts& o,
+                            j3d_solve_result* res, hipStream_t st) {
+  Scratch* s = nullptr;
+  J3D_TRY(get_scratch(st, &s));
+  const TileCfg cfg = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());
+  const long long S = o.max_sweeps;
+  const long long points = (long long)u.nx() * u.ny() * u.nz();
+
+  // u, and two arrays of u's layout in the work buffer, all with u's halo
+  const size_t span = (u.span_bytes() + 255) / 256 * 256;
+  J3D_TRY(ensure_work(s, 2 * span));
+  Field buf3[3] = {u, u, u};
+  buf3[1].base = static_cast<char*>(s->work);
+  buf3[2].base = static_cast<char*>(s->work) + span;
+  J3D_HIP(hipMemcpyAsync(buf3[1].base, u.base, u.span_bytes(), hipMemcpyDeviceToDevice, st));
+  J3D_HIP(hipMemcpyAsync(buf3[2].base, u.base, u.span_bytes(), hipMemcpyDeviceToDevice, st));
+
+  GridArgs one[3], resid[3];
+  for (int b = 0; b < 3; ++b) {
+    one[b] = make_args(&buf3[b], &buf3[(b + 1) % 3], &f, nullptr, nullptr, h, cfg, 0);
+    resid[b] = make_args(&buf3[b], nullptr, &f, nullptr, nullptr, h, cfg, 0);
+  }
+  const int nt = one[0].tiles_x * one[0].tiles_y * one[0].tiles_z;
+  const size_t ntp = ((size_t)nt + 31) / 32 * 32;
+  J3D_TRY(ensure_partials(s, 2 * ntp));
+  double* part[2] = {s->partials, s->partials + ntp};
+  J3D_TRY(ensure_hist(s, (size_t)S + 1));
+  J3D_HIP(hipMemsetAsync(s->ctl, 0, sizeof(Control), st));
+  J3D_TRY(norm_f(f, cfg, s, st));
+  int* done = &s->ctl->done;
+  auto pre_of = [&](long long q) {  // the reduction of check q (the partials of pass q)
+    PreReduce pr{part[q & 1], nt, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
+                 &s->ctl->nonfinite, &s->ctl->qnext};
+    return pr;
+  };
+  // pass p: iterate p (array p % 3) -> p + 1, residual of iterate p into
+  // part[p % 2], the check of pass p - 1 reduced on the side
+  auto pass = [&](long long p, hipStream_t q) -> int {
+    const int b = (int)(p % 3);
+    if (p == 0) {
+      J3D_HIP(launch_pass_one(J3D_F64, F_WRITE | F_RES, cfg, one[b], part[0], done, q));
+    } else {
+      J3D_HIP(launch_pass_one_pre(J3D_F64, F_WRITE | F_RES, cfg, one[b], part[p & 1], done, pre_of(p - 1), q));
+    }
+    return J3D_OK;
+  };
+  const long long chunk = chunk_sweeps(points, 24.0, 6);  // a multiple of the 3 x 2 rotation
+  long long p = 0;
+  int slot = 0;
+  bool seen = false;
+  if (S > 0) {
+    J3D_TRY(pass(0, st));
+    p = 1;
+  }
+  // whole chunks starting at passes 1, 1 + M, ... replayed from one graph
+  const long long M = std::min(chunk, (S - 1) / 2 / 6 * 6);
+  if (S > 0 && M > 0) {
+    std::string key = "fp64-fused";
+    auto add = [&key](const void* x, size_t n) { key.append(static_cast<const char*>(x), n); };
+    add(one, sizeof one);
+    add(&cfg, sizeof cfg);
+    const long long meta[3] = {M, nt, (long long)ntp};
+    add(meta, sizeof meta);
+    const void* ptrs[3] = {s->partials, s->hist, s->ctl};
+    add(ptrs, sizeof ptrs);
+    add(&o.rtol, sizeof o.rtol);
+    hipGraphExec_t exec = nullptr;
+    J3D_TRY(solve_graph(s, key, [&](hipStream_t q) -> int {
+      for (long long i = 1; i <= M; ++i) J3D_TRY(pass(i, q));
+      return J3D_OK;
+    }, &exec));
+    while (p + M <= S && !seen) {
+      J3D_HIP(hipGraphLaunch(exec, st));
+      p += M;
+      J3D_TRY(publish_done(s, slot, st));
+      if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
+      ++slot;
+    }
+  }
+  while (p < S && !seen) {
+    const long long end = std::min(S, p + chunk);
+    for (; p < end; ++p) J3D_TRY(pass(p, st));
+    J3D_TRY(publish_done(s, slot, st));
+    if (slot > 0) J3D_TRY(poll_done(s, slot - 1, &seen));
+    ++slot;
+  }
+  // the residual of the last iterate (check S), which also reduces check
+  // S - 1; skipped, like every kernel after it, once a check converged
+  const int bl = (int)(S % 3);
+  if (S > 0)
+    J3D_HIP(launch_pass_one_pre(J3D_F64, F_RES, cfg, resid[bl], part[S & 1], done, pre_of(S - 1), st));
+  else
+    J3D_HIP(launch_pass_one(J3D_F64, F_RES, cfg, resid[bl], part[0], done, st));
+  J3D_HIP(launch_reduce_count(part[S & 1], nt, s->hist, &s->ctl->normf, o.rtol, done, &s->ctl->conv_at,
+                              &s->ctl->nonfinite, &s->ctl->qnext, st));
+  Control ctl;
+  J3D_TRY(read_control(s, &ctl, st));
+  long long sweeps, nh;
+  int at;
+  if (ctl.done) {
+    sweeps = ctl.conv_at;
+    nh = ctl.conv_at + 1;
+    at = (int)(ctl.conv_at % 3);
+  } else {
+    sweeps = S;
+    nh = S + 1;
+    at = bl;
+  }
+  std::vector<double> hist;
+  J3D_TRY(read_history(s, nh, &hist, st));
+  if (at != 0) {
+    J3D_HIP(launch_copy_interior(reinterpret_cast<const double*>(buf3[at].base), reinterpret_cast<double*>(u.base),
+                                 u.nx(), u.ny(), u.nz(), u.sy, u.sz, u.sy, u.sz, st));
+    J3D_HIP(hipStreamSynchronize(st));
+  }
+  fill_result(res, sweeps, hist[(size_t)nh - 1], hist, ctl.normf, ctl.done != 0, ctl.nonfinite != 0, o);
+  return ctl.nonfinite ? fail(J3D_ENONFINITE, "residual became non-finite") : J3D_OK;
+}
+
 int solve_fp64(const Field& u, const Field& f, double h, const j3d_solve_opts& o,
                j3d_solve_result* res, hipStream_t st) {
+  if (forced_step() == 0 && fused_checks_apply(o.check_every, (long long)u.nx() * u.ny() * u.nz()))
+    return solve_fp64_fused_checks(u, f, h, o, res, st);
   Scratch* s = nullptr;
   J3D_TRY(get_scratch(st, &s));
   const TileCfg cfg = default_cfg(J3D_F64, u.nx(), u.ny(), u.nz());

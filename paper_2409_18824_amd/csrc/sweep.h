@@ -645,18 +645,59 @@ __device__ __forceinline__ void sweep_tile(const GridArgs& g, int t, double* __r
   __syncthreads();
 }
 
+// The previous pass's check (PreReduce), reduced by one workgroup of any
+// size that divides 1024 into the same bits as the 1024-thread reduction
+// kernels: thread t stands in for threads t, t + T, t + 2T, ... of those,
+// each with its own sum in slot order, and the wavefront butterflies and
+// the sums of the 16 wavefronts follow in the same order.
+__device__ __forceinline__ void pre_reduce(const PreReduce& pr) {
+  constexpr int VT = 1024;  // threads of the reduction kernels
+  __shared__ double ws[VT / WAVE];
+  const int T = blockDim.x * blockDim.y;
+  const int t = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int q = t; q < VT; q += T) {
+    double a = 0.0;
+    for (int m = q; m < pr.n; m += VT) a += pr.partials[m];
+    a = wave_sum(a);
+    if ((q & (WAVE - 1)) == 0) ws[q / WAVE] = a;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double tot = ws[0];
+#pragma unroll
+    for (int w = 1; w < VT / WAVE; ++w) tot += ws[w];
+    const long long q = *pr.qnext;
+    const double r = sqrt(tot);
+    pr.hist[q] = r;
+    const bool bad = !isfinite(r);
+    if (bad || r <= pr.rtol * (*pr.normf)) {
+      *pr.done = 1;
+      *pr.conv_at = q;
+      if (bad) *pr.nonfinite = 1;
+    }
+    *pr.qnext = q + 1;
+  }
+}
+
+// One pass over one grid; with pr.partials set, the last workgroup reduces
+// the previous pass's check instead of taking tiles.
 template <typename T, int BY, int WX, int VAR, unsigned FL>
 __global__ void __launch_bounds__(WAVE * WX * BY)
-    k_pass_one(GridArgs g, double* __restrict__ partials, const int* __restrict__ done) {
+    k_pass_one(GridArgs g, double* __restrict__ partials, const int* __restrict__ done, PreReduce pr) {
   if (done != nullptr && *done != 0) return;
+  const int nb = (int)gridDim.x - (pr.partials != nullptr ? 1 : 0);  // workgroups taking tiles
+  if ((int)blockIdx.x == nb) {
+    pre_reduce(pr);
+    return;
+  }
   __shared__ Smem<T, BY, WX, VAR> sm;
   const int ntiles = g.tiles_x * g.tiles_y * g.tiles_z;
   if (g.order == 0) {
-    for (int t = xcd_remap(blockIdx.x, gridDim.x); t < ntiles; t += gridDim.x)
+    for (int t = xcd_remap(blockIdx.x, nb); t < ntiles; t += nb)
       sweep_tile<T, BY, WX, VAR, FL>(g, t, partials, sm);
   } else {
     const int nv = virtual_tiles(ntiles, g.order, g.chunk);
-    for (int vb = blockIdx.x; vb < nv; vb += gridDim.x) {
+    for (int vb = blockIdx.x; vb < nv; vb += nb) {
       const int t = g.order == 2 ? xcd_chunked(vb, g.chunk) : vb;
       if (t < ntiles) sweep_tile<T, BY, WX, VAR, FL>(g, t, partials, sm);
     }
@@ -710,6 +751,7 @@ struct Launch {
   double* partials;
   const int* done;
   hipStream_t st;
+  PreReduce pr{};  // one-sweep passes over one grid only
 };
 
 template <typename T, int BY, int WX, int VAR, unsigned FL>
@@ -736,8 +778,9 @@ hipError_t go(const Launch& L) {
       grid = min(grid, cap);
     }
     if (grid <= 0) return hipSuccess;
+    if (L.pr.partials != nullptr) ++grid;  // the workgroup that reduces the previous check
     hipLaunchKernelGGL((k_pass_one<T, BY, WX, VAR, FL>), dim3(grid), dim3(WAVE * WX, BY), 0, L.st, g,
-                       L.partials, L.done);
+                       L.partials, L.done, L.pr);
   }
   return hipGetLastError();
 }

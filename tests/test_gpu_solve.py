@@ -68,6 +68,48 @@ def test_plain_early_exit_matches_oracle():
     assert np.array_equal(du.to_numpy(), uo)
 
 
+@pytest.mark.parametrize("n,rtol", [(12, 1e-3), (16, 2e-5), (9, 1e-12)])
+def test_plain_early_exit_every_sweep_matches_oracle(n, rtol):
+    """A check after every sweep (each check reduced by a workgroup of the
+    next pass, which runs before the verdict is known): the solve stops at
+    the oracle's sweep with the oracle's iterate, including exits inside a
+    replayed chunk."""
+    say("plain early exit, check every sweep", n, rtol)
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 5, 1, 0, 1)
+    f = synth.manufactured_f(n, n, n, h)
+    du, df = j3d.FArray.from_numpy(u0), j3d.FArray.from_numpy(f)
+    res = j3d.poisson_solve(du, df, h, rtol=rtol, max_sweeps=100000, check_every=1)
+    uo, ro = oracle.solve_plain(u0, f, h, rtol=rtol, check_every=1, max_sweeps=100000)
+    assert ro.converged and res.converged
+    assert res.sweeps == ro.sweeps
+    assert len(res.history) == len(ro.history)
+    assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res.history, ro.history))
+    assert np.array_equal(du.to_numpy(), uo)
+
+
+@pytest.mark.parametrize("n,S,rtol", [(64, 100, 0.0), (9, 1, 0.0), (9, 0, 0.0), (11, 1001, 0.0), (12, 100000, 1e-3),
+                                      (10, 7, 0.0), (13, 13, 0.0)])
+def test_fused_checks_equal_reduction_kernels(n, S, rtol, monkeypatch):
+    """The checks reduced inside the next pass give the same bits as the
+    schedule with a reduction kernel per check: history, sweeps, iterate."""
+    say("fused checks", n, S, rtol)
+    h = 1.0 / (n + 1)
+    u0 = synth.uniform_field(n, n, n, 7, 1, 0, 1)
+    f = synth.manufactured_f(n, n, n, h) if rtol > 0 else synth.uniform_field(n, n, n, 7, 2, -1, 1)
+    df = j3d.FArray.from_numpy(f)
+    out = []
+    for fused in ("1", "0"):
+        monkeypatch.setenv("J3D_SOLVE_FUSED_CHECKS", fused)
+        du = j3d.FArray.from_numpy(u0)
+        r = j3d.poisson_solve(du, df, h, rtol=rtol, max_sweeps=S, check_every=1)
+        out.append((r.sweeps, r.converged, list(r.history), r.resid, du.to_numpy()))
+    a, b = out
+    assert a[0] == b[0] and a[1] == b[1] and a[3] == b[3]
+    assert a[2] == b[2], "residual histories differ"
+    assert np.array_equal(a[4], b[4])
+
+
 @pytest.mark.parametrize("n,inner,rtol,cap", [(24, 50, 1e-8, 100000), (13, 7, 1e-10, 100000),
                                               (16, 50, 1e-14, 120), (10, 1, 1e-3, 1000), (11, 2, 1e-9, 100000),
                                               (12, 3, 1e-9, 100000), (9, 4, 1e-9, 100000), (14, 6, 1e-12, 53),
