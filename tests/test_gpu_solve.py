@@ -88,12 +88,20 @@ def test_plain_early_exit_every_sweep_matches_oracle(n, rtol):
     assert np.array_equal(du.to_numpy(), uo)
 
 
-@pytest.mark.parametrize("n,S,rtol", [(64, 100, 0.0), (9, 1, 0.0), (9, 0, 0.0), (11, 1001, 0.0), (12, 100000, 1e-3),
-                                      (10, 7, 0.0), (13, 13, 0.0)])
-def test_fused_checks_equal_reduction_kernels(n, S, rtol, monkeypatch):
+@pytest.mark.parametrize("n,S,rtol,tune", [(64, 100, 0.0, None), (9, 1, 0.0, None), (9, 0, 0.0, None),
+                                           (11, 1001, 0.0, None), (12, 100000, 1e-3, None), (10, 7, 0.0, None),
+                                           (13, 13, 0.0, None),
+                                           # one to sixteen wavefronts per workgroup (the reducing workgroup
+                                           # stands in for 1024 / T threads), persistent grids, LDS variants
+                                           (40, 50, 0.0, (1, 4, 20, 1, 2, 1)), (40, 50, 0.0, (8, 2, 6, 0, 1, 2)),
+                                           (40, 50, 0.0, (2, 2, 21, 0, 1, 1)), (40, 50, 0.0, (4, 8, 20, 1, 0, 4)),
+                                           (33, 40, 0.0, (1, 16, 4, 0, 2, 1))])
+def test_fused_checks_equal_reduction_kernels(n, S, rtol, tune, monkeypatch):
     """The checks reduced inside the next pass give the same bits as the
     schedule with a reduction kernel per check: history, sweeps, iterate."""
-    say("fused checks", n, S, rtol)
+    say("fused checks", n, S, rtol, tune)
+    if tune is not None:
+        j3d.j3d_tune_set_single(j3d.F64, n, n, n, tune)
     h = 1.0 / (n + 1)
     u0 = synth.uniform_field(n, n, n, 7, 1, 0, 1)
     f = synth.manufactured_f(n, n, n, h) if rtol > 0 else synth.uniform_field(n, n, n, 7, 2, -1, 1)
