@@ -245,11 +245,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_n(const void* b, ui
 // Loads run one plane ahead: step k takes the loads issued one step
 // earlier (its one wait), issues the loads of plane k+1, stores the results
 // of step k-1 and computes plane k, so the loads it waits for had a whole
-// step of arithmetic to arrive, and the stores it issues are waited for only
-// at the start of the next step.  Every memory operation of a step is issued by every
-// lane on every step: loads come from in-bounds addresses (lanes and rows
-// past the interior are clamped onto the halo; the last step reloads its
-// own plane), stores of masked lanes (and the empty store of the first
+// step of arithmetic to arrive, and the stores it issues are waited for
+// only at the start of the next step.  Every lane issues every memory
+// operation of every step: loads come from in-bounds addresses (lanes and
+// rows past the interior are clamped onto the halo; the last step reloads
+// its own plane), stores of masked lanes (and the empty store of the first
 // step) are given an out-of-range offset and dropped by the hardware.  The
 // loop therefore has no branches around memory operations, which lets the
 // compiler count exactly which loads a wait needs.  Addresses are a scalar
