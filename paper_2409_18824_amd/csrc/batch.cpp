@@ -546,34 +546,55 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
   return rc;
 }
 
-// Time F_WRITE passes of every listed tile shape; return the fastest.
+// Time F_WRITE passes of every listed tile shape; return the fastest.  Each
+// shape gets a warm-up and the best of three launches; the (up to) six
+// fastest are then timed again, best of five, and the fastest of that
+// round wins, so that shapes within the launch-to-launch noise of each
+// other are not picked by one lucky launch.
 template <typename Launcher>
 int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, Launcher&& launch,
               float* best_ms = nullptr) {
   hipEvent_t e0, e1;
   J3D_HIP(hipEventCreate(&e0));
   J3D_HIP(hipEventCreate(&e1));
-  float bt = 1e30f;
   int rc = J3D_OK;
-  for (const TileCfg& c : list) {
-    rc = launch(c);
+  auto time_of = [&](const TileCfg& c, int reps, float* out) -> int {
+    J3D_TRY(launch(c));  // warm-up (also builds the tables)
     float ms_min = 1e30f;
-    for (int r = 0; r < 3 && rc == J3D_OK; ++r) {
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(J3D_EHIP, "event record"); break; }
-      rc = launch(c);
-      if (rc != J3D_OK) break;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        rc = fail(J3D_EHIP, "event sync");
-        break;
-      }
+    for (int r = 0; r < reps; ++r) {
+      if (hipEventRecord(e0, st) != hipSuccess) return fail(J3D_EHIP, "event record");
+      J3D_TRY(launch(c));
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return fail(J3D_EHIP, "event sync");
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
       ms_min = std::min(ms_min, ms);
     }
-    if (rc != J3D_OK) break;
-    if (ms_min < bt) {
-      bt = ms_min;
-      *best = c;
+    *out = ms_min;
+    return J3D_OK;
+  };
+  std::vector<std::pair<float, size_t>> first;
+  for (size_t q = 0; q < list.size() && rc == J3D_OK; ++q) {
+    float t = 0.f;
+    rc = time_of(list[q], 3, &t);
+    if (rc == J3D_OK) first.emplace_back(t, q);
+  }
+  float bt = 1e30f;
+  if (rc == J3D_OK && !first.empty()) {
+    std::stable_sort(first.begin(), first.end(),
+                     [](const std::pair<float, size_t>& a, const std::pair<float, size_t>& b) { return a.first < b.first; });
+    const size_t top = std::min<size_t>(6, first.size());
+    if (top == 1) {
+      bt = first[0].first;
+      *best = list[first[0].second];
+    }
+    for (size_t q = 0; q < top && top > 1 && rc == J3D_OK; ++q) {
+      float t = 0.f;
+      rc = time_of(list[first[q].second], 5, &t);
+      if (rc == J3D_OK && t < bt) {
+        bt = t;
+        *best = list[first[q].second];
+      }
     }
   }
   (void)hipEventDestroy(e0);
@@ -623,6 +644,19 @@ void release_batch_cache() {
   g_plans.clear();
 }
 
+// The batched tuners upload a tile table per shape; the launchers keep the
+// last shape they uploaded, so that only the warm-up launch of a shape pays
+// for the host-side table build and copy and the timed launches are bare.
+struct Prepared {
+  int kind = 0;  // passes of the uploaded table (0: none)
+  TileCfg c{};
+  int nt = 0;
+  bool holds(int k, const TileCfg& d) const {
+    return kind == k && c.rows == d.rows && c.planes == d.planes && c.variant == d.variant &&
+           c.persistent == d.persistent && c.order == d.order && c.cols == d.cols;
+  }
+};
+
 // Tunes the batched sweep for the batch's shape class (used by serve.cpp too).
 int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st);
 
@@ -631,7 +665,12 @@ int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st) 
   GridArgs* dtab = nullptr;
   double* parts = nullptr;
   size_t tab_cap = 0, part_cap = 0;
+  Prepared prep;
   auto launch = [&](const TileCfg& c) -> int {
+    if (prep.holds(1, c)) {
+      J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, c, dtab, n, prep.nt, parts, nullptr, st));
+      return J3D_OK;
+    }
     std::vector<GridArgs> tab[4];
     int nt = 0;
     build_tables(bf, c, tab, &nt);
@@ -651,6 +690,9 @@ int autotune_batch_fields(const BatchFields& bf, TileCfg* best, hipStream_t st) 
     }
     J3D_HIP(hipMemcpyAsync(dtab, tab[0].data(), (size_t)n * sizeof(GridArgs), hipMemcpyHostToDevice, st));
     J3D_HIP(hipStreamSynchronize(st));
+    prep.kind = 1;
+    prep.c = c;
+    prep.nt = nt;
     J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, c, dtab, n, nt, parts, nullptr, st));
     return J3D_OK;
   };
@@ -672,6 +714,7 @@ int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, bool keep_c2
   int part_cap = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&dtab), (size_t)n * sizeof(GridArgs), "tune table");
   if (rc != J3D_OK) return rc;
+  Prepared prep;
   auto upload = [&](const std::vector<GridArgs>& tab, int nt) -> int {
     if (nt > part_cap) {
       if (parts) (void)hipFree(parts);
@@ -684,19 +727,29 @@ int autotune_batch2_fields(const BatchFields& bf, const TileCfg& c, bool keep_c2
     return J3D_OK;
   };
   auto launch2 = [&](const TileCfg& c2) -> int {
-    std::vector<GridArgs> tab2[2];
-    int nt = 0;
-    build_tables2(bf, c2, tab2, &nt);
-    J3D_TRY(upload(tab2[0], nt));
-    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE, c2, dtab, n, nt, parts, nullptr, st));
+    if (!prep.holds(2, c2)) {
+      std::vector<GridArgs> tab2[2];
+      int nt = 0;
+      build_tables2(bf, c2, tab2, &nt);
+      J3D_TRY(upload(tab2[0], nt));
+      prep.kind = 2;
+      prep.c = c2;
+      prep.nt = nt;
+    }
+    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE, c2, dtab, n, prep.nt, parts, nullptr, st));
     return J3D_OK;
   };
   auto launch1 = [&](const TileCfg& c1) -> int {
-    std::vector<GridArgs> tab[4];
-    int nt = 0;
-    build_tables(bf, c1, tab, &nt);
-    J3D_TRY(upload(tab[0], nt));
-    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, c1, dtab, n, nt, parts, nullptr, st));
+    if (!prep.holds(1, c1)) {
+      std::vector<GridArgs> tab[4];
+      int nt = 0;
+      build_tables(bf, c1, tab, &nt);
+      J3D_TRY(upload(tab[0], nt));
+      prep.kind = 1;
+      prep.c = c1;
+      prep.nt = nt;
+    }
+    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, c1, dtab, n, prep.nt, parts, nullptr, st));
     return J3D_OK;
   };
   float t2 = 0.f, t1 = 0.f;
@@ -723,6 +776,7 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
   int part_cap = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&dtab), (size_t)n * sizeof(GridArgs), "tune table");
   if (rc != J3D_OK) return rc;
+  Prepared prep;
   auto upload = [&](const std::vector<GridArgs>& tab, int nt) -> int {
     if (nt > part_cap) {
       if (parts) (void)hipFree(parts);
@@ -735,27 +789,42 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
     return J3D_OK;
   };
   auto launch3 = [&](const TileCfg& k3) -> int {
-    std::vector<GridArgs> tab3[2];
-    int nt = 0;
-    build_tables3(bf, k3, tab3, &nt);
-    J3D_TRY(upload(tab3[0], nt));
-    J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE, k3, dtab, n, nt, parts, nullptr, st));
+    if (!prep.holds(3, k3)) {
+      std::vector<GridArgs> tab3[2];
+      int nt = 0;
+      build_tables3(bf, k3, tab3, &nt);
+      J3D_TRY(upload(tab3[0], nt));
+      prep.kind = 3;
+      prep.c = k3;
+      prep.nt = nt;
+    }
+    J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE, k3, dtab, n, prep.nt, parts, nullptr, st));
     return J3D_OK;
   };
   auto launch2 = [&](const TileCfg& k2) -> int {
-    std::vector<GridArgs> tab2[2];
-    int nt = 0;
-    build_tables2(bf, k2, tab2, &nt);
-    J3D_TRY(upload(tab2[0], nt));
-    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE, k2, dtab, n, nt, parts, nullptr, st));
+    if (!prep.holds(2, k2)) {
+      std::vector<GridArgs> tab2[2];
+      int nt = 0;
+      build_tables2(bf, k2, tab2, &nt);
+      J3D_TRY(upload(tab2[0], nt));
+      prep.kind = 2;
+      prep.c = k2;
+      prep.nt = nt;
+    }
+    J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE, k2, dtab, n, prep.nt, parts, nullptr, st));
     return J3D_OK;
   };
   auto launch1 = [&](const TileCfg& k1) -> int {
-    std::vector<GridArgs> tab[4];
-    int nt = 0;
-    build_tables(bf, k1, tab, &nt);
-    J3D_TRY(upload(tab[0], nt));
-    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, k1, dtab, n, nt, parts, nullptr, st));
+    if (!prep.holds(1, k1)) {
+      std::vector<GridArgs> tab[4];
+      int nt = 0;
+      build_tables(bf, k1, tab, &nt);
+      J3D_TRY(upload(tab[0], nt));
+      prep.kind = 1;
+      prep.c = k1;
+      prep.nt = nt;
+    }
+    J3D_HIP(launch_pass_batch(J3D_F64, F_WRITE, k1, dtab, n, prep.nt, parts, nullptr, st));
     return J3D_OK;
   };
   float t3 = 0.f, tother = 0.f;

@@ -114,6 +114,22 @@ __device__ __forceinline__ void sweep3_tile(const GridArgs& g, int t, double* __
   const T h2 = h2_of<T>(g);
   const int ztop = g.nz + 1;
 
+  // A wavefront whose rows all lie past the boundary row y = ny + 1 (in a
+  // grid's last block row when H does not divide ny) feeds no output: the
+  // wavefront below it ends on the boundary row or beyond, and those rows
+  // keep their values whatever their neighbours, so what this wavefront
+  // would leave in the shared edge rows is never selected.  It only takes
+  // its part in the block's barriers (the set-up one, one per plane step,
+  // the residual's and the last) and adds zero to the residual.  Wavefront
+  // 0 is never such a wavefront (its first row is ty*H - 1 <= ny - 2).
+  if (ty * H - 1 + wy * RY >= g.ny + 2) {
+    __syncthreads();
+    for (int k = k0 - 2; k <= k1 + 1; ++k) __syncthreads();
+    if (RES_ANY != 0) (void)block_sum<BY>(0.0, sm.red);
+    __syncthreads();
+    return;
+  }
+
   // byte offsets within a plane of the thread's rows
   uint32_t ou[RY], of[RY], oo[RY];
   bool inner2[RY], inner3[RY], col_in[RY];

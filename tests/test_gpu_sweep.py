@@ -101,7 +101,7 @@ def test_sweep2_equals_two_sweeps(shape, tune):
 
 
 TUNES3 = [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (4, 7, 6, 0, 1, 1), (8, 64, 20, 0, 0, 1),
-          (2, 3, 20, 0, 2, 1), (4, 48, 20, 0, 1, 1), (4, 24, 20, 0, 2, 1)]
+          (2, 3, 20, 0, 2, 1), (4, 48, 20, 0, 1, 1), (4, 24, 20, 0, 2, 1), (16, 24, 6, 0, 1, 1)]
 SHAPES3 = [(1, 1, 1), (3, 4, 5), (58, 6, 9), (59, 12, 10), (57, 13, 8), (117, 30, 17), (17, 45, 64), (200, 28, 3)]
 
 
@@ -127,7 +127,8 @@ def test_sweep3_equals_three_sweeps(shape, tune):
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 5), (59, 12, 10), (117, 30, 17), (17, 45, 64), (200, 28, 3)])
-@pytest.mark.parametrize("tune", [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (2, 3, 20, 0, 2, 1)])
+@pytest.mark.parametrize("tune", [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (2, 3, 20, 0, 2, 1),
+                                  (16, 24, 6, 0, 0, 1)])
 @pytest.mark.parametrize("after", [1, 2])
 def test_sweep3_residual_of_intermediate_iterates(shape, tune, after):
     """The residual fused at stage 2 or 3 of the pass is that of J(u) or
