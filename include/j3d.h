@@ -406,7 +406,12 @@ int j3d_tune_get(int32_t index, j3d_tune* out);
  * any resid_every: each residual is fused into the pass that forms its
  * iterate, at that stage of the pass (a shorter pass covers the rest, and
  * one pass is split when needed to keep the u_a/u_b placement above);
- * J3D_BATCH_TRIPLES=0 or =1 forces this off or on.
+ * J3D_BATCH_TRIPLES=0 or =1 forces this off or on.  The three-sweep shape
+ * is timed on the batch among the jacobi3d_sweep3 shapes in the XCD-blocked
+ * tile order (order 0) and in a balanced order (order 3, batches only: the
+ * tile list cut into one run of about equal work per XCD, each run longest
+ * tile first); J3D_BATCH_TILE3="rows,planes,variant,order" fixes it
+ * (J3D_EINVAL for a shape the three-sweep pass does not have).
  */
 int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsweeps,
                          int32_t resid_every, double* resid_out, const j3d_tune* tune,

@@ -216,6 +216,50 @@ void build_tables3(const BatchFields& bf, const TileCfg& c3, std::vector<GridArg
   *ntiles = tile0;
 }
 
+// Dispatch slots of the balanced tile order of the batched three-sweep pass
+// (kOrderSlots).  The flat tile list is cut into 8 contiguous runs of about
+// equal work, run x for XCD x (the hardware hands workgroup b to XCD b mod
+// 8, so each XCD's L2 keeps the halo rows its neighbouring tiles share, as
+// in order 0, which cuts by tile count), and each run is taken longest
+// tile first (a stable sort: tiles of equal length keep their neighbours),
+// so that the short tiles of grids' last z-slabs fill the end of the
+// launch.  A tile's work is counted as its planes plus 8 (the pipeline's
+// fill and drain and the tile's set-up).  slots[8 i + x] is the i-th tile
+// of run x, or tile -1 past the run's end.
+void build_slots3(const std::vector<GridArgs>& tab, int ntiles, std::vector<TileSlot>* slots) {
+  std::vector<int> cost((size_t)ntiles), owner((size_t)ntiles);
+  long long total = 0;
+  for (int g = 0; g < (int)tab.size(); ++g) {
+    const GridArgs& a = tab[g];
+    const int slab = a.tiles_x * a.tiles_y;
+    for (int tz = 0; tz < a.tiles_z; ++tz) {
+      const int k0 = 1 + tz * a.planes;
+      const int len = std::min(k0 + a.planes, a.nz + 1) - k0 + 8;
+      for (int q = 0; q < slab; ++q) {
+        cost[(size_t)a.tile0 + (size_t)tz * slab + q] = len;
+        owner[(size_t)a.tile0 + (size_t)tz * slab + q] = g;
+      }
+      total += (long long)len * slab;
+    }
+  }
+  std::vector<int> run[8];
+  long long acc = 0;
+  int x = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    while (x < 7 && acc * 8 >= total * (x + 1)) ++x;  // run x holds its share
+    run[x].push_back(t);
+    acc += cost[t];
+  }
+  size_t longest = 0;
+  for (std::vector<int>& r : run) {
+    std::stable_sort(r.begin(), r.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    longest = std::max(longest, r.size());
+  }
+  slots->assign(8 * longest, TileSlot{-1, 0});
+  for (int q = 0; q < 8; ++q)
+    for (size_t i = 0; i < run[q].size(); ++i) (*slots)[8 * i + q] = TileSlot{run[q][i], owner[run[q][i]]};
+}
+
 // The passes of a call with three-sweep passes: (sweeps in the pass, stage
 // of the residual it carries or -1).  Passes run straight through the call
 // (a batch has no early exit); the pass through which iterate q*E passes
@@ -285,6 +329,8 @@ struct Plan {
   TileCfg c2{};             // tile shape of the two-sweep passes
   TileCfg c3{};             // tile shape of the three-sweep passes
   GridArgs* tab = nullptr;  // device: 4 * ngrids one-sweep, 2 * ngrids two-sweep, 2 * ngrids three-sweep entries
+  TileSlot* slots3 = nullptr;  // device: dispatch slots of the three-sweep passes (c3.order == kOrderSlots)
+  int nslots3 = 0;
   double* partials = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -301,6 +347,7 @@ void free_plan(Plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->tab) (void)hipFree(p->tab);
+  if (p->slots3) (void)hipFree(p->slots3);
   if (p->partials) (void)hipFree(p->partials);
   delete p;
 }
@@ -353,7 +400,8 @@ int enqueue_batch(const Plan& p, const TileCfg& c, int nsweeps, int every, doubl
       if (ps.m == 3) {
         t = p.tab + (size_t)(6 + buf) * n;
         const unsigned rf = !check ? 0u : ps.stage == 0 ? F_RES : ps.stage == 1 ? F_RES1 : F_RES2;
-        J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE | rf, p.c3, t, n, p.ntiles3, p.partials, nullptr, st));
+        J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE | rf, p.c3, t, n, p.ntiles3, p.partials, nullptr, st, p.slots3,
+                                    p.nslots3));
       } else if (ps.m == 2) {
         t = p.tab + (size_t)(4 + buf) * n;
         J3D_HIP(launch_sweep2_batch(J3D_F64, F_WRITE | (check ? F_RES : 0u), p.c2, t, n, p.ntiles2,
@@ -424,6 +472,22 @@ int make_plan(const std::string& key, const BatchFields& bf, const TileCfg& c, b
   if (e != hipSuccess) {
     free_plan(p);
     return hip_fail(e, "upload batch table");
+  }
+  if (triples && c3.order == kOrderSlots) {
+    std::vector<TileSlot> sl;
+    build_slots3(tab3[0], p->ntiles3, &sl);
+    rc = dev_alloc(&mem, sl.size() * sizeof(TileSlot), "batch slots");
+    if (rc != J3D_OK) {
+      free_plan(p);
+      return rc;
+    }
+    p->slots3 = static_cast<TileSlot*>(mem);
+    p->nslots3 = (int)sl.size();
+    e = hipMemcpy(p->slots3, sl.data(), sl.size() * sizeof(TileSlot), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "upload batch slots");
+    }
   }
   hipStream_t cs;
   rc = capture_stream(dev, &cs);
@@ -547,8 +611,8 @@ int time_candidates(hipStream_t st, TileCfg* best, Launcher&& launch) {
 }
 
 // Time F_WRITE passes of every listed tile shape; return the fastest.  Each
-// shape gets a warm-up and the best of three launches; the (up to) six
-// fastest are then timed again, best of five, and the fastest of that
+// shape gets a warm-up and the best of three launches; the (up to) eight
+// fastest are then timed again, best of seven, and the fastest of that
 // round wins, so that shapes within the launch-to-launch noise of each
 // other are not picked by one lucky launch.
 template <typename Launcher>
@@ -583,14 +647,14 @@ int time_list(hipStream_t st, TileCfg* best, const std::vector<TileCfg>& list, L
   if (rc == J3D_OK && !first.empty()) {
     std::stable_sort(first.begin(), first.end(),
                      [](const std::pair<float, size_t>& a, const std::pair<float, size_t>& b) { return a.first < b.first; });
-    const size_t top = std::min<size_t>(6, first.size());
+    const size_t top = std::min<size_t>(8, first.size());
     if (top == 1) {
       bt = first[0].first;
       *best = list[first[0].second];
     }
     for (size_t q = 0; q < top && top > 1 && rc == J3D_OK; ++q) {
       float t = 0.f;
-      rc = time_of(list[first[q].second], 5, &t);
+      rc = time_of(list[first[q].second], 7, &t);
       if (rc == J3D_OK && t < bt) {
         bt = t;
         *best = list[first[q].second];
@@ -788,17 +852,36 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
     J3D_HIP(hipStreamSynchronize(st));
     return J3D_OK;
   };
+  TileSlot* dslots = nullptr;
+  size_t slot_cap = 0;
+  int nslots = 0;
   auto launch3 = [&](const TileCfg& k3) -> int {
     if (!prep.holds(3, k3)) {
       std::vector<GridArgs> tab3[2];
       int nt = 0;
       build_tables3(bf, k3, tab3, &nt);
       J3D_TRY(upload(tab3[0], nt));
+      nslots = 0;
+      if (k3.order == kOrderSlots) {
+        std::vector<TileSlot> sl;
+        build_slots3(tab3[0], nt, &sl);
+        if (sl.size() > slot_cap) {
+          if (dslots) (void)hipFree(dslots);
+          dslots = nullptr;
+          slot_cap = 0;
+          J3D_TRY(dev_alloc(reinterpret_cast<void**>(&dslots), sl.size() * sizeof(TileSlot), "tune slots"));
+          slot_cap = sl.size();
+        }
+        J3D_HIP(hipMemcpyAsync(dslots, sl.data(), sl.size() * sizeof(TileSlot), hipMemcpyHostToDevice, st));
+        J3D_HIP(hipStreamSynchronize(st));
+        nslots = (int)sl.size();
+      }
       prep.kind = 3;
       prep.c = k3;
       prep.nt = nt;
     }
-    J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE, k3, dtab, n, prep.nt, parts, nullptr, st));
+    J3D_HIP(launch_sweep3_batch(J3D_F64, F_WRITE, k3, dtab, n, prep.nt, parts, nullptr, st,
+                                k3.order == kOrderSlots ? dslots : nullptr, nslots));
     return J3D_OK;
   };
   auto launch2 = [&](const TileCfg& k2) -> int {
@@ -828,7 +911,19 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
     return J3D_OK;
   };
   float t3 = 0.f, tother = 0.f;
-  const std::vector<TileCfg> cand3 = keep_c3 ? std::vector<TileCfg>{*best3} : sweep3_candidates(J3D_F64);
+  std::vector<TileCfg> cand3;
+  if (keep_c3) {
+    cand3.push_back(*best3);
+  } else {
+    // every single-grid shape in the XCD-blocked order and in the balanced
+    // slot order (orders 1 and 2, which give up the per-XCD locality, lose
+    // on batches)
+    for (const TileCfg& k : sweep3_candidates(J3D_F64)) {
+      if (k.order != 0) continue;
+      cand3.push_back(k);
+      cand3.push_back(TileCfg{k.rows, k.planes, k.variant, k.persistent, kOrderSlots, k.cols});
+    }
+  }
   rc = time_list(st, best3, cand3, launch3, &t3);
   TileCfg other = pairs ? c2 : c;
   if (rc == J3D_OK)
@@ -837,6 +932,7 @@ int autotune_batch3_fields(const BatchFields& bf, const TileCfg& c, bool pairs, 
   (void)hipStreamSynchronize(st);
   (void)hipFree(dtab);
   if (parts) (void)hipFree(parts);
+  if (dslots) (void)hipFree(dslots);
   *use = t3 / 3.f < tother / (pairs ? 2.f : 1.f);
   return rc;
 }
@@ -900,7 +996,25 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsw
   // three-sweep passes when that kernel has it.
   bool triples = false;
   TileCfg c3 = default_cfg3(J3D_F64, 64, 64, 64);
-  if (tune != nullptr && tile3_cfg_supported(J3D_F64, c)) c3 = c;
+  bool keep_c3 = false;
+  if (tune != nullptr && tile3_cfg_supported(J3D_F64, c)) {
+    c3 = c;
+    keep_c3 = true;
+  }
+  // J3D_BATCH_TILE3="rows,planes,variant,order" fixes the three-sweep shape
+  // (order kOrderSlots: the balanced slot order); the choice of pass kind is
+  // still timed unless J3D_BATCH_TRIPLES forces it.
+  const char* env3 = getenv("J3D_BATCH_TILE3");
+  if (env3 != nullptr) {
+    TileCfg t{0, 0, 0, 0, 0, 1};
+    if (sscanf(env3, "%d,%d,%d,%d", &t.rows, &t.planes, &t.variant, &t.order) != 4)
+      return fail(J3D_EINVAL, "J3D_BATCH_TILE3: expected rows,planes,variant,order");
+    TileCfg chk = t;
+    if (chk.order == kOrderSlots) chk.order = 0;
+    if (!tile3_cfg_supported(J3D_F64, chk)) return fail(J3D_EINVAL, "J3D_BATCH_TILE3: unsupported shape");
+    c3 = t;
+    keep_c3 = true;
+  }
   const char* force3 = getenv("J3D_BATCH_TRIPLES");
   int mode3 = (force3 && *force3 == '0') ? 0 : (force3 && *force3 == '1') ? 1 : -1;
   // the three-sweep pass needs every plane below 4 GiB
@@ -911,10 +1025,11 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsw
       triples = true;
     } else {
       char sig[64];
-      snprintf(sig, sizeof sig, ":x3:%d:%d", tune != nullptr ? 1 : 0, pairs ? 1 : 0);
+      snprintf(sig, sizeof sig, ":x3:%d:%d:%d,%d,%d,%d", keep_c3 ? 1 : 0, pairs ? 1 : 0, keep_c3 ? c3.rows : 0,
+               keep_c3 ? c3.planes : 0, keep_c3 ? c3.variant : 0, keep_c3 ? c3.order : 0);
       const std::string k3 = batch_key(ngrids, bf.a.data()) + sig;
       if (!pair_lookup(k3, &c3, &triples)) {
-        J3D_TRY(autotune_batch3_fields(bf, c, pairs, c2, tune != nullptr, &c3, &triples, st));
+        J3D_TRY(autotune_batch3_fields(bf, c, pairs, c2, keep_c3, &c3, &triples, st));
         pair_store(k3, c3, triples);
       }
       if (mode3 == 1) triples = true;

@@ -47,6 +47,17 @@ enum : unsigned {
   F_RES2 = 128u,  // three-sweep pass: sum of r^2 of the iterate after its second sweep (FP64)
 };
 
+// One dispatch slot of a batched pass launched from a slot list: the tile
+// (in the batch's flat tile numbering, -1 for none) and the grid owning it.
+struct alignas(8) TileSlot {
+  int tile;
+  int grid;
+};
+
+// Tile order of batched three-sweep passes launched from a slot list (the
+// slots carry the order; see build_slots3).
+constexpr int kOrderSlots = 3;
+
 struct TileCfg {
   int rows;       // wavefronts per workgroup
   int planes;     // z-planes per tile
@@ -91,8 +102,11 @@ hipError_t launch_sweep3_one(int dtype, unsigned flags, const TileCfg& c, const 
 // The three-sweep pass over a table of grids: FP64 with F_WRITE and at
 // most one of F_RES, F_RES1, F_RES2; FP32 with the flags of the correction
 // cycles (F_WRITE or F_LAST, each with or without F_FIRST).
+// With slots, workgroup b runs tile slots[b].tile of grid slots[b].grid
+// (nslots workgroups; tile -1: none) and c.order may be kOrderSlots.
 hipError_t launch_sweep3_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
-                               int ntiles, double* partials, const int* done, hipStream_t st);
+                               int ntiles, double* partials, const int* done, hipStream_t st,
+                               const TileSlot* slots = nullptr, int nslots = 0);
 
 // Number of resident workgroups used for persistent launches.
 int persistent_grid(const TileCfg& c);

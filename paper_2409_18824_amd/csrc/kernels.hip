@@ -378,11 +378,18 @@ hipError_t launch_sweep3_one(int dtype, unsigned flags, const TileCfg& c, const 
 }
 
 hipError_t launch_sweep3_batch(int dtype, unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
-                               int ntiles, double* partials, const int* done, hipStream_t st) {
-  if (!tile3_cfg_supported(dtype, c)) return hipErrorInvalidValue;
+                               int ntiles, double* partials, const int* done, hipStream_t st,
+                               const TileSlot* slots, int nslots) {
+  TileCfg k = c;
+  if (k.order == kOrderSlots) {
+    if (slots == nullptr) return hipErrorInvalidValue;
+    k.order = 0;  // the slot list replaces the order
+  }
+  if (!tile3_cfg_supported(dtype, k) || (slots != nullptr && nslots < 0)) return hipErrorInvalidValue;
   if (dtype == J3D_F64)
-    return sweep_detail::dispatch_sweep3_batch_f64(flags, c, table, ngrids, ntiles, partials, done, st);
-  return sweep_detail::dispatch_sweep3_batch_f32(flags, c, table, ngrids, ntiles, partials, done, st);
+    return sweep_detail::dispatch_sweep3_batch_f64(flags, k, table, ngrids, ntiles, slots, nslots, partials, done,
+                                                   st);
+  return sweep_detail::dispatch_sweep3_batch_f32(flags, k, table, ngrids, ntiles, slots, nslots, partials, done, st);
 }
 
 hipError_t launch_sweep2_one(int dtype, unsigned flags, const TileCfg& c, const GridArgs& g,

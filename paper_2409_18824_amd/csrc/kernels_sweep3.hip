@@ -18,15 +18,16 @@ hipError_t dispatch_sweep3_f64(unsigned flags, const TileCfg& c, const GridArgs&
 }
 
 hipError_t dispatch_sweep3_batch_f64(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
-                                     int ntiles, double* partials, const int* done, hipStream_t st) {
+                                     int ntiles, const TileSlot* slots, int nslots, double* partials,
+                                     const int* done, hipStream_t st) {
   switch (flags) {
-    case F_WRITE: return by_shape3_batch<double, F_WRITE>(c, table, ngrids, ntiles, partials, done, st);
+    case F_WRITE: return by_shape3_batch<double, F_WRITE>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     case F_WRITE | F_RES:
-      return by_shape3_batch<double, F_WRITE | F_RES>(c, table, ngrids, ntiles, partials, done, st);
+      return by_shape3_batch<double, F_WRITE | F_RES>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     case F_WRITE | F_RES1:
-      return by_shape3_batch<double, F_WRITE | F_RES1>(c, table, ngrids, ntiles, partials, done, st);
+      return by_shape3_batch<double, F_WRITE | F_RES1>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     case F_WRITE | F_RES2:
-      return by_shape3_batch<double, F_WRITE | F_RES2>(c, table, ngrids, ntiles, partials, done, st);
+      return by_shape3_batch<double, F_WRITE | F_RES2>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -19,14 +19,15 @@ hipError_t dispatch_sweep3_f32(unsigned flags, const TileCfg& c, const GridArgs&
 }
 
 hipError_t dispatch_sweep3_batch_f32(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
-                                     int ntiles, double* partials, const int* done, hipStream_t st) {
+                                     int ntiles, const TileSlot* slots, int nslots, double* partials,
+                                     const int* done, hipStream_t st) {
   switch (flags) {
-    case F_WRITE: return by_shape3_batch<float, F_WRITE>(c, table, ngrids, ntiles, partials, done, st);
+    case F_WRITE: return by_shape3_batch<float, F_WRITE>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     case F_WRITE | F_FIRST:
-      return by_shape3_batch<float, F_WRITE | F_FIRST>(c, table, ngrids, ntiles, partials, done, st);
-    case F_LAST: return by_shape3_batch<float, F_LAST>(c, table, ngrids, ntiles, partials, done, st);
+      return by_shape3_batch<float, F_WRITE | F_FIRST>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case F_LAST: return by_shape3_batch<float, F_LAST>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     case F_LAST | F_FIRST:
-      return by_shape3_batch<float, F_LAST | F_FIRST>(c, table, ngrids, ntiles, partials, done, st);
+      return by_shape3_batch<float, F_LAST | F_FIRST>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     default: return hipErrorInvalidValue;
   }
 }

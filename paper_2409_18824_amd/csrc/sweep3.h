@@ -403,8 +403,16 @@ __global__ void __launch_bounds__(WAVE * BY)
 template <typename T, int BY, int VAR, unsigned FL>
 __global__ void __launch_bounds__(WAVE * BY)
     k_sweep3_batch(const GridArgs* __restrict__ table, int ngrids, int ntiles, double* __restrict__ partials,
-                   const int* __restrict__ done, int order, int chunk) {
+                   const int* __restrict__ done, int order, int chunk, const TileSlot* __restrict__ slots) {
   __shared__ Smem3<T, BY> sm;
+  if (slots != nullptr) {
+    // one workgroup per slot: the tile and its grid come with the slot
+    const TileSlot s = slots[blockIdx.x];
+    if (s.tile < 0 || (done != nullptr && done[table[s.grid].id] != 0)) return;
+    const GridArgs g = table[s.grid];
+    sweep3_tile<T, BY, VAR, FL>(g, s.tile - g.tile0, partials, sm);
+    return;
+  }
   const int nv = order == 0 ? ntiles : virtual_tiles(ntiles, order, chunk);
   const int first = order == 0 ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   for (int vb = first; vb < nv; vb += gridDim.x) {
@@ -445,31 +453,31 @@ hipError_t go3(const GridArgs& g, double* partials, const int* done, hipStream_t
 // Batched launch: one workgroup per tile of the flat list (order 0 remaps
 // blocks to XCDs, order 2 chunks the list per XCD in runs of kBatchChunk).
 template <typename T, int BY, int VAR, unsigned FL>
-hipError_t go3_batch(const TileCfg& c, const GridArgs* table, int ngrids, int ntiles, double* partials,
-                     const int* done, hipStream_t st) {
+hipError_t go3_batch(const TileCfg& c, const GridArgs* table, int ngrids, int ntiles, const TileSlot* slots,
+                     int nslots, double* partials, const int* done, hipStream_t st) {
   if constexpr (!shape3_instantiated(BY, VAR)) {
     return hipErrorInvalidValue;
   } else {
     const int chunk = kBatchChunk;
-    const int grid = virtual_tiles(ntiles, c.order, chunk);
+    const int grid = slots != nullptr ? nslots : virtual_tiles(ntiles, c.order, chunk);
     if (grid <= 0 || ngrids <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep3_batch<T, BY, VAR, FL>), dim3(grid), dim3(WAVE, BY), 0, st, table, ngrids,
-                       ntiles, partials, done, c.order, chunk);
+                       ntiles, partials, done, c.order, chunk, slots);
     return hipGetLastError();
   }
 }
 
 template <typename T, unsigned FL>
-hipError_t by_shape3_batch(const TileCfg& c, const GridArgs* table, int ngrids, int ntiles, double* partials,
-                           const int* done, hipStream_t st) {
+hipError_t by_shape3_batch(const TileCfg& c, const GridArgs* table, int ngrids, int ntiles, const TileSlot* slots,
+                           int nslots, double* partials, const int* done, hipStream_t st) {
   switch (c.rows * 100 + c.variant) {
-    case 206: return go3_batch<T, 2, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
-    case 220: return go3_batch<T, 2, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
-    case 406: return go3_batch<T, 4, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
-    case 420: return go3_batch<T, 4, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
-    case 806: return go3_batch<T, 8, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
-    case 820: return go3_batch<T, 8, 20, FL>(c, table, ngrids, ntiles, partials, done, st);
-    case 1606: return go3_batch<T, 16, 6, FL>(c, table, ngrids, ntiles, partials, done, st);
+    case 206: return go3_batch<T, 2, 6, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case 220: return go3_batch<T, 2, 20, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case 406: return go3_batch<T, 4, 6, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case 420: return go3_batch<T, 4, 20, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case 806: return go3_batch<T, 8, 6, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case 820: return go3_batch<T, 8, 20, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
+    case 1606: return go3_batch<T, 16, 6, FL>(c, table, ngrids, ntiles, slots, nslots, partials, done, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -493,9 +501,11 @@ hipError_t dispatch_sweep3_f64(unsigned flags, const TileCfg& c, const GridArgs&
 hipError_t dispatch_sweep3_f32(unsigned flags, const TileCfg& c, const GridArgs& g, double* partials,
                                const int* done, hipStream_t st);
 hipError_t dispatch_sweep3_batch_f64(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
-                                     int ntiles, double* partials, const int* done, hipStream_t st);
+                                     int ntiles, const TileSlot* slots, int nslots, double* partials,
+                                     const int* done, hipStream_t st);
 hipError_t dispatch_sweep3_batch_f32(unsigned flags, const TileCfg& c, const GridArgs* table, int ngrids,
-                                     int ntiles, double* partials, const int* done, hipStream_t st);
+                                     int ntiles, const TileSlot* slots, int nslots, double* partials,
+                                     const int* done, hipStream_t st);
 
 }  // namespace sweep_detail
 }  // namespace j3d

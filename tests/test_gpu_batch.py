@@ -53,6 +53,45 @@ def test_batch_three_sweep_passes_match_oracle(monkeypatch, tune, nsweeps, every
     check_batch_against_oracle(tune, nsweeps, every)
 
 
+@pytest.mark.parametrize("nsweeps,every", [(20, 4), (13, 5), (7, 3), (11, 1)])
+@pytest.mark.parametrize("tile3", ["16,24,6,3", "8,16,20,3", "2,8,20,3", "4,64,6,3", "16,96,6,3"])
+def test_batch_three_sweep_slot_order_matches_oracle(monkeypatch, tile3, nsweeps, every):
+    """Three-sweep passes launched from the balanced slot list (tiles cut into
+    eight runs of equal work, each longest tile first): every tile runs once,
+    iterates bit-exact, every residual of the cadence."""
+    monkeypatch.setenv("J3D_BATCH_TRIPLES", "1")
+    monkeypatch.setenv("J3D_BATCH_TILE3", tile3)
+    check_batch_against_oracle(None, nsweeps, every)
+
+
+@pytest.mark.parametrize("shape", ["16,24,6", "8,16,20"])
+def test_batch_slot_order_equals_blocked_order_bitwise(monkeypatch, shape):
+    """The slot order changes only which workgroup runs a tile: iterates and
+    residuals (same per-tile partials, same reduction) are bitwise those of
+    the XCD-blocked order."""
+    monkeypatch.setenv("J3D_BATCH_TRIPLES", "1")
+    results = []
+    for order in ("0", "3"):
+        monkeypatch.setenv("J3D_BATCH_TILE3", shape + "," + order)
+        say("batch slots", shape, order)
+        grids, _ = make_batch(SHAPES)
+        out = torch.zeros((len(grids), 5), dtype=torch.float64, device="cuda")
+        j3d.jacobi3d_sweep_batch(grids, 20, 5, out)
+        torch.cuda.synchronize()
+        results.append(([ua.to_numpy() for ua, _, _, _ in grids], out.cpu().numpy()))
+    (u0, r0), (u3, r3) = results
+    assert all(np.array_equal(a, b) for a, b in zip(u0, u3))
+    assert np.array_equal(r0, r3)
+
+
+def test_batch_tile3_override_rejects_bad_shapes(monkeypatch):
+    grids, _ = make_batch(SHAPES[:2])
+    for bad in ("3,24,6,0", "16,24,6,4", "16,24", "8,0,20,3"):
+        monkeypatch.setenv("J3D_BATCH_TILE3", bad)
+        with pytest.raises(RuntimeError, match="J3D_BATCH_TILE3"):
+            j3d.jacobi3d_sweep_batch(grids, 6, 3, None)
+
+
 def check_batch_against_oracle(tune, nsweeps, every):
     say("batch", tune, nsweeps, every)
     grids, host = make_batch(SHAPES)
