@@ -30,6 +30,9 @@ Other workloads (their own JSON line; not the default):
                      to a relative residual of 1e-8 (time to solution);
   --workload batch   256 independent grids, each axis uniform in {32..256},
                      200 sweeps with residuals every 10, one graph launch;
+                     the line names the pass kind and tile shape the call ran
+                     and, for three-sweep passes, carries that kernel's
+                     roofline (graphs of ten passes without residuals);
   --workload serve   a Poisson request stream (200/s, n log-uniform in
                      [32, 384], tolerance 1e-6 or 1e-8, 5000-sweep cap) through
                      the continuous-batching server: solves/s, p50/p99 latency;
@@ -464,6 +467,32 @@ def run_batch(args):
     glups = pts * nsw * args.steps / el / 1e9
     r = out.cpu().numpy()
     assert np.all(np.isfinite(r)) and np.all(r[:, -1] < r[:, 0])
+    # the pass kind and shape the timed calls ran; with three-sweep passes,
+    # their kernel alone: a call of 30 sweeps without residuals is ten
+    # three-sweep batched passes back to back in one graph (timed with events
+    # on the stream the graph runs on; per pass: the call's time / 10)
+    kind, shape = j3d.j3d_batch_last_plan()
+    roof = None
+    if kind == 3:
+        j3d.jacobi3d_sweep_batch(grids, 30, every, None)
+        torch.cuda.synchronize()
+        assert j3d.j3d_batch_last_plan() == (kind, shape)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(6)]
+        for a0, a1 in evs:
+            a0.record()
+            j3d.jacobi3d_sweep_batch(grids, 30, every, None)
+            a1.record()
+        torch.cuda.synchronize()
+        us = sorted(a0.elapsed_time(a1) * 1e3 / 10 for a0, a1 in evs)
+        avg = sum(us) / len(us)
+        alg = BYTES_PER_LUP_F64 * pts
+        gbs = alg / avg / 1e3
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sweep3_batch<F_WRITE> (three FP64 sweeps per pass over all grids)",
+                "avg_launch_us": round(avg, 1), "median_launch_us": round(us[len(us) // 2], 1),
+                "launches": 10 * len(us), "bytes_per_launch_algorithmic": int(alg),
+                "timing": "6 graphs of 10 passes; median over the graphs"}
     # one more call from u0 = 0, sampled against the oracle: the smallest and
     # the largest grid, the first and last of the tile list, four seeded others
     import oracle
@@ -495,7 +524,10 @@ def run_batch(args):
     out_d = _base(args, "GLUP/s (batched uneven grids)", round(glups, 3), "GLUP/s", round(el / args.steps * 1e3, 3),
                   "f64", "batch-256-grids-32to256-200sweeps-resid10",
                   extra={"grids": len(grids), "points": pts, "tile": tune,
+                         "sweeps_per_pass": kind, "pass_tile": list(shape),
                          "single_sweep_equivalent_gbs": round(glups * 24.0, 1)})
+    if roof is not None:
+        out_d["roofline"] = roof
     out_d["oracle_error"] = {"grids_checked": sorted(pick), "max_rel_diff_u": err_u, "max_rel_diff_resid": err_r,
                              "reference": "oracle.solve_plain of each sampled grid alone, 200 sweeps, residual every 10"}
     model, nproc = host_cpu()

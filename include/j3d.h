@@ -422,6 +422,14 @@ int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsweeps,
  * Blocks until done. */
 int j3d_autotune(int32_t ngrids, j3d_grid* grids, j3d_tune* best, void* stream);
 
+/* The plan of this thread's most recent jacobi3d_sweep_batch call that
+ * launched work: *sweeps_per_pass = 3, 2 or 1 for three-, two- or one-sweep
+ * passes (the kind its passes of full length had), *shape = the tile shape
+ * of those passes (order 3: the balanced slot order of three-sweep passes).
+ * Both written by the call (intent(out)).  Host-only; J3D_EINVAL for a null
+ * pointer, J3D_ESTATE when this thread has made no such call. */
+int j3d_batch_last_plan(int32_t* sweeps_per_pass, j3d_tune* shape);
+
 /* Kernel kinds for the single-grid tuning calls: J3D_F64 and J3D_F32 name
  * the one-sweep passes of that element type, J3D_KIND_F64X2 and
  * J3D_KIND_F32X2 the two-sweep passes of jacobi3d_sweep2 (the FP32 one also

@@ -339,6 +339,13 @@ struct Plan {
 
 std::mutex g_plan_mu;
 std::vector<Plan*> g_plans;
+// The pass kind (sweeps per pass, 0: none yet) and tile shape of this
+// thread's most recent jacobi3d_sweep_batch call.
+struct LastPlan {
+  int kind = 0;
+  TileCfg c{};
+};
+thread_local LastPlan g_last_plan;
 uint64_t g_stamp = 0;
 constexpr size_t kMaxPlans = 16;
 hipStream_t g_cap_stream[64] = {};
@@ -1071,6 +1078,17 @@ extern "C" int jacobi3d_sweep_batch(int32_t ngrids, j3d_grid* grids, int32_t nsw
     plan->stamp = ++g_stamp;
   }
   J3D_HIP(hipGraphLaunch(plan->exec, st));
+  g_last_plan.kind = triples ? 3 : pairs ? 2 : 1;
+  g_last_plan.c = triples ? c3 : pairs ? c2 : c;
+  return J3D_OK;
+}
+
+extern "C" int j3d_batch_last_plan(int32_t* sweeps_per_pass, j3d_tune* shape) {
+  if (sweeps_per_pass == nullptr || shape == nullptr) return fail(J3D_EINVAL, "null pointer");
+  if (g_last_plan.kind == 0) return fail(J3D_ESTATE, "this thread has made no jacobi3d_sweep_batch call");
+  *sweeps_per_pass = g_last_plan.kind;
+  const TileCfg& c = g_last_plan.c;
+  *shape = j3d_tune{c.rows, c.planes, c.variant, c.persistent, c.order, c.cols};
   return J3D_OK;
 }
 

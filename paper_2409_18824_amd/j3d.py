@@ -122,6 +122,7 @@ _SIGS = {
     "j3d_tune_get": ([_I32, _P(Tune)], ctypes.c_int),
     "jacobi3d_sweep_batch": ([_I32, _P(Grid), _I32, _I32, _V, _P(Tune), _V], ctypes.c_int),
     "j3d_autotune": ([_I32, _P(Grid), _P(Tune), _V], ctypes.c_int),
+    "j3d_batch_last_plan": ([_P(_I32), _P(Tune)], ctypes.c_int),
     "j3d_autotune_single": ([_I32, _I32, _I32, _I32, _P(Tune), _V], ctypes.c_int),
     "j3d_tune_set_single": ([_I32, _I32, _I32, _I32, _P(Tune)], ctypes.c_int),
     "j3d_tune_query_single": ([_I32, _I32, _I32, _I32, _P(Tune)], ctypes.c_int),
@@ -531,6 +532,14 @@ def j3d_autotune(grids, stream=None):
     t = Tune()
     _check(_lib.j3d_autotune(len(grids), arr, ctypes.byref(t), _stream_handle(stream)), "j3d_autotune")
     return t.as_tuple()
+
+
+def j3d_batch_last_plan():
+    """(sweeps per pass, tile shape) of this thread's most recent jacobi3d_sweep_batch call."""
+    k = ctypes.c_int32()
+    t = Tune()
+    _check(_lib.j3d_batch_last_plan(ctypes.byref(k), ctypes.byref(t)), "j3d_batch_last_plan")
+    return k.value, t.as_tuple()
 
 
 def j3d_autotune_single(dtype, nx, ny, nz, stream=None):

@@ -56,6 +56,7 @@ INTENT = {
     "j3d_autotune_single": {"best": "out"},
     "j3d_tune_set_single": {"t": "in"},
     "j3d_tune_query_single": {"out": "out"},
+    "j3d_batch_last_plan": {"sweeps_per_pass": "out", "shape": "out"},
     "poisson_serve_create": {"opts": "in", "out": "out"},
     "poisson_serve_submit": {"req": "in", "ticket": "out"},
     "poisson_serve_poll": {"out": "out", "n": "out"},
@@ -313,6 +314,16 @@ def test_tune_query_default_set_and_bad_kind():
     assert ei.value.code == j3d.EDTYPE
     with pytest.raises(j3d.J3DError):
         j3d.j3d_tune_query_single(j3d.F64, 0, 5, 3)
+
+
+def test_batch_last_plan_before_any_batch_call():
+    """Host-only query: no batch call on this thread yet -> ESTATE; null pointers -> EINVAL."""
+    with pytest.raises(j3d.J3DError) as ei:
+        j3d.j3d_batch_last_plan()
+    assert ei.value.code == j3d.ESTATE
+    k = ctypes.c_int32()
+    assert j3d._lib.j3d_batch_last_plan(None, ctypes.byref(j3d.Tune())) == j3d.EINVAL
+    assert j3d._lib.j3d_batch_last_plan(ctypes.byref(k), None) == j3d.EINVAL
 
 
 def test_jacobi2d_validation_before_device_work():

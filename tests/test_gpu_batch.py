@@ -62,6 +62,8 @@ def test_batch_three_sweep_slot_order_matches_oracle(monkeypatch, tile3, nsweeps
     monkeypatch.setenv("J3D_BATCH_TRIPLES", "1")
     monkeypatch.setenv("J3D_BATCH_TILE3", tile3)
     check_batch_against_oracle(None, nsweeps, every)
+    rows, planes, var, order = (int(x) for x in tile3.split(","))
+    assert j3d.j3d_batch_last_plan() == (3, (rows, planes, var, 0, order, 1))
 
 
 @pytest.mark.parametrize("shape", ["16,24,6", "8,16,20"])
