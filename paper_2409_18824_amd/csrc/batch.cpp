@@ -678,7 +678,7 @@ std::vector<TileCfg> sweep3_candidates(int dtype) {
   std::vector<TileCfg> v;
   for (int rows : {2, 4, 8, 16})
     for (int var : {6, 20})
-      for (int planes : {16, 24, 32, 48, 64, 96})
+      for (int planes : {16, 24, 32, 48, 64, 96, 128, 144, 192})
         for (int order : {0, 1, 2}) {
           TileCfg c{rows, planes, var, 0, order, 1};
           if (tile3_cfg_supported(dtype, c)) v.push_back(c);

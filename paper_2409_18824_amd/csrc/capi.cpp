@@ -63,25 +63,34 @@ TileCfg default_cfg3(int dtype, int nx, int ny, int nz) {
   // wavefronts of 4 rows per thread, per-slab XCD chunks; beyond, 8
   // wavefronts of 2 rows per thread (about 95 registers per thread against
   // 160 with 4 rows, so twice the wavefronts per CU), 32 planes in
-  // per-slab XCD chunks, and above 400^3 96 planes in launch order (512^3:
-  // 722 us per FP64 pass against 776 with 4 x 4 rows and 48 planes).  FP32
-  // above 400^3: 4 wavefronts of 4 rows per thread, 24 planes, per-slab XCD
-  // chunks (442 us per pass at 512^3 against 450 with the FP64 shape).
+  // per-slab XCD chunks.  Above 400^3 (measured at 512^3): FP64 16
+  // wavefronts of 2 rows (32-row blocks, one workgroup per CU) and 144
+  // planes in launch order, 712 us per pass against 731 with 8 wavefronts
+  // and 96 planes (the block's waste on ragged y edges is small since
+  // wavefronts wholly past the grid skip their work; 144 planes make four
+  // z-slabs, the last one short); FP32 8 wavefronts of 2 rows, 48 planes,
+  // per-slab XCD chunks, 419 us against 439 with 4 wavefronts of 4 rows and
+  // 24 planes.  Other sizes above 400^3 are best tuned (j3d_autotune_single).
   const long long pts = (long long)nx * ny * nz;
   const bool small = pts <= 200LL * 200 * 200;
   const bool large = pts > 300LL * 300 * 300;
   const bool huge = pts > 400LL * 400 * 400;
   c.rows = large ? 8 : 4;
-  c.planes = huge ? 96 : large ? 32 : 16;
+  c.planes = large ? 32 : 16;
   c.variant = (small || large) ? 6 : 20;
   c.persistent = 0;
-  c.order = small ? 0 : huge ? 1 : 2;
+  c.order = small ? 0 : 2;
   c.cols = 1;
-  if (dtype == J3D_F32 && huge) {
-    c.rows = 4;
-    c.planes = 24;
-    c.variant = 20;
-    c.order = 2;
+  if (huge) {
+    if (dtype == J3D_F32) {
+      c.rows = 8;
+      c.planes = 48;
+      c.order = 2;
+    } else {
+      c.rows = 16;
+      c.planes = 144;
+      c.order = 1;
+    }
   }
   return c;
 }

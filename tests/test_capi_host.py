@@ -421,8 +421,8 @@ def test_three_sweep_kind_defaults_and_validation():
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 97, 5, 3) == (4, 16, 6, 0, 0, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 256, 256, 256) == (4, 16, 20, 0, 2, 1)
     assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 384, 384, 384) == (8, 32, 6, 0, 2, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (8, 96, 6, 0, 1, 1)
-    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (4, 24, 20, 0, 2, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F64X3, 512, 512, 512) == (16, 144, 6, 0, 1, 1)
+    assert j3d.j3d_tune_query_single(j3d.KIND_F32X3, 512, 512, 512) == (8, 48, 6, 0, 2, 1)
     for bad in [(1, 16, 20, 0, 1, 1), (4, 16, 16, 0, 1, 1), (4, 16, 20, 1, 1, 1), (4, 16, 20, 0, 1, 2),
                 (16, 16, 20, 0, 1, 1), (3, 16, 20, 0, 1, 1), (5, 16, 20, 0, 1, 1), (6, 8, 6, 0, 1, 1),
                 (7, 16, 20, 0, 1, 1), (4, 16, 6, 0, 3, 1)]:
