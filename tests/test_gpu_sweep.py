@@ -101,7 +101,8 @@ def test_sweep2_equals_two_sweeps(shape, tune):
 
 
 TUNES3 = [(4, 32, 20, 0, 1, 1), (2, 16, 20, 0, 0, 1), (8, 8, 6, 0, 2, 1), (4, 7, 6, 0, 1, 1), (8, 64, 20, 0, 0, 1),
-          (2, 3, 20, 0, 2, 1), (4, 48, 20, 0, 1, 1), (4, 24, 20, 0, 2, 1), (16, 24, 6, 0, 1, 1)]
+          (2, 3, 20, 0, 2, 1), (4, 48, 20, 0, 1, 1), (4, 24, 20, 0, 2, 1), (16, 24, 6, 0, 1, 1),
+          (16, 144, 6, 0, 1, 1), (16, 5, 6, 0, 2, 1)]
 SHAPES3 = [(1, 1, 1), (3, 4, 5), (58, 6, 9), (59, 12, 10), (57, 13, 8), (117, 30, 17), (17, 45, 64), (200, 28, 3)]
 
 
@@ -154,7 +155,8 @@ def test_sweep3_residual_of_intermediate_iterates(shape, tune, after):
 
 
 @pytest.mark.parametrize("shape", [(70, 13, 21), (1, 1, 1), (130, 40, 9), (58, 14, 33)])
-@pytest.mark.parametrize("tune", [(8, 32, 20, 0, 1, 1), (4, 16, 6, 0, 0, 1), (2, 8, 20, 0, 2, 1)])
+@pytest.mark.parametrize("tune", [(8, 32, 20, 0, 1, 1), (4, 16, 6, 0, 0, 1), (2, 8, 20, 0, 2, 1), (8, 48, 6, 0, 2, 1),
+                                  (16, 7, 6, 0, 1, 1)])
 def test_sweep3_fp32_equals_three_fp32_sweeps(shape, tune):
     nx, ny, nz = shape
     say("sweep3 fp32", shape, tune)
