@@ -66,6 +66,31 @@ def test_batch_three_sweep_slot_order_matches_oracle(monkeypatch, tile3, nsweeps
     assert j3d.j3d_batch_last_plan() == (3, (rows, planes, var, 0, order, 1))
 
 
+@pytest.mark.parametrize("shapes,tile3", [([(70, 70, 70)], "16,24,6,3"), ([(1, 1, 1)], "2,8,20,3"),
+                                          ([(3, 300, 2), (120, 1, 9)], "16,5,6,3")])
+def test_batch_slot_order_few_tiles(monkeypatch, shapes, tile3):
+    """Slot lists with fewer tiles than XCDs, or one grid only: runs left
+    empty hold no tile, every tile still runs once."""
+    monkeypatch.setenv("J3D_BATCH_TRIPLES", "1")
+    monkeypatch.setenv("J3D_BATCH_TILE3", tile3)
+    say("batch slots few", shapes, tile3)
+    grids, host = make_batch(shapes)
+    out = torch.zeros((len(grids), 4), dtype=torch.float64, device="cuda")
+    j3d.jacobi3d_sweep_batch(grids, 9, 3, out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    for g, ((ua, ub, _, _), (u0, f, h)) in enumerate(zip(grids, host)):
+        u = u0.copy()
+        want = []
+        for s in range(10):
+            if s % 3 == 0:
+                want.append(oracle.residual_l2(u, f, h))
+            if s < 9:
+                u = oracle.sweep(u, f, h)
+        assert np.array_equal(ub.to_numpy(), u), "grid %d" % g  # 9 sweeps: odd, result in u_b
+        assert all(rel(a, b) <= RESID_RTOL for a, b in zip(res[g], want)), (g, res[g], want)
+
+
 @pytest.mark.parametrize("shape", ["16,24,6", "8,16,20"])
 def test_batch_slot_order_equals_blocked_order_bitwise(monkeypatch, shape):
     """The slot order changes only which workgroup runs a tile: iterates and
